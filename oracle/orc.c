@@ -1,0 +1,513 @@
+/*
+ * CPU FP64 oracle of the plane-extraction path of arXiv 2411.01919.
+ *
+ * TEST INFRASTRUCTURE ONLY: the plain, slow reference that the GPU library is
+ * checked against.  Only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load it.  It shares no code with the GPU library.
+ *
+ * Written for reading against the paper, not for speed: every step is the
+ * plain definition, in float64, in the order the method states it.  OpenMP
+ * is used only across independent pixels or hypotheses; every reduction is
+ * either an integer count or done serially in a fixed order.
+ *
+ * Readings of the paper taken here (the paper is silent or garbled on them):
+ *  - holes: depth 0 is "no measurement"; they get no flux and stay 0;
+ *  - diffusion: the per-edge flux form of Eq. 1 on the 4-neighbourhood (the
+ *    classical explicit Perona-Malik scheme), gradient along an edge taken as
+ *    the neighbour difference, zero flux across the border and into holes,
+ *    Jacobi update (every pixel reads the previous iterate);
+ *  - normals: Eq. 2 taken as the geometric normal of the back-projected
+ *    surface: Sobel sums of the point image, n = -(Gx x Gy)/|Gx x Gy|, which
+ *    faces the camera;
+ *  - RANSAC: whole-frame sequential extraction; the hypothesis with the most
+ *    inliers wins (ties to the lowest index); one total-least-squares refit on
+ *    its inliers; the refit plane's inliers are removed and labelled if there
+ *    are at least min_inliers of them; strict "<" against the threshold;
+ *  - sampling: Philox4x64-10 keyed by (seed, frame) with counter
+ *    (hypothesis, round, block, 0); each 64-bit word w picks position
+ *    floor(w * M0 / 2^64) in the frame's fixed list of valid pixels and is
+ *    rejected if that pixel is already assigned or already chosen; 16 blocks
+ *    (64 words) at most, else the hypothesis is invalid; a triple whose
+ *    cross product is at most 1e-3 |e1| |e2| is degenerate (invalid).
+ */
+#include "orc.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon et al., SC'11): 10 rounds of the 4x64 S-box with the
+ * published multipliers and Weyl key increments.                           */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    const uint64_t MUL0 = 0xD2E7470EE14C6C93ULL, MUL1 = 0xCA5A826395121157ULL;
+    const uint64_t WEYL0 = 0x9E3779B97F4A7C15ULL, WEYL1 = 0xBB67AE8584CAA73BULL;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += WEYL0;
+            k1 += WEYL1;
+        }
+        unsigned __int128 p0 = (unsigned __int128)MUL0 * c0;
+        unsigned __int128 p1 = (unsigned __int128)MUL1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t n0 = hi1 ^ c1 ^ k0;
+        uint64_t n1 = lo1;
+        uint64_t n2 = hi0 ^ c3 ^ k1;
+        uint64_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eq. 1 / Alg. 1: explicit Perona-Malik diffusion.                          */
+/* I^{it+1}_p = I^it_p + lambda * sum_{q in N4(p), inside, valid} g(I_q - I_p) (I_q - I_p) */
+/* ------------------------------------------------------------------------ */
+static double edge_stop_g(double x, double kappa, int kind) {
+    double s = x / kappa;
+    if (kind == 1) return 1.0 / (1.0 + s * s);
+    return exp(-(s * s));
+}
+
+void orc_diffuse(const double* depth, int W, int H, int iters, double lambda, double kappa,
+                 int edge_stop, double* out) {
+    size_t n = (size_t)W * H;
+    double* cur = (double*)malloc(n * sizeof(double));
+    double* nxt = (double*)malloc(n * sizeof(double));
+    for (size_t p = 0; p < n; ++p) cur[p] = depth[p];
+    const int du[4] = {0, 0, -1, 1};
+    const int dv[4] = {-1, 1, 0, 0};
+    for (int it = 0; it < iters; ++it) {
+#pragma omp parallel for schedule(static)
+        for (int v = 0; v < H; ++v) {
+            for (int u = 0; u < W; ++u) {
+                size_t p = (size_t)v * W + u;
+                if (!(depth[p] > 0.0)) {
+                    nxt[p] = 0.0;
+                    continue;
+                }
+                double flux = 0.0;
+                for (int k = 0; k < 4; ++k) {
+                    int uq = u + du[k], vq = v + dv[k];
+                    if (uq < 0 || uq >= W || vq < 0 || vq >= H) continue; /* zero flux at the border */
+                    size_t q = (size_t)vq * W + uq;
+                    if (!(depth[q] > 0.0)) continue;                       /* zero flux into a hole */
+                    double delta = cur[q] - cur[p];
+                    flux += edge_stop_g(delta, kappa, edge_stop) * delta;
+                }
+                nxt[p] = cur[p] + lambda * flux;
+            }
+        }
+        double* t = cur; cur = nxt; nxt = t;
+    }
+    memcpy(out, cur, n * sizeof(double));
+    free(cur);
+    free(nxt);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Back-projection (Sec. III-D: polygons projected to 3-D with K; Alg. 2).    */
+/* ------------------------------------------------------------------------ */
+void orc_backproject(const double* depth_mm, int W, int H, double fx, double fy, double cx, double cy,
+                     double* P, uint8_t* valid) {
+    size_t n = (size_t)W * H;
+    for (int v = 0; v < H; ++v) {
+        for (int u = 0; u < W; ++u) {
+            size_t p = (size_t)v * W + u;
+            double z = depth_mm[p] / 1000.0;
+            int ok = depth_mm[p] > 0.0;
+            valid[p] = (uint8_t)ok;
+            P[p] = ok ? z * ((double)u - cx) / fx : 0.0;
+            P[n + p] = ok ? z * ((double)v - cy) / fy : 0.0;
+            P[2 * n + p] = ok ? z : 0.0;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eq. 2 / Alg. 1: Sobel gradients and the normal image.                      */
+/* ------------------------------------------------------------------------ */
+void orc_normals(const double* P, const uint8_t* valid, int W, int H, double* N, uint8_t* nvalid,
+                 double* gx_out, double* gy_out) {
+    const double SX[3][3] = {{-1, 0, 1}, {-2, 0, 2}, {-1, 0, 1}};
+    const double SY[3][3] = {{-1, -2, -1}, {0, 0, 0}, {1, 2, 1}};
+    size_t n = (size_t)W * H;
+#pragma omp parallel for schedule(static)
+    for (int v = 0; v < H; ++v) {
+        for (int u = 0; u < W; ++u) {
+            size_t p = (size_t)v * W + u;
+            int ok = (u >= 1 && u <= W - 2 && v >= 1 && v <= H - 2);
+            for (int j = 0; ok && j < 3; ++j)
+                for (int i = 0; ok && i < 3; ++i)
+                    if (!valid[(size_t)(v + j - 1) * W + (u + i - 1)]) ok = 0;
+            double gx[3] = {0, 0, 0}, gy[3] = {0, 0, 0};
+            if (ok) {
+                for (int j = 0; j < 3; ++j)
+                    for (int i = 0; i < 3; ++i) {
+                        size_t q = (size_t)(v + j - 1) * W + (u + i - 1);
+                        for (int c = 0; c < 3; ++c) {
+                            gx[c] += SX[j][i] * P[c * n + q];
+                            gy[c] += SY[j][i] * P[c * n + q];
+                        }
+                    }
+            }
+            double m[3] = {gx[1] * gy[2] - gx[2] * gy[1], gx[2] * gy[0] - gx[0] * gy[2],
+                           gx[0] * gy[1] - gx[1] * gy[0]};
+            double mn = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+            if (!(mn > 0.0)) ok = 0;
+            nvalid[p] = (uint8_t)ok;
+            for (int c = 0; c < 3; ++c) {
+                N[c * n + p] = ok ? -m[c] / mn : 0.0;
+                if (gx_out) gx_out[c * n + p] = gx[c];
+                if (gy_out) gy_out[c * n + p] = gy[c];
+            }
+        }
+    }
+}
+
+int orc_valid_list(const uint8_t* valid, int npx, int32_t* L) {
+    int m = 0;
+    for (int p = 0; p < npx; ++p)
+        if (valid[p]) L[m++] = p;
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 2: "select random subset of 3 points", "fit plane model".            */
+/* ------------------------------------------------------------------------ */
+static void point_at(const double* P, size_t n, int px, double out[3]) {
+    out[0] = P[px];
+    out[1] = P[n + px];
+    out[2] = P[2 * n + px];
+}
+
+void orc_hypotheses(const double* P, int W, int H, const int32_t* L, int M0, const uint8_t* assigned,
+                    const orc_ransac_params* prm, int r, int32_t* triples, double* planes, uint8_t* hvalid) {
+    size_t n = (size_t)W * H;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < prm->hyps; ++j) {
+        int slot[3] = {-1, -1, -1};
+        int got = 0;
+        for (int b = 0; b < 16 && got < 3; ++b) {
+            uint64_t ctr[4] = {(uint64_t)j, (uint64_t)r, (uint64_t)b, 0};
+            uint64_t key[2] = {prm->seed, prm->frame};
+            uint64_t w[4];
+            orc_philox4x64_10(ctr, key, w);
+            for (int q = 0; q < 4 && got < 3; ++q) {
+                int k = (int)(((unsigned __int128)w[q] * (uint64_t)M0) >> 64);
+                if (assigned[L[k]]) continue;
+                int dup = 0;
+                for (int s = 0; s < got; ++s)
+                    if (slot[s] == k) dup = 1;
+                if (dup) continue;
+                slot[got++] = k;
+            }
+        }
+        double* pl = planes + 4 * (size_t)j;
+        pl[0] = pl[1] = pl[2] = pl[3] = 0.0;
+        triples[3 * j + 0] = slot[0];
+        triples[3 * j + 1] = slot[1];
+        triples[3 * j + 2] = slot[2];
+        hvalid[j] = 0;
+        if (got < 3) continue;
+        double p0[3], p1[3], p2[3];
+        point_at(P, n, L[slot[0]], p0);
+        point_at(P, n, L[slot[1]], p1);
+        point_at(P, n, L[slot[2]], p2);
+        double e1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+        double e2[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+        double m[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                       e1[0] * e2[1] - e1[1] * e2[0]};
+        double mn = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+        double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+        double l2 = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+        if (!(mn > 1e-3 * l1 * l2)) continue; /* degenerate triple */
+        double nn[3] = {m[0] / mn, m[1] / mn, m[2] / mn};
+        double d = -(nn[0] * p0[0] + nn[1] * p0[1] + nn[2] * p0[2]);
+        if (d < 0) {
+            nn[0] = -nn[0]; nn[1] = -nn[1]; nn[2] = -nn[2];
+            d = -d;
+        }
+        pl[0] = nn[0]; pl[1] = nn[1]; pl[2] = nn[2]; pl[3] = d;
+        hvalid[j] = 1;
+    }
+}
+
+/* Gather the unassigned valid points (positions of L in order). */
+static int gather_remaining(const double* P, int W, int H, const int32_t* L, int M0, const uint8_t* assigned,
+                            double* xyz, int32_t* pix) {
+    size_t n = (size_t)W * H;
+    int m = 0;
+    for (int k = 0; k < M0; ++k) {
+        int px = L[k];
+        if (assigned[px]) continue;
+        xyz[3 * (size_t)m + 0] = P[px];
+        xyz[3 * (size_t)m + 1] = P[n + px];
+        xyz[3 * (size_t)m + 2] = P[2 * n + px];
+        pix[m] = px;
+        ++m;
+    }
+    return m;
+}
+
+/* Alg. 2 inner loop: for every point, distance to the plane (Eq. 3), inlier iff below t. */
+static void score_points(const double* xyz, int m, const double* planes, const uint8_t* hvalid, int nh,
+                         double thresh, const double* eps, int32_t* counts, int32_t* counts_lo,
+                         int32_t* counts_hi) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int j = 0; j < nh; ++j) {
+        int32_t c = 0, clo = 0, chi = 0;
+        if (hvalid[j]) {
+            const double* pl = planes + 4 * (size_t)j;
+            double tlo = eps ? thresh - eps[j] : thresh;
+            double thi = eps ? thresh + eps[j] : thresh;
+            for (int i = 0; i < m; ++i) {
+                const double* p = xyz + 3 * (size_t)i;
+                double dist = fabs(pl[0] * p[0] + pl[1] * p[1] + pl[2] * p[2] + pl[3]);
+                c += dist < thresh;
+                clo += dist < tlo;
+                chi += dist < thi;
+            }
+        }
+        counts[j] = c;
+        if (counts_lo) counts_lo[j] = clo;
+        if (counts_hi) counts_hi[j] = chi;
+    }
+}
+
+void orc_score(const double* P, int W, int H, const int32_t* L, int M0, const uint8_t* assigned,
+               const double* planes, const uint8_t* hvalid, int nh, double thresh, const double* eps,
+               int32_t* counts, int32_t* counts_lo, int32_t* counts_hi, double* pmax) {
+    double* xyz = (double*)malloc(3 * (size_t)(M0 > 0 ? M0 : 1) * sizeof(double));
+    int32_t* pix = (int32_t*)malloc((size_t)(M0 > 0 ? M0 : 1) * sizeof(int32_t));
+    int m = gather_remaining(P, W, H, L, M0, assigned, xyz, pix);
+    if (pmax) {
+        double best = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double* p = xyz + 3 * (size_t)i;
+            double r = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+            if (r > best) best = r;
+        }
+        *pmax = best;
+    }
+    score_points(xyz, m, planes, hvalid, nh, thresh, eps, counts, counts_lo, counts_hi);
+    free(xyz);
+    free(pix);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Symmetric 3x3 eigen-decomposition, cyclic Jacobi (Golub & Van Loan 8.5).  */
+/* ------------------------------------------------------------------------ */
+void orc_eig3(const double A_in[9], double w[3], double V[9]) {
+    double A[3][3], Q[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            A[i][j] = A_in[3 * i + j];
+            Q[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        double dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+        if (off == 0.0 || off <= 1e-40 * dia) break;
+        for (int p = 0; p < 2; ++p) {
+            for (int q = p + 1; q < 3; ++q) {
+                if (A[p][q] == 0.0) continue;
+                /* rotation that zeroes A[p][q]: tan of the angle is the smaller root */
+                double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0);
+                double s = t * c;
+                /* A <- J^T A J with J the (p,q) rotation [c s; -s c] */
+                for (int k = 0; k < 3; ++k) {
+                    double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    double qkp = Q[k][p], qkq = Q[k][q];
+                    Q[k][p] = c * qkp - s * qkq;
+                    Q[k][q] = s * qkp + c * qkq;
+                }
+            }
+        }
+    }
+    /* sort ascending */
+    int idx[3] = {0, 1, 2};
+    double ev[3] = {A[0][0], A[1][1], A[2][2]};
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b)
+            if (ev[idx[b]] < ev[idx[a]]) {
+                int t = idx[a]; idx[a] = idx[b]; idx[b] = t;
+            }
+    for (int c = 0; c < 3; ++c) {
+        w[c] = ev[idx[c]];
+        for (int k = 0; k < 3; ++k) V[3 * k + c] = Q[k][idx[c]];
+    }
+}
+
+/* Least-squares refit: the plane through the centroid whose normal is the
+ * direction of least scatter minimises the sum of squared distances (the
+ * "optimal plane model" of Sec. III-A, Eq. 3 with a squared distance). */
+int orc_refit(const double* P, int W, int H, const int32_t* idx, int cnt, double plane[4], double centroid[3]) {
+    size_t n = (size_t)W * H;
+    plane[0] = plane[1] = plane[2] = plane[3] = 0.0;
+    centroid[0] = centroid[1] = centroid[2] = 0.0;
+    if (cnt < 3) return -1;
+    double c[3] = {0, 0, 0};
+    for (int i = 0; i < cnt; ++i)
+        for (int k = 0; k < 3; ++k) c[k] += P[k * n + idx[i]];
+    for (int k = 0; k < 3; ++k) c[k] /= cnt;
+    double C[9] = {0};
+    for (int i = 0; i < cnt; ++i) {
+        double q[3];
+        for (int k = 0; k < 3; ++k) q[k] = P[k * n + idx[i]] - c[k];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) C[3 * a + b] += q[a] * q[b];
+    }
+    double w[3], V[9];
+    orc_eig3(C, w, V);
+    double nn[3] = {V[0], V[3], V[6]}; /* column 0: smallest eigenvalue */
+    double nrm = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    for (int k = 0; k < 3; ++k) nn[k] /= nrm;
+    double d = -(nn[0] * c[0] + nn[1] * c[1] + nn[2] * c[2]);
+    if (d < 0) {
+        for (int k = 0; k < 3; ++k) nn[k] = -nn[k];
+        d = -d;
+    }
+    plane[0] = nn[0]; plane[1] = nn[1]; plane[2] = nn[2]; plane[3] = d;
+    centroid[0] = c[0]; centroid[1] = c[1]; centroid[2] = c[2];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One round of sequential RANSAC (follow mode).                              */
+/* ------------------------------------------------------------------------ */
+void orc_ransac_round(const double* P, int W, int H, const int32_t* L, int M0, const uint8_t* assigned,
+                      const orc_ransac_params* prm, int r, const double* eps,
+                      int32_t* triples, double* planes, uint8_t* hvalid,
+                      int32_t* counts, int32_t* counts_lo, int32_t* counts_hi,
+                      uint8_t* smask, uint8_t* fmask, orc_round_result* res) {
+    size_t n = (size_t)W * H;
+    int nh = prm->hyps;
+    memset(res, 0, sizeof(*res));
+    res->jstar = -1;
+    if (smask) memset(smask, 0, n);
+    if (fmask) memset(fmask, 0, n);
+
+    double* xyz = (double*)malloc(3 * (size_t)(M0 > 0 ? M0 : 1) * sizeof(double));
+    int32_t* pix = (int32_t*)malloc((size_t)(M0 > 0 ? M0 : 1) * sizeof(int32_t));
+    int m = gather_remaining(P, W, H, L, M0, assigned, xyz, pix);
+    res->n_remaining = m;
+    if (m < 3) {
+        res->status = 3;
+        free(xyz); free(pix);
+        return;
+    }
+
+    int32_t* tr = triples ? triples : (int32_t*)malloc(3 * (size_t)nh * sizeof(int32_t));
+    double* pl = planes ? planes : (double*)malloc(4 * (size_t)nh * sizeof(double));
+    uint8_t* hv = hvalid ? hvalid : (uint8_t*)malloc((size_t)nh);
+    int32_t* ct = counts ? counts : (int32_t*)malloc((size_t)nh * sizeof(int32_t));
+
+    orc_hypotheses(P, W, H, L, M0, assigned, prm, r, tr, pl, hv);
+    score_points(xyz, m, pl, hv, nh, prm->thresh, eps, ct, counts_lo, counts_hi);
+
+    /* select: most inliers, ties to the lowest index, invalid never chosen */
+    int js = -1;
+    for (int j = 0; j < nh; ++j)
+        if (hv[j] && (js < 0 || ct[j] > ct[js])) js = j;
+    res->jstar = js;
+    if (js < 0) {
+        res->status = 1;
+    } else {
+        const double* h = pl + 4 * (size_t)js;
+        memcpy(res->hyp_plane, h, 4 * sizeof(double));
+        int32_t* S = (int32_t*)malloc((size_t)m * sizeof(int32_t));
+        int ns = 0;
+        for (int i = 0; i < m; ++i) {
+            const double* p = xyz + 3 * (size_t)i;
+            if (fabs(h[0] * p[0] + h[1] * p[1] + h[2] * p[2] + h[3]) < prm->thresh) {
+                S[ns++] = pix[i];
+                if (smask) smask[pix[i]] = 1;
+            }
+        }
+        res->s_count = ns;
+        orc_refit(P, W, H, S, ns, res->plane, res->centroid);
+        const double* q = res->plane;
+        int nf = 0;
+        for (int i = 0; i < m; ++i) {
+            const double* p = xyz + 3 * (size_t)i;
+            if (fabs(q[0] * p[0] + q[1] * p[1] + q[2] * p[2] + q[3]) < prm->thresh) {
+                ++nf;
+                if (fmask) fmask[pix[i]] = 1;
+            }
+        }
+        res->f_count = nf;
+        res->status = (nf >= prm->min_inliers) ? 0 : 2;
+        free(S);
+    }
+    if (!triples) free(tr);
+    if (!planes) free(pl);
+    if (!hvalid) free(hv);
+    if (!counts) free(ct);
+    free(xyz);
+    free(pix);
+}
+
+int orc_ransac(const double* P, const uint8_t* valid, int W, int H, const orc_ransac_params* prm,
+               int8_t* labels, double* planes_out, double* centroids_out, int32_t* inliers_out,
+               int32_t* jstar_out, double* residuals) {
+    size_t n = (size_t)W * H;
+    int32_t* L = (int32_t*)malloc(n * sizeof(int32_t));
+    int M0 = orc_valid_list(valid, (int)n, L);
+    uint8_t* assigned = (uint8_t*)calloc(n, 1);
+    uint8_t* fmask = (uint8_t*)malloc(n);
+    for (size_t p = 0; p < n; ++p) labels[p] = -1;
+    double res_count = 0.0;
+    int np = 0;
+    for (int r = 0; r < prm->max_planes; ++r) {
+        orc_round_result rr;
+        orc_ransac_round(P, W, H, L, M0, assigned, prm, r, NULL, NULL, NULL, NULL, NULL, NULL, NULL,
+                         NULL, fmask, &rr);
+        if (rr.status == 3) break;
+        if (rr.status == 1) break;
+        res_count += (double)rr.n_remaining * prm->hyps;
+        if (rr.status != 0) break;
+        for (size_t p = 0; p < n; ++p)
+            if (fmask[p]) {
+                labels[p] = (int8_t)np;
+                assigned[p] = 1;
+            }
+        if (planes_out) memcpy(planes_out + 4 * (size_t)np, rr.plane, 4 * sizeof(double));
+        if (centroids_out) memcpy(centroids_out + 3 * (size_t)np, rr.centroid, 3 * sizeof(double));
+        if (inliers_out) inliers_out[np] = rr.f_count;
+        if (jstar_out) jstar_out[np] = rr.jstar;
+        ++np;
+        if (rr.n_remaining - rr.f_count < 3) break;
+    }
+    if (residuals) *residuals = res_count;
+    free(L);
+    free(assigned);
+    free(fmask);
+    return np;
+}
