@@ -1,0 +1,234 @@
+/*
+ * pp.h -- C ABI of the MI355X (gfx950) plane-extraction library libpp.so.
+ *
+ * The library computes the per-frame plane-extraction path of "Real-Time
+ * Polygonal Semantic Mapping for Humanoid Robot Stair Climbing"
+ * (arXiv 2411.01919):
+ *   1. Perona-Malik anisotropic diffusion of a depth image (Sec. III-C, Eq. 1,
+ *      Alg. 1),
+ *   2. back-projection of the depth image to a point image with the camera
+ *      intrinsics (Sec. III-D, Alg. 2),
+ *   3. the normal image from Sobel gradients (Sec. III-C, Eq. 2, Alg. 1),
+ *   4. RANSAC plane extraction: random 3-point hypotheses, inlier scoring with
+ *      the point-to-plane distance (Eq. 3, Alg. 2), selection, a
+ *      least-squares refit of the winning plane ("optimal plane model",
+ *      Sec. III-A) and removal of its inliers, repeated for up to
+ *      max_planes planes per frame.
+ * Every stage runs as hand-written HIP kernels on the GPU.
+ *
+ * Conventions (all calls):
+ *  - Plain C types only.  Every pointer named *_dev is a device pointer the
+ *    caller allocated and owns; the library never frees caller memory.
+ *  - Images are row-major with a row pitch in pixels (pitch_px >= width);
+ *    3-vector images are three planes [3][height][pitch_px].
+ *  - Depth is uint16 millimetres with 0 = hole; diffused depth is float mm;
+ *    points, planes and thresholds are in metres; camera frame x right,
+ *    y down, z forward; pixel (u, v) = (column, row) looks along
+ *    ((u - cx)/fx, (v - cy)/fy, 1).
+ *  - hip_stream is a hipStream_t (NULL = the null stream).  Calls enqueue
+ *    their kernels asynchronously and return; outputs are valid once the
+ *    stream has reached that point.  Counts the host needs (number of
+ *    planes) are written to device memory, so no call synchronises.
+ *  - Arguments are checked before any HIP call; a bad argument returns
+ *    PP_E_INVAL and enqueues nothing.  A failing HIP call returns PP_E_HIP and
+ *    poisons the context: every later call on it returns PP_E_HIP until it is
+ *    destroyed.  pp_last_error() describes the last failure.
+ *  - A pp_ctx is not thread-safe; use one per thread (or serialise).  It owns
+ *    scratch memory that grows to the largest shape seen and is reused.
+ */
+#ifndef PP_H
+#define PP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pp_status;
+enum {
+    PP_OK = 0,
+    PP_PENDING = 1,         /* pp_poll: result not ready yet */
+    PP_E_INVAL = -1,        /* bad argument (nothing was enqueued) */
+    PP_E_NOMEM = -2,        /* device allocation failed */
+    PP_E_BUDGET = -3,       /* a frame can never fit the server's HBM budget */
+    PP_E_HIP = -4,          /* a HIP runtime call failed; the object is poisoned */
+    PP_E_NODEVICE = -5,     /* no usable GPU */
+    PP_E_CLOSED = -6,       /* server/stream closed or destroyed */
+    PP_E_UNSUPPORTED = -7,  /* valid request outside what this build implements */
+    PP_E_TIMEOUT = -8       /* pp_poll waited timeout_us without a result */
+};
+
+typedef struct pp_ctx pp_ctx;
+
+typedef struct { float fx, fy, cx, cy; } pp_intrinsics;              /* pixels */
+typedef struct { int32_t width, height, pitch_px; } pp_frame_desc;   /* 3 <= w,h <= 16384; w*h <= 2^27 */
+
+enum { PP_EDGE_EXP = 0, PP_EDGE_RATIONAL = 1 };
+/* Alg. 1 parameters: iterations N, step gamma (lambda), edge scale k (kappa, mm).
+ * edge_stop PP_EDGE_EXP: g(x) = exp(-(x/kappa)^2) as Alg. 1 prints it;
+ * PP_EDGE_RATIONAL: g(x) = 1/(1 + (x/kappa)^2).  0 < lambda <= 0.25, kappa > 0. */
+typedef struct { int32_t iters; float lambda; float kappa_mm; int32_t edge_stop; } pp_diffuse_params;
+
+/* Inlier scoring arithmetic.  Every form decides |n.p + d| < t exactly as the
+ * canonical FP32 residual fmaf(nx,x, fmaf(ny,y, fmaf(nz,z,d))) does: the fast
+ * forms recheck residuals within recheck_band_m of t with that formula. */
+enum { PP_SCORE_FP32 = 0, PP_SCORE_MFMA_F32 = 1, PP_SCORE_BF16 = 2, PP_SCORE_FP16 = 3 };
+
+/* Alg. 2 "RANSAC parameters".  Hypotheses draw from Philox4x64-10 keyed by
+ * (seed, frame_id) with counter (hypothesis, round, block, 0).
+ * 1 <= max_planes <= 127; 1 <= hyps_per_plane <= 8192; thresh_m > 0;
+ * min_inliers >= 1; recheck_band_m >= 0 (used by the MFMA forms). */
+typedef struct {
+    int32_t max_planes;
+    int32_t hyps_per_plane;
+    int32_t min_inliers;
+    float thresh_m;
+    uint64_t seed;
+    uint64_t frame_id;
+    int32_t precision;      /* PP_SCORE_* */
+    float recheck_band_m;
+} pp_ransac_params;
+
+/* One extracted plane: n.p + d = 0 with |n| = 1 and d >= 0 (faces the camera). */
+typedef struct {
+    double n[3];
+    double d;
+    double centroid[3];
+    int32_t inliers;        /* |F|: points labelled with this plane */
+    int32_t hyp_index;      /* winning hypothesis j* of the round */
+} pp_plane;
+
+/* Optional introspection of pp_ransac_planes (any pointer may be NULL).
+ * Device buffers, caller-owned; masks must be zeroed by the caller.
+ * counts [max_planes][hyps], hyps [max_planes][hyps][4] (n, d; d = NaN when
+ * invalid), triples [max_planes][hyps][3] (positions in the valid list, -1
+ * when sampling gave up), round_info [max_planes][4] = (j*, |S|, |F|, status:
+ * 0 plane emitted, 1 no valid hypothesis, 2 |F| < min_inliers, -1 not run),
+ * masks [max_planes][height*width] (bit0: inlier of j*, bit1: in F),
+ * valid_list [height*width] (pixel offsets y*pitch+x) and n_valid [1]. */
+typedef struct {
+    int32_t* counts;
+    float* hyps;
+    int32_t* triples;
+    int32_t* round_info;
+    uint8_t* masks;
+    int32_t* valid_list;
+    int32_t* n_valid;
+} pp_ransac_debug;
+
+/* ---------------------------------------------------------------- context */
+/* Create a context on HIP device `device`.  PP_E_NODEVICE without a GPU. */
+pp_status pp_ctx_create(int32_t device, pp_ctx** out);
+/* Wait for the context's outstanding work, free its scratch, destroy it. */
+pp_status pp_ctx_destroy(pp_ctx* ctx);
+const char* pp_status_string(pp_status s);
+/* Text of the last failure on ctx (or of the last failing create when ctx is NULL). */
+const char* pp_last_error(const pp_ctx* ctx);
+
+/* ---------------------------------------------------------------- stages */
+/* Step 1 (Eq. 1, Alg. 1): N explicit Perona-Malik iterations on the uint16
+ * depth image depth_dev [height][pitch]; out_mm_dev [height][pitch] float mm.
+ * Per-edge flux lambda * g(I_q - I_p) (I_q - I_p) over the 4 neighbours,
+ * zero flux across the border and into holes; holes stay 0. */
+pp_status pp_diffuse(pp_ctx* ctx, const uint16_t* depth_dev, float* out_mm_dev, pp_frame_desc desc,
+                     const pp_diffuse_params* params, void* hip_stream);
+
+/* Steps 2-3 (Alg. 2 back-projection; Eq. 2, Alg. 1 normals): from float depth
+ * in mm, points_dev [3][h][pitch] = z((u-cx)/fx, (v-cy)/fy, 1) metres (0 at
+ * holes), normals_dev [3][h][pitch] = -(Sx P x Sy P)/|.| with 3x3 Sobel sums
+ * of the point image, valid_dev [h][pitch]: bit0 depth > 0, bit1 normal
+ * valid (all 9 neighbours inside and valid, non-zero cross product). */
+pp_status pp_normals(pp_ctx* ctx, const float* depth_mm_dev, pp_frame_desc desc, pp_intrinsics K,
+                     float* points_dev, float* normals_dev, uint8_t* valid_dev, void* hip_stream);
+
+/* Step 4 (Alg. 2, Eq. 3): sequential whole-frame RANSAC over the depth-valid
+ * points (valid bit0).  Round r: hypotheses, inlier counts, j* = most
+ * inliers (ties: lowest index), least-squares refit on j*'s inliers (FP64
+ * moments + 3x3 eigen-solve), F = refit plane's inliers; if |F| >=
+ * min_inliers, planes_dev[r] is written and labels_dev[F] = r, else the
+ * frame stops.  Also stops with no valid hypothesis, after max_planes, or
+ * with fewer than 3 points left.  labels_dev [h][pitch] int8 (-1 none);
+ * n_planes_dev [1].  region_dev_or_null must be NULL (per-region mode is
+ * not built: PP_E_UNSUPPORTED). */
+pp_status pp_ransac_planes(pp_ctx* ctx, const float* points_dev, const uint8_t* valid_dev,
+                           const int16_t* region_dev_or_null, pp_frame_desc desc, const pp_ransac_params* params,
+                           pp_plane* planes_dev, int32_t* n_planes_dev, int8_t* labels_dev, void* hip_stream);
+
+/* pp_ransac_planes that also fills the introspection buffers of *dbg. */
+pp_status pp_ransac_planes_dbg(pp_ctx* ctx, const float* points_dev, const uint8_t* valid_dev,
+                               pp_frame_desc desc, const pp_ransac_params* params, pp_plane* planes_dev,
+                               int32_t* n_planes_dev, int8_t* labels_dev, const pp_ransac_debug* dbg,
+                               void* hip_stream);
+
+/* Score caller-given triples of pixel offsets (y*pitch+x) against every
+ * depth-valid point: planes_dev [n][4] receives each triple's FP32 plane
+ * (d = NaN if degenerate), counts_dev [n] its inlier count (Eq. 3, strict <). */
+pp_status pp_debug_score_triples(pp_ctx* ctx, const float* points_dev, const uint8_t* valid_dev,
+                                 pp_frame_desc desc, const int32_t* triples_dev, int32_t n, float thresh_m,
+                                 int32_t precision, float recheck_band_m, float* planes_dev,
+                                 int32_t* counts_dev, void* hip_stream);
+
+/* ---------------------------------------------------------------- whole frames */
+/* One frame through all four steps.  All pointers are caller device buffers:
+ * depth [h][pitch] uint16 in; depth_mm, points, normals, valid, labels,
+ * planes [max_planes], n_planes [1] out. */
+typedef struct {
+    const uint16_t* depth;
+    pp_frame_desc desc;
+    pp_intrinsics K;
+    pp_diffuse_params diffuse;
+    pp_ransac_params ransac;
+    float* depth_mm;
+    float* points;
+    float* normals;
+    uint8_t* valid;
+    pp_plane* planes;
+    int32_t* n_planes;
+    int8_t* labels;
+} pp_frame_job;
+
+/* Host-only check of a job's descriptor, parameters and pointers (non-NULL);
+ * makes no HIP call.  PP_OK or PP_E_INVAL. */
+pp_status pp_validate_job(const pp_frame_job* job);
+
+/* A ragged batch of frames (any mix of sizes and parameters) run together:
+ * each stage is one launch over all frames, and the whole sequence is
+ * captured once per batch layout into a HIP graph and replayed.  Results are
+ * bitwise identical to running each frame alone.  jobs is a host array. */
+pp_status pp_batch_run(pp_ctx* ctx, int32_t n_frames, const pp_frame_job* jobs, void* hip_stream);
+
+/* Same, without graph capture (plain stream launches). */
+pp_status pp_batch_run_eager(pp_ctx* ctx, int32_t n_frames, const pp_frame_job* jobs, void* hip_stream);
+
+/* ---------------------------------------------------------------- tuning */
+/* Launch-shape knobs the autotuner searches (0 = library default).
+ * diffuse_tile: index of the diffusion tile shape, diffuse_t: iterations
+ * fused per pass (temporal blocking depth), score_hb: hypotheses per
+ * scoring block, score_chunk: points per scoring work item. */
+typedef struct {
+    int32_t diffuse_tile;
+    int32_t diffuse_t;
+    int32_t score_hb;
+    int32_t score_chunk;
+} pp_tuning;
+/* Set (or, with NULL, reset) the context's tuning; invalid knobs: PP_E_INVAL. */
+pp_status pp_set_tuning(pp_ctx* ctx, const pp_tuning* tuning);
+pp_status pp_get_tuning(const pp_ctx* ctx, pp_tuning* out);
+/* Number of choices per knob (for the autotuner's search space). */
+pp_status pp_tuning_space(int32_t* n_tiles, int32_t* max_t, int32_t* n_hb, int32_t* n_chunk);
+
+/* ---------------------------------------------------------------- timing */
+/* Stage timing: while enabled, every launch of the inlier-scoring kernel
+ * (one per RANSAC round) is bracketed by HIP events recorded on the launching
+ * stream, also inside captured graphs.  pp_stage_time returns the summed
+ * elapsed ms of those launches in the most recent run on ctx and their number;
+ * the caller must have synchronised the stream first. */
+pp_status pp_set_stage_timing(pp_ctx* ctx, int32_t enable);
+pp_status pp_stage_time(pp_ctx* ctx, float* total_ms, int32_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PP_H */

@@ -1,0 +1,330 @@
+"""MI355X-native plane extraction from depth images (arXiv 2411.01919 hot path).
+
+Python binding of libpp.so: marshals torch tensors (device memory) and torch
+streams into the C ABI of include/pp.h.  Every step of the path runs in the
+library's HIP kernels; this module only checks shapes and passes pointers.
+
+    depth_mm = diffuse(depth_u16, iters=20)                     # Eq. 1 / Alg. 1
+    pts, nrm, valid = normals(depth_mm, K)                      # Alg. 2 / Eq. 2
+    planes, n, labels = ransac_planes(pts, valid, params)       # Alg. 2 / Eq. 3
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+from . import _native as N
+from ._native import (PP_EDGE_EXP, PP_EDGE_RATIONAL, PP_SCORE_BF16, PP_SCORE_FP16, PP_SCORE_FP32,  # noqa: F401
+                      PP_SCORE_MFMA_F32, LibraryMissing)
+
+__all__ = [
+    "PPError", "Context", "RansacConfig", "DiffuseConfig", "default_context", "diffuse", "normals",
+    "ransac_planes", "ransac_planes_debug", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
+    "planes_to_numpy", "PP_SCORE_FP32", "PP_SCORE_MFMA_F32", "PP_SCORE_BF16", "PP_SCORE_FP16",
+]
+
+
+class PPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{N.status_string(status)} ({status}): {msg}")
+        self.status = status
+
+
+@dataclass
+class DiffuseConfig:
+    iters: int = 20
+    lam: float = 0.2
+    kappa_mm: float = 30.0
+    edge_stop: int = PP_EDGE_EXP
+
+    def c(self) -> N.DiffuseParams:
+        return N.DiffuseParams(int(self.iters), float(self.lam), float(self.kappa_mm), int(self.edge_stop))
+
+
+@dataclass
+class RansacConfig:
+    max_planes: int = 12
+    hyps: int = 1024
+    min_inliers: int = 615
+    thresh_m: float = 0.01
+    seed: int = 0
+    frame_id: int = 0
+    precision: int = PP_SCORE_FP32
+    recheck_band_m: float = 0.0
+
+    def c(self) -> N.RansacParams:
+        return N.RansacParams(int(self.max_planes), int(self.hyps), int(self.min_inliers), float(self.thresh_m),
+                              int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.frame_id) & 0xFFFFFFFFFFFFFFFF,
+                              int(self.precision), float(self.recheck_band_m))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _check_dev(t, name: str, dtypes, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Context:
+    """A pp_ctx on one device (owns the library's scratch memory)."""
+
+    def __init__(self, device: int = 0):
+        L = N.lib()
+        h = N.c_vp()
+        s = L.pp_ctx_create(int(device), ctypes.byref(h))
+        if s != N.PP_OK:
+            raise PPError(s, L.pp_last_error(None).decode())
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            N.lib().pp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, s: int):
+        if s != N.PP_OK:
+            raise PPError(s, N.lib().pp_last_error(self.h).decode())
+
+    def set_tuning(self, diffuse_tile=0, diffuse_t=0, score_hb=0, score_chunk=0):
+        t = N.Tuning(diffuse_tile, diffuse_t, score_hb, score_chunk)
+        self.check(N.lib().pp_set_tuning(self.h, ctypes.byref(t)))
+
+    def reset_tuning(self):
+        self.check(N.lib().pp_set_tuning(self.h, None))
+
+    def set_stage_timing(self, enable: bool):
+        self.check(N.lib().pp_set_stage_timing(self.h, 1 if enable else 0))
+
+    def stage_time(self):
+        """(summed ms, launches) of the scoring launches of the last run (stream must be synchronised)."""
+        ms, n = N.c_f32(), N.c_i32()
+        self.check(N.lib().pp_stage_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+    def get_tuning(self) -> dict:
+        t = N.Tuning()
+        self.check(N.lib().pp_get_tuning(self.h, ctypes.byref(t)))
+        return dict(diffuse_tile=t.diffuse_tile, diffuse_t=t.diffuse_t, score_hb=t.score_hb, score_chunk=t.score_chunk)
+
+
+_default = {}
+
+
+def default_context(device: Optional[int] = None) -> Context:
+    torch = _torch()
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def _desc(H: int, W: int, pitch: Optional[int] = None) -> N.FrameDesc:
+    return N.FrameDesc(int(W), int(H), int(pitch if pitch is not None else W))
+
+
+def diffuse(depth, iters: int = 20, lam: float = 0.2, kappa_mm: float = 30.0, edge_stop: int = PP_EDGE_EXP,
+            out=None, ctx: Optional[Context] = None, stream=None):
+    """Step 1: Perona-Malik diffusion (Eq. 1, Alg. 1) of a [H][W] uint16/int16
+    depth tensor in mm -> float32 [H][W] mm (holes stay 0)."""
+    torch = _torch()
+    _check_dev(depth, "depth", (torch.uint16, torch.int16))
+    H, W = depth.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=depth.device)
+    _check_dev(out, "out", (torch.float32,), (H, W))
+    ctx = ctx or default_context(depth.device.index)
+    p = DiffuseConfig(iters, lam, kappa_mm, edge_stop).c()
+    ctx.check(N.lib().pp_diffuse(ctx.h, _ptr(depth), _ptr(out), _desc(H, W), ctypes.byref(p), _stream(stream)))
+    return out
+
+
+def normals(depth_mm, K, points=None, nrm=None, valid=None, ctx: Optional[Context] = None, stream=None):
+    """Steps 2-3: back-projection and Sobel normals (Alg. 2, Eq. 2, Alg. 1).
+    K = (fx, fy, cx, cy).  Returns (points [3][H][W] m, normals [3][H][W], valid u8)."""
+    torch = _torch()
+    _check_dev(depth_mm, "depth_mm", (torch.float32,))
+    H, W = depth_mm.shape
+    dev = depth_mm.device
+    points = points if points is not None else torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    nrm = nrm if nrm is not None else torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    valid = valid if valid is not None else torch.empty((H, W), dtype=torch.uint8, device=dev)
+    _check_dev(points, "points", (torch.float32,), (3, H, W))
+    _check_dev(nrm, "normals", (torch.float32,), (3, H, W))
+    _check_dev(valid, "valid", (torch.uint8,), (H, W))
+    ctx = ctx or default_context(dev.index)
+    Kc = N.Intrinsics(*[float(x) for x in K])
+    ctx.check(N.lib().pp_normals(ctx.h, _ptr(depth_mm), _desc(H, W), Kc, _ptr(points), _ptr(nrm), _ptr(valid),
+                                 _stream(stream)))
+    return points, nrm, valid
+
+
+PLANE_BYTES = ctypes.sizeof(N.Plane)
+
+
+def planes_to_numpy(planes_u8, n: int):
+    """Decode a byte tensor of pp_plane records into numpy: (n, d, centroid, inliers, hyp_index)."""
+    import numpy as np
+    raw = planes_u8.detach().cpu().numpy().tobytes()
+    recs = (N.Plane * (len(raw) // PLANE_BYTES)).from_buffer_copy(raw)
+    out = []
+    for i in range(n):
+        r = recs[i]
+        out.append(dict(n=np.array(r.n[:]), d=r.d, centroid=np.array(r.centroid[:]), inliers=r.inliers,
+                        hyp_index=r.hyp_index))
+    return out
+
+
+def _ransac_outputs(H, W, cfg: RansacConfig, dev):
+    torch = _torch()
+    planes = torch.zeros((cfg.max_planes * PLANE_BYTES,), dtype=torch.uint8, device=dev)
+    n = torch.zeros((1,), dtype=torch.int32, device=dev)
+    labels = torch.empty((H, W), dtype=torch.int8, device=dev)
+    return planes, n, labels
+
+
+def ransac_planes(points, valid, cfg: RansacConfig, planes=None, n_planes=None, labels=None,
+                  ctx: Optional[Context] = None, stream=None):
+    """Step 4: sequential RANSAC (Alg. 2, Eq. 3).  Returns (planes as pp_plane
+    bytes [max_planes*64] u8, n_planes int32 [1], labels int8 [H][W])."""
+    torch = _torch()
+    _check_dev(points, "points", (torch.float32,))
+    _, H, W = points.shape
+    _check_dev(valid, "valid", (torch.uint8,), (H, W))
+    dev = points.device
+    if planes is None:
+        planes, n_planes, labels = _ransac_outputs(H, W, cfg, dev)
+    ctx = ctx or default_context(dev.index)
+    p = cfg.c()
+    ctx.check(N.lib().pp_ransac_planes(ctx.h, _ptr(points), _ptr(valid), None, _desc(H, W), ctypes.byref(p),
+                                       _ptr(planes), _ptr(n_planes), _ptr(labels), _stream(stream)))
+    return planes, n_planes, labels
+
+
+def ransac_planes_debug(points, valid, cfg: RansacConfig, ctx: Optional[Context] = None, stream=None):
+    """ransac_planes plus per-round introspection (hypotheses, triples,
+    counts, round info, S/F masks, valid list)."""
+    torch = _torch()
+    _, H, W = points.shape
+    dev = points.device
+    R, Hy = cfg.max_planes, cfg.hyps
+    planes, n_planes, labels = _ransac_outputs(H, W, cfg, dev)
+    dbg_t = dict(
+        counts=torch.zeros((R, Hy), dtype=torch.int32, device=dev),
+        hyps=torch.zeros((R, Hy, 4), dtype=torch.float32, device=dev),
+        triples=torch.full((R, Hy, 3), -2, dtype=torch.int32, device=dev),
+        round_info=torch.zeros((R, 4), dtype=torch.int32, device=dev),
+        masks=torch.zeros((R, H * W), dtype=torch.uint8, device=dev),
+        valid_list=torch.zeros((H * W,), dtype=torch.int32, device=dev),
+        n_valid=torch.zeros((1,), dtype=torch.int32, device=dev),
+    )
+    dbg = N.RansacDebug(*[_ptr(dbg_t[k]) for k in ("counts", "hyps", "triples", "round_info", "masks",
+                                                      "valid_list", "n_valid")])
+    ctx = ctx or default_context(dev.index)
+    p = cfg.c()
+    ctx.check(N.lib().pp_ransac_planes_dbg(ctx.h, _ptr(points), _ptr(valid), _desc(H, W), ctypes.byref(p),
+                                           _ptr(planes), _ptr(n_planes), _ptr(labels), ctypes.byref(dbg),
+                                           _stream(stream)))
+    return planes, n_planes, labels, dbg_t
+
+
+def score_triples(points, valid, triples, thresh_m: float, precision: int = PP_SCORE_FP32,
+                  recheck_band_m: float = 0.0, ctx: Optional[Context] = None, stream=None):
+    """Inlier counts of caller-given triples of pixel offsets over every
+    depth-valid point -> (planes float32 [n][4], counts int32 [n])."""
+    torch = _torch()
+    _, H, W = points.shape
+    _check_dev(triples, "triples", (torch.int32,))
+    n = triples.shape[0]
+    dev = points.device
+    planes = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    counts = torch.empty((n,), dtype=torch.int32, device=dev)
+    ctx = ctx or default_context(dev.index)
+    ctx.check(N.lib().pp_debug_score_triples(ctx.h, _ptr(points), _ptr(valid), _desc(H, W), _ptr(triples), int(n),
+                                             float(thresh_m), int(precision), float(recheck_band_m), _ptr(planes),
+                                             _ptr(counts), _stream(stream)))
+    return planes, counts
+
+
+@dataclass
+class FrameOutputs:
+    """Device buffers of one frame's results (allocated once, reused)."""
+    depth: object        # uint16/int16 [H][W] input
+    depth_mm: object     # float32 [H][W]
+    points: object       # float32 [3][H][W]
+    normals: object      # float32 [3][H][W]
+    valid: object        # uint8 [H][W]
+    planes: object       # uint8 [max_planes * 64]
+    n_planes: object     # int32 [1]
+    labels: object       # int8 [H][W]
+    K: Tuple[float, float, float, float]
+    diffuse: DiffuseConfig
+    ransac: RansacConfig
+
+    def job(self) -> N.FrameJob:
+        H, W = self.depth.shape
+        return N.FrameJob(_ptr(self.depth), _desc(H, W), N.Intrinsics(*[float(x) for x in self.K]), self.diffuse.c(),
+                          self.ransac.c(), _ptr(self.depth_mm), _ptr(self.points), _ptr(self.normals),
+                          _ptr(self.valid), _ptr(self.planes), _ptr(self.n_planes), _ptr(self.labels))
+
+
+def make_outputs(depth, K, diffuse_cfg: DiffuseConfig, ransac_cfg: RansacConfig) -> FrameOutputs:
+    torch = _torch()
+    _check_dev(depth, "depth", (torch.uint16, torch.int16))
+    H, W = depth.shape
+    dev = depth.device
+    planes, n, labels = _ransac_outputs(H, W, ransac_cfg, dev)
+    return FrameOutputs(depth, torch.empty((H, W), dtype=torch.float32, device=dev),
+                        torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                        torch.empty((3, H, W), dtype=torch.float32, device=dev),
+                        torch.empty((H, W), dtype=torch.uint8, device=dev), planes, n, labels, tuple(K),
+                        diffuse_cfg, ransac_cfg)
+
+
+def batch_run(frames: Sequence[FrameOutputs], graph: bool = True, ctx: Optional[Context] = None, stream=None):
+    """Run a ragged batch of frames through all four steps in one launch per
+    stage (captured once per batch layout into a HIP graph when graph=True)."""
+    if not frames:
+        return
+    jobs = (N.FrameJob * len(frames))(*[f.job() for f in frames])
+    ctx = ctx or default_context(frames[0].depth.device.index)
+    fn = N.lib().pp_batch_run if graph else N.lib().pp_batch_run_eager
+    ctx.check(fn(ctx.h, len(frames), jobs, _stream(stream)))
+
+
+def run_frame(fo: FrameOutputs, ctx: Optional[Context] = None, stream=None):
+    """The plain per-frame path: pp_diffuse, pp_normals, pp_ransac_planes on one stream."""
+    H, W = fo.depth.shape
+    diffuse(fo.depth, fo.diffuse.iters, fo.diffuse.lam, fo.diffuse.kappa_mm, fo.diffuse.edge_stop, out=fo.depth_mm,
+            ctx=ctx, stream=stream)
+    normals(fo.depth_mm, fo.K, fo.points, fo.normals, fo.valid, ctx=ctx, stream=stream)
+    ransac_planes(fo.points, fo.valid, fo.ransac, fo.planes, fo.n_planes, fo.labels, ctx=ctx, stream=stream)

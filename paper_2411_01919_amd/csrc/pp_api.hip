@@ -1,0 +1,674 @@
+// C ABI of libpp.so: contexts, argument checks, scratch management and the
+// launch sequences of the plain (per-stage), per-frame and batched paths.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "pp_internal.h"
+
+using ppk::FrameDev;
+using ppk::RoundState;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// Library scratch of one frame slot, carved out of a single allocation.
+struct Slot {
+    void* base = nullptr;
+    size_t bytes = 0;
+    size_t px_cap = 0;
+    int hyp_cap = 0;
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct pp_ctx {
+    int device = 0;
+    bool poisoned = false;
+    std::string last_error;
+    ppk::Tuning tuning{0, 5, 1, 2};
+    std::vector<Slot> slots;
+    // device frame tables: [0] single-frame calls, [1] batches
+    FrameDev* plain_tab = nullptr;
+    FrameDev* batch_tab = nullptr;
+    int batch_tab_cap = 0;
+    // pinned staging for batch tables (ring, one event per entry)
+    static constexpr int kRing = 8;
+    FrameDev* staging[kRing] = {nullptr};
+    int staging_cap[kRing] = {0};
+    hipEvent_t staging_ev[kRing] = {nullptr};
+    bool staging_used[kRing] = {false};
+    int ring_pos = 0;
+    hipStream_t capture_stream = nullptr;
+    std::map<std::string, GraphEntry> graphs;
+    void* debug_scratch = nullptr;
+    size_t debug_scratch_bytes = 0;
+    // stage timing: events around each round's scoring launch
+    bool timing = false;
+    hipEvent_t score_ev[ppk::kMaxRounds][2] = {};
+    int timed_rounds = 0;
+};
+
+namespace {
+
+pp_status fail(pp_ctx* c, pp_status s, const std::string& msg) {
+    if (c) {
+        c->last_error = msg;
+        if (s == PP_E_HIP) c->poisoned = true;
+    } else {
+        g_create_error = msg;
+    }
+    return s;
+}
+
+pp_status hip_fail(pp_ctx* c, hipError_t e, const char* where) {
+    return fail(c, PP_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call)                                        \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
+    } while (0)
+
+bool desc_ok(const pp_frame_desc& d) {
+    return d.width >= 3 && d.height >= 3 && d.width <= 16384 && d.height <= 16384 && d.pitch_px >= d.width &&
+           (int64_t)d.width * d.height <= (int64_t(1) << 27) && (int64_t)d.pitch_px * d.height <= (int64_t(1) << 30);
+}
+
+bool diffuse_params_ok(const pp_diffuse_params* p) {
+    return p && p->iters >= 0 && p->iters <= 1000 && p->lambda > 0.f && p->lambda <= 0.25f && p->kappa_mm > 0.f &&
+           isfinite(p->lambda) && (p->edge_stop == PP_EDGE_EXP || p->edge_stop == PP_EDGE_RATIONAL);
+}
+
+bool ransac_params_ok(const pp_ransac_params* p) {
+    return p && p->max_planes >= 1 && p->max_planes <= ppk::kMaxRounds && p->hyps_per_plane >= 1 &&
+           p->hyps_per_plane <= ppk::kMaxHyps && p->min_inliers >= 1 && p->thresh_m > 0.f && isfinite(p->thresh_m) &&
+           p->precision >= PP_SCORE_FP32 && p->precision <= PP_SCORE_FP16 && p->recheck_band_m >= 0.f &&
+           isfinite(p->recheck_band_m);
+}
+
+bool intrinsics_ok(const pp_intrinsics& K) {
+    return K.fx > 0.f && K.fy > 0.f && isfinite(K.fx) && isfinite(K.fy) && isfinite(K.cx) && isfinite(K.cy);
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t delta, L, list, hyp, triples, counts, partials, chunk_cnt, st, total;
+};
+
+Layout slot_layout(size_t px, int hyps) {
+    Layout l;
+    const size_t nch_refit = (px + ppk::kRefitChunk - 1) / ppk::kRefitChunk;
+    const size_t nch_valid = (px + ppk::kValidChunk - 1) / ppk::kValidChunk;
+    size_t o = 0;
+    l.delta = o; o += align256(2 * px * sizeof(float));
+    l.L = o; o += align256(px * sizeof(int32_t));
+    l.list = o; o += align256(2 * px * sizeof(float4));
+    l.hyp = o; o += align256((size_t)hyps * sizeof(float4));
+    l.triples = o; o += align256((size_t)hyps * 3 * sizeof(int32_t));
+    l.counts = o; o += align256((size_t)hyps * sizeof(int32_t));
+    l.partials = o; o += align256(nch_refit * 10 * sizeof(double));
+    l.chunk_cnt = o; o += align256(std::max(nch_refit, nch_valid) * sizeof(int32_t));
+    l.st = o; o += align256(sizeof(RoundState));
+    l.total = o;
+    return l;
+}
+
+// Make slot i big enough for px pixels and hyps hypotheses.  Growing waits
+// for the device first: earlier work may still use the old buffers.
+pp_status ensure_slot(pp_ctx* c, int i, size_t px, int hyps) {
+    if ((int)c->slots.size() <= i) c->slots.resize(i + 1);
+    Slot& s = c->slots[i];
+    if (s.base && s.px_cap >= px && s.hyp_cap >= hyps) return PP_OK;
+    const size_t npx = std::max(px, s.px_cap);
+    const int nh = std::max(hyps, s.hyp_cap);
+    Layout l = slot_layout(npx, nh);
+    if (s.base) {
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipFree(s.base));
+        s.base = nullptr;
+    }
+    hipError_t e = hipMalloc(&s.base, l.total);
+    if (e != hipSuccess) {
+        s.base = nullptr;
+        s.px_cap = 0;
+        s.hyp_cap = 0;
+        (void)hipGetLastError();
+        return fail(c, PP_E_NOMEM, "hipMalloc of frame scratch failed");
+    }
+    s.bytes = l.total;
+    s.px_cap = npx;
+    s.hyp_cap = nh;
+    return PP_OK;
+}
+
+void bind_slot(const pp_ctx* c, int i, FrameDev& f) {
+    const Slot& s = c->slots[i];
+    Layout l = slot_layout(s.px_cap, s.hyp_cap);
+    char* b = static_cast<char*>(s.base);
+    f.delta[0] = reinterpret_cast<float*>(b + l.delta);
+    f.delta[1] = f.delta[0] + s.px_cap;
+    f.L = reinterpret_cast<int32_t*>(b + l.L);
+    f.list[0] = reinterpret_cast<float4*>(b + l.list);
+    f.list[1] = f.list[0] + s.px_cap;
+    f.hyp = reinterpret_cast<float4*>(b + l.hyp);
+    f.triples = reinterpret_cast<int32_t*>(b + l.triples);
+    f.counts = reinterpret_cast<int32_t*>(b + l.counts);
+    f.partials = reinterpret_cast<double*>(b + l.partials);
+    f.chunk_cnt = reinterpret_cast<int32_t*>(b + l.chunk_cnt);
+    f.st = reinterpret_cast<RoundState*>(b + l.st);
+}
+
+void fill_geometry(FrameDev& f, const pp_frame_desc& d) {
+    f.W = d.width;
+    f.H = d.height;
+    f.pitch = d.pitch_px;
+}
+
+void fill_diffuse(FrameDev& f, const pp_diffuse_params& p) {
+    f.iters = p.iters;
+    f.lambda = p.lambda;
+    f.edge_stop = p.edge_stop;
+    const double k2 = (double)p.kappa_mm * (double)p.kappa_mm;
+    // exp(-(x/k)^2) = 2^(-x^2 log2(e)/k^2); as k -> inf the scale underflows to 0 and g == 1
+    f.g_scale = (float)(p.edge_stop == PP_EDGE_RATIONAL ? 1.0 / k2 : 1.4426950408889634 / k2);
+}
+
+void fill_ransac(FrameDev& f, const pp_ransac_params& p) {
+    f.max_planes = p.max_planes;
+    f.hyps = p.hyps_per_plane;
+    f.min_inliers = p.min_inliers;
+    f.precision = p.precision;
+    f.thresh = p.thresh_m;
+    f.band = p.recheck_band_m;
+    f.seed = p.seed;
+    f.frame_id = p.frame_id;
+}
+
+__global__ void k_set_frame(FrameDev* dst, FrameDev v) { *dst = v; }
+
+__global__ void k_force_active(FrameDev* tab) {
+    RoundState* st = tab[0].st;
+    st->active[0] = st->M0 > 0 ? 1 : 0;
+}
+
+pp_status put_plain(pp_ctx* c, const FrameDev& f, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_frame, dim3(1), dim3(1), 0, s, c->plain_tab, f);
+    HIPCHK(c, hipGetLastError());
+    return PP_OK;
+}
+
+pp_status check_ctx(pp_ctx* c) {
+    if (!c) return PP_E_INVAL;
+    if (c->poisoned) return PP_E_HIP;
+    return PP_OK;
+}
+
+pp_status set_device(pp_ctx* c) {
+    HIPCHK(c, hipSetDevice(c->device));
+    return PP_OK;
+}
+
+}  // namespace
+
+// =====================================================================
+extern "C" {
+
+const char* pp_status_string(pp_status s) {
+    switch (s) {
+        case PP_OK: return "ok";
+        case PP_PENDING: return "pending";
+        case PP_E_INVAL: return "invalid argument";
+        case PP_E_NOMEM: return "out of device memory";
+        case PP_E_BUDGET: return "exceeds the HBM budget";
+        case PP_E_HIP: return "HIP runtime error";
+        case PP_E_NODEVICE: return "no GPU device";
+        case PP_E_CLOSED: return "closed";
+        case PP_E_UNSUPPORTED: return "unsupported";
+        case PP_E_TIMEOUT: return "timed out";
+        default: return "unknown status";
+    }
+}
+
+const char* pp_last_error(const pp_ctx* c) { return c ? c->last_error.c_str() : g_create_error.c_str(); }
+
+pp_status pp_ctx_create(int32_t device, pp_ctx** out) {
+    if (!out) return PP_E_INVAL;
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return fail(nullptr, PP_E_NODEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= n) return fail(nullptr, PP_E_INVAL, "device index out of range");
+    pp_ctx* c = new pp_ctx();
+    c->device = device;
+    e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMalloc(&c->plain_tab, sizeof(FrameDev));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+    for (int i = 0; e == hipSuccess && i < pp_ctx::kRing; ++i) e = hipEventCreateWithFlags(&c->staging_ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        g_create_error = std::string("context set-up failed: ") + hipGetErrorString(e);
+        pp_ctx_destroy(c);
+        return e == hipErrorOutOfMemory ? PP_E_NOMEM : PP_E_HIP;
+    }
+    *out = c;
+    return PP_OK;
+}
+
+pp_status pp_ctx_destroy(pp_ctx* c) {
+    if (!c) return PP_E_INVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : c->graphs)
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    for (auto& s : c->slots)
+        if (s.base) (void)hipFree(s.base);
+    if (c->plain_tab) (void)hipFree(c->plain_tab);
+    if (c->batch_tab) (void)hipFree(c->batch_tab);
+    if (c->debug_scratch) (void)hipFree(c->debug_scratch);
+    for (int i = 0; i < pp_ctx::kRing; ++i) {
+        if (c->staging[i]) (void)hipHostFree(c->staging[i]);
+        if (c->staging_ev[i]) (void)hipEventDestroy(c->staging_ev[i]);
+    }
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    for (int r = 0; r < ppk::kMaxRounds; ++r)
+        for (int k = 0; k < 2; ++k)
+            if (c->score_ev[r][k]) (void)hipEventDestroy(c->score_ev[r][k]);
+    delete c;
+    return PP_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+pp_status pp_tuning_space(int32_t* n_tiles, int32_t* max_t, int32_t* n_hb, int32_t* n_chunk) {
+    if (n_tiles) *n_tiles = ppk::kNumTiles;
+    if (max_t) *max_t = ppk::kMaxT;
+    if (n_hb) *n_hb = ppk::kNumHB;
+    if (n_chunk) *n_chunk = ppk::kNumChunk;
+    return PP_OK;
+}
+
+pp_status pp_set_tuning(pp_ctx* c, const pp_tuning* t) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if (!t) {
+        c->tuning = ppk::Tuning{0, 5, 1, 2};
+        return PP_OK;
+    }
+    ppk::Tuning n = c->tuning;
+    if (t->diffuse_tile) {
+        if (t->diffuse_tile < 1 || t->diffuse_tile > ppk::kNumTiles) return fail(c, PP_E_INVAL, "diffuse_tile out of range");
+        n.diffuse_tile = t->diffuse_tile - 1;
+    }
+    if (t->diffuse_t) {
+        if (!ppk::t_supported(t->diffuse_t)) return fail(c, PP_E_INVAL, "diffuse_t must be one of 1,2,3,4,5,8,10");
+        n.diffuse_t = t->diffuse_t;
+    }
+    if (t->score_hb) {
+        if (t->score_hb < 1 || t->score_hb > ppk::kNumHB) return fail(c, PP_E_INVAL, "score_hb out of range");
+        n.score_hb = t->score_hb - 1;
+    }
+    if (t->score_chunk) {
+        if (t->score_chunk < 1 || t->score_chunk > ppk::kNumChunk) return fail(c, PP_E_INVAL, "score_chunk out of range");
+        n.score_chunk = t->score_chunk - 1;
+    }
+    c->tuning = n;
+    c->graphs.clear();  // captured launch shapes change
+    return PP_OK;
+}
+
+pp_status pp_get_tuning(const pp_ctx* c, pp_tuning* out) {
+    if (!c || !out) return PP_E_INVAL;
+    out->diffuse_tile = c->tuning.diffuse_tile + 1;
+    out->diffuse_t = c->tuning.diffuse_t;
+    out->score_hb = c->tuning.score_hb + 1;
+    out->score_chunk = c->tuning.score_chunk + 1;
+    return PP_OK;
+}
+
+pp_status pp_set_stage_timing(pp_ctx* c, int32_t enable) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if ((s = set_device(c)) != PP_OK) return s;
+    if (enable && !c->score_ev[0][0])
+        for (int r = 0; r < ppk::kMaxRounds; ++r)
+            for (int k = 0; k < 2; ++k) HIPCHK(c, hipEventCreate(&c->score_ev[r][k]));
+    if (c->timing != (enable != 0)) c->graphs.clear();  // captured graphs differ by the event nodes
+    c->timing = enable != 0;
+    c->timed_rounds = 0;
+    return PP_OK;
+}
+
+pp_status pp_stage_time(pp_ctx* c, float* total_ms, int32_t* launches) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if (!total_ms || !launches) return fail(c, PP_E_INVAL, "pp_stage_time: null output");
+    float tot = 0.f;
+    for (int r = 0; r < c->timed_rounds; ++r) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->score_ev[r][0], c->score_ev[r][1]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = c->timed_rounds;
+    return PP_OK;
+}
+
+// ------------------------------------------------------------------ stages
+pp_status pp_diffuse(pp_ctx* c, const uint16_t* depth_dev, float* out_mm_dev, pp_frame_desc desc,
+                     const pp_diffuse_params* p, void* stream) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if (!depth_dev || !out_mm_dev || !desc_ok(desc) || !diffuse_params_ok(p))
+        return fail(c, PP_E_INVAL, "pp_diffuse: bad argument");
+    if ((s = set_device(c)) != PP_OK) return s;
+    const size_t px = (size_t)desc.width * desc.height;
+    if ((s = ensure_slot(c, 0, px, 1)) != PP_OK) return s;
+    FrameDev f{};
+    bind_slot(c, 0, f);
+    fill_geometry(f, desc);
+    fill_diffuse(f, *p);
+    f.depth = depth_dev;
+    f.dmm = out_mm_dev;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = put_plain(c, f, st)) != PP_OK) return s;
+    HIPCHK(c, ppk::launch_diffuse(c->plain_tab, 1, desc.width, desc.height, p->iters, c->tuning, st));
+    return PP_OK;
+}
+
+pp_status pp_normals(pp_ctx* c, const float* depth_mm_dev, pp_frame_desc desc, pp_intrinsics K, float* points_dev,
+                     float* normals_dev, uint8_t* valid_dev, void* stream) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if (!depth_mm_dev || !points_dev || !normals_dev || !valid_dev || !desc_ok(desc) || !intrinsics_ok(K))
+        return fail(c, PP_E_INVAL, "pp_normals: bad argument");
+    if ((s = set_device(c)) != PP_OK) return s;
+    FrameDev f{};
+    fill_geometry(f, desc);
+    f.dmm = const_cast<float*>(depth_mm_dev);
+    f.pts = points_dev;
+    f.nrm = normals_dev;
+    f.valid = valid_dev;
+    f.fx = K.fx; f.fy = K.fy; f.cx = K.cx; f.cy = K.cy;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = put_plain(c, f, st)) != PP_OK) return s;
+    HIPCHK(c, ppk::launch_normals(c->plain_tab, 1, desc.width, desc.height, st));
+    return PP_OK;
+}
+
+static pp_status ransac_common(pp_ctx* c, const float* points_dev, const uint8_t* valid_dev, pp_frame_desc desc,
+                               const pp_ransac_params* p, pp_plane* planes_dev, int32_t* n_planes_dev,
+                               int8_t* labels_dev, const pp_ransac_debug* dbg, void* stream) {
+    pp_status s;
+    if (p->precision != PP_SCORE_FP32) return fail(c, PP_E_UNSUPPORTED, "only PP_SCORE_FP32 scoring is built");
+    if ((s = set_device(c)) != PP_OK) return s;
+    const size_t px = (size_t)desc.width * desc.height;
+    if ((s = ensure_slot(c, 0, px, p->hyps_per_plane)) != PP_OK) return s;
+    FrameDev f{};
+    bind_slot(c, 0, f);
+    fill_geometry(f, desc);
+    fill_ransac(f, *p);
+    f.pts = const_cast<float*>(points_dev);
+    f.valid = const_cast<uint8_t*>(valid_dev);
+    f.labels = labels_dev;
+    f.planes = planes_dev;
+    f.n_planes = n_planes_dev;
+    hipStream_t st = (hipStream_t)stream;
+    if (dbg) {
+        f.dbg = *dbg;
+        if (dbg->round_info) HIPCHK(c, hipMemsetAsync(dbg->round_info, 0xFF, sizeof(int32_t) * 4 * p->max_planes, st));
+    }
+    if ((s = put_plain(c, f, st)) != PP_OK) return s;
+    HIPCHK(c, ppk::launch_valid_list(c->plain_tab, 1, (int)px, st));
+    for (int r = 0; r < p->max_planes; ++r)
+        HIPCHK(c, ppk::launch_round(c->plain_tab, 1, r, (int)px, p->hyps_per_plane, p->precision, c->tuning, st,
+                                    c->timing ? c->score_ev[r][0] : nullptr, c->timing ? c->score_ev[r][1] : nullptr));
+    if (c->timing) c->timed_rounds = p->max_planes;
+    return PP_OK;
+}
+
+pp_status pp_ransac_planes(pp_ctx* c, const float* points_dev, const uint8_t* valid_dev,
+                           const int16_t* region_dev_or_null, pp_frame_desc desc, const pp_ransac_params* p,
+                           pp_plane* planes_dev, int32_t* n_planes_dev, int8_t* labels_dev, void* stream) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if (!points_dev || !valid_dev || !planes_dev || !n_planes_dev || !labels_dev || !desc_ok(desc) ||
+        !ransac_params_ok(p))
+        return fail(c, PP_E_INVAL, "pp_ransac_planes: bad argument");
+    if (region_dev_or_null) return fail(c, PP_E_UNSUPPORTED, "per-region RANSAC is not built");
+    return ransac_common(c, points_dev, valid_dev, desc, p, planes_dev, n_planes_dev, labels_dev, nullptr, stream);
+}
+
+pp_status pp_ransac_planes_dbg(pp_ctx* c, const float* points_dev, const uint8_t* valid_dev, pp_frame_desc desc,
+                               const pp_ransac_params* p, pp_plane* planes_dev, int32_t* n_planes_dev,
+                               int8_t* labels_dev, const pp_ransac_debug* dbg, void* stream) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if (!points_dev || !valid_dev || !planes_dev || !n_planes_dev || !labels_dev || !desc_ok(desc) ||
+        !ransac_params_ok(p) || !dbg)
+        return fail(c, PP_E_INVAL, "pp_ransac_planes_dbg: bad argument");
+    return ransac_common(c, points_dev, valid_dev, desc, p, planes_dev, n_planes_dev, labels_dev, dbg, stream);
+}
+
+pp_status pp_debug_score_triples(pp_ctx* c, const float* points_dev, const uint8_t* valid_dev, pp_frame_desc desc,
+                                 const int32_t* triples_dev, int32_t n, float thresh_m, int32_t precision,
+                                 float recheck_band_m, float* planes_dev, int32_t* counts_dev, void* stream) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if (!points_dev || !valid_dev || !triples_dev || !planes_dev || !counts_dev || !desc_ok(desc) || n < 1 ||
+        n > (1 << 24) || !(thresh_m > 0.f) || precision < PP_SCORE_FP32 || precision > PP_SCORE_FP16 ||
+        !(recheck_band_m >= 0.f))
+        return fail(c, PP_E_INVAL, "pp_debug_score_triples: bad argument");
+    if (precision != PP_SCORE_FP32) return fail(c, PP_E_UNSUPPORTED, "only PP_SCORE_FP32 scoring is built");
+    if ((s = set_device(c)) != PP_OK) return s;
+    const size_t px = (size_t)desc.width * desc.height;
+    if ((s = ensure_slot(c, 0, px, 1)) != PP_OK) return s;
+    FrameDev f{};
+    bind_slot(c, 0, f);
+    fill_geometry(f, desc);
+    f.pts = const_cast<float*>(points_dev);
+    f.valid = const_cast<uint8_t*>(valid_dev);
+    f.thresh = thresh_m;
+    f.band = recheck_band_m;
+    f.precision = precision;
+    f.max_planes = 1;
+    f.hyps = n;
+    f.hyp = reinterpret_cast<float4*>(planes_dev);
+    f.counts = counts_dev;
+    // the valid-list pass writes labels and n_planes; point them at scratch
+    const size_t need = align256(px) + 256;
+    if (c->debug_scratch_bytes < need) {
+        if (c->debug_scratch) {
+            HIPCHK(c, hipDeviceSynchronize());
+            HIPCHK(c, hipFree(c->debug_scratch));
+            c->debug_scratch = nullptr;
+            c->debug_scratch_bytes = 0;
+        }
+        HIPCHK(c, hipMalloc(&c->debug_scratch, need));
+        c->debug_scratch_bytes = need;
+    }
+    f.labels = static_cast<int8_t*>(c->debug_scratch);
+    f.n_planes = reinterpret_cast<int32_t*>(static_cast<char*>(c->debug_scratch) + align256(px));
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = put_plain(c, f, st)) != PP_OK) return s;
+    HIPCHK(c, ppk::launch_valid_list(c->plain_tab, 1, (int)px, st));
+    hipLaunchKernelGGL(k_force_active, dim3(1), dim3(1), 0, st, c->plain_tab);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, ppk::launch_hyp_from_triples(c->plain_tab, triples_dev, n, st));
+    HIPCHK(c, ppk::launch_score_only(c->plain_tab, (int)px, n, precision, c->tuning, st));
+    return PP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+namespace {
+
+bool job_ok(const pp_frame_job& j) {
+    return j.depth && j.depth_mm && j.points && j.normals && j.valid && j.planes && j.n_planes && j.labels &&
+           desc_ok(j.desc) && intrinsics_ok(j.K) && diffuse_params_ok(&j.diffuse) && ransac_params_ok(&j.ransac) &&
+           j.ransac.precision == PP_SCORE_FP32;
+}
+
+struct BatchPlan {
+    int nf = 0, maxW = 0, maxH = 0, max_px = 0, max_hyps = 0, max_rounds = 0;
+    std::vector<int> order;                        // table position -> job index
+    std::vector<std::pair<int, int>> iter_groups;  // (first table position, count) with equal iterations
+    std::vector<int> group_iters;
+    std::string key;
+};
+
+BatchPlan plan_batch(const pp_frame_job* jobs, int n, const ppk::Tuning& tu) {
+    BatchPlan b;
+    b.nf = n;
+    b.order.resize(n);
+    for (int i = 0; i < n; ++i) b.order[i] = i;
+    std::stable_sort(b.order.begin(), b.order.end(),
+                     [&](int a, int c) { return jobs[a].diffuse.iters < jobs[c].diffuse.iters; });
+    for (int i = 0; i < n; ++i) {
+        const pp_frame_job& j = jobs[b.order[i]];
+        b.maxW = std::max(b.maxW, j.desc.width);
+        b.maxH = std::max(b.maxH, j.desc.height);
+        b.max_px = std::max(b.max_px, j.desc.width * j.desc.height);
+        b.max_hyps = std::max(b.max_hyps, j.ransac.hyps_per_plane);
+        b.max_rounds = std::max(b.max_rounds, j.ransac.max_planes);
+        if (i == 0 || j.diffuse.iters != jobs[b.order[i - 1]].diffuse.iters) {
+            b.iter_groups.push_back({i, 0});
+            b.group_iters.push_back(j.diffuse.iters);
+        }
+        b.iter_groups.back().second++;
+    }
+    char buf[256];
+    snprintf(buf, sizeof buf, "n%d W%d H%d px%d h%d r%d t%d.%d.%d.%d", n, b.maxW, b.maxH, b.max_px, b.max_hyps,
+             b.max_rounds, tu.diffuse_tile, tu.diffuse_t, tu.score_hb, tu.score_chunk);
+    b.key = buf;
+    for (size_t g = 0; g < b.iter_groups.size(); ++g) {
+        snprintf(buf, sizeof buf, " g%d:%d:%d", b.iter_groups[g].first, b.iter_groups[g].second, b.group_iters[g]);
+        b.key += buf;
+    }
+    return b;
+}
+
+pp_status enqueue_batch(pp_ctx* c, const BatchPlan& b, hipStream_t st) {
+    for (size_t g = 0; g < b.iter_groups.size(); ++g)
+        HIPCHK(c, ppk::launch_diffuse(c->batch_tab + b.iter_groups[g].first, b.iter_groups[g].second, b.maxW, b.maxH,
+                                      b.group_iters[g], c->tuning, st));
+    HIPCHK(c, ppk::launch_normals(c->batch_tab, b.nf, b.maxW, b.maxH, st));
+    HIPCHK(c, ppk::launch_valid_list(c->batch_tab, b.nf, b.max_px, st));
+    for (int r = 0; r < b.max_rounds; ++r)
+        HIPCHK(c, ppk::launch_round(c->batch_tab, b.nf, r, b.max_px, b.max_hyps, PP_SCORE_FP32, c->tuning, st,
+                                    c->timing ? c->score_ev[r][0] : nullptr, c->timing ? c->score_ev[r][1] : nullptr));
+    if (c->timing) c->timed_rounds = b.max_rounds;
+    return PP_OK;
+}
+
+pp_status upload_batch_table(pp_ctx* c, const pp_frame_job* jobs, const BatchPlan& b, hipStream_t st) {
+    pp_status s;
+    for (int i = 0; i < b.nf; ++i) {
+        const pp_frame_job& j = jobs[b.order[i]];
+        if ((s = ensure_slot(c, 1 + i, (size_t)j.desc.width * j.desc.height, j.ransac.hyps_per_plane)) != PP_OK) return s;
+    }
+    if (b.nf > c->batch_tab_cap) {
+        if (c->batch_tab) {
+            HIPCHK(c, hipDeviceSynchronize());
+            HIPCHK(c, hipFree(c->batch_tab));
+            c->batch_tab = nullptr;
+        }
+        HIPCHK(c, hipMalloc(&c->batch_tab, sizeof(FrameDev) * b.nf));
+        c->batch_tab_cap = b.nf;
+        c->graphs.clear();  // captured graphs reference the old table
+    }
+    const int k = c->ring_pos;
+    c->ring_pos = (k + 1) % pp_ctx::kRing;
+    if (c->staging_used[k]) HIPCHK(c, hipEventSynchronize(c->staging_ev[k]));
+    if (c->staging_cap[k] < b.nf) {
+        if (c->staging[k]) HIPCHK(c, hipHostFree(c->staging[k]));
+        c->staging[k] = nullptr;
+        HIPCHK(c, hipHostMalloc((void**)&c->staging[k], sizeof(FrameDev) * b.nf, hipHostMallocDefault));
+        c->staging_cap[k] = b.nf;
+    }
+    for (int i = 0; i < b.nf; ++i) {
+        const pp_frame_job& j = jobs[b.order[i]];
+        FrameDev f{};
+        bind_slot(c, 1 + i, f);
+        fill_geometry(f, j.desc);
+        fill_diffuse(f, j.diffuse);
+        fill_ransac(f, j.ransac);
+        f.fx = j.K.fx; f.fy = j.K.fy; f.cx = j.K.cx; f.cy = j.K.cy;
+        f.depth = j.depth;
+        f.dmm = j.depth_mm;
+        f.pts = j.points;
+        f.nrm = j.normals;
+        f.valid = j.valid;
+        f.labels = j.labels;
+        f.planes = j.planes;
+        f.n_planes = j.n_planes;
+        c->staging[k][i] = f;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->batch_tab, c->staging[k], sizeof(FrameDev) * b.nf, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipEventRecord(c->staging_ev[k], st));
+    c->staging_used[k] = true;
+    return PP_OK;
+}
+
+pp_status batch_run(pp_ctx* c, int32_t n, const pp_frame_job* jobs, void* stream, bool use_graph) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if (n < 1 || n > 65535 || !jobs) return fail(c, PP_E_INVAL, "pp_batch_run: bad frame count");
+    for (int i = 0; i < n; ++i)
+        if (!job_ok(jobs[i])) return fail(c, PP_E_INVAL, "pp_batch_run: bad job " + std::to_string(i));
+    if ((s = set_device(c)) != PP_OK) return s;
+    BatchPlan b = plan_batch(jobs, n, c->tuning);
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = upload_batch_table(c, jobs, b, st)) != PP_OK) return s;
+    if (!use_graph) return enqueue_batch(c, b, st);
+    auto it = c->graphs.find(b.key);
+    if (it == c->graphs.end()) {
+        hipGraph_t g = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+        pp_status es = enqueue_batch(c, b, c->capture_stream);
+        hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+        if (es != PP_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return es;
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+        GraphEntry ge;
+        e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+        it = c->graphs.emplace(b.key, ge).first;
+    }
+    HIPCHK(c, hipGraphLaunch(it->second.exec, st));
+    return PP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pp_status pp_validate_job(const pp_frame_job* job) { return job && job_ok(*job) ? PP_OK : PP_E_INVAL; }
+
+pp_status pp_batch_run(pp_ctx* c, int32_t n, const pp_frame_job* jobs, void* stream) {
+    return batch_run(c, n, jobs, stream, true);
+}
+
+pp_status pp_batch_run_eager(pp_ctx* c, int32_t n, const pp_frame_job* jobs, void* stream) {
+    return batch_run(c, n, jobs, stream, false);
+}
+
+}  // extern "C"

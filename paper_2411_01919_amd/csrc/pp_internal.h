@@ -1,0 +1,102 @@
+// Internal declarations shared by the kernels (pp_kernels.hip) and the C ABI
+// (pp_api.hip) of libpp.so.  Not installed; the public interface is pp.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pp.h"
+
+namespace ppk {
+
+constexpr int kMaxRounds = 127;   // labels are int8
+constexpr int kMaxHyps = 8192;
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64s)
+constexpr int kValidChunk = 1024; // pixels per valid-list chunk
+constexpr int kRefitChunk = 2048; // points per refit / apply chunk
+
+// Per-frame RANSAC state in device memory.  Fields indexed by the round r are
+// written only by an earlier kernel than the ones that read them, so no
+// kernel reads a field another block of the same launch may be writing.
+struct RoundState {
+    int32_t M0;                        // |L|: depth-valid pixels
+    int32_t active[kMaxRounds + 1];    // round r runs iff active[r]
+    int32_t M[kMaxRounds + 1];         // |R_r|: unassigned points entering round r
+    int32_t stop[kMaxRounds + 1];      // round r found no valid hypothesis
+    int32_t jstar[kMaxRounds + 1];
+    double shift[3];                   // moment origin of the current round (a point of j*)
+    double plane[4];                   // refit plane of the current round
+    double centroid[3];
+    int32_t s_count;
+    int32_t pad;
+};
+
+// Everything a kernel needs about one frame.  Kernels read a table of these
+// from device memory and take the frame index from blockIdx.z.
+struct FrameDev {
+    // caller buffers
+    const uint16_t* depth;   // [H][pitch]
+    float* dmm;              // [H][pitch] diffused depth, mm
+    float* pts;              // [3][H][pitch] metres
+    float* nrm;              // [3][H][pitch]
+    uint8_t* valid;          // [H][pitch]
+    int8_t* labels;          // [H][pitch]
+    pp_plane* planes;        // [max_planes]
+    int32_t* n_planes;       // [1]
+    // geometry
+    int32_t W, H, pitch, pad0;
+    float fx, fy, cx, cy;
+    // diffusion
+    int32_t iters;
+    float lambda;
+    float g_scale;           // exp form: log2(e)/kappa^2 ; rational: 1/kappa^2
+    int32_t edge_stop;
+    // RANSAC
+    int32_t max_planes, hyps, min_inliers, precision;
+    float thresh, band;
+    uint64_t seed, frame_id;
+    // library scratch
+    float* delta[2];         // [H][W] diffusion ping-pong (delta = I - I0)
+    int32_t* L;              // [W*H] valid list (pixel offsets y*pitch+x)
+    float4* list[2];         // [W*H] remaining points (x, y, z, offset bits)
+    float4* hyp;             // [hyps] (n, d); d = NaN when invalid
+    int32_t* triples;        // [hyps][3]
+    int32_t* counts;         // [hyps]
+    double* partials;        // [refit chunks][10]
+    int32_t* chunk_cnt;      // [max(valid chunks, refit chunks)]
+    RoundState* st;
+    // introspection (may be null)
+    pp_ransac_debug dbg;
+};
+
+struct Tuning {
+    int diffuse_tile;  // index into the tile table
+    int diffuse_t;     // iterations per pass
+    int score_hb;      // index into {8, 16, 32}
+    int score_chunk;   // index into {1024, 2048, 4096, 8192}
+};
+
+constexpr int kNumTiles = 4;
+constexpr int kMaxT = 10;
+constexpr int kNumHB = 3;
+constexpr int kNumChunk = 4;
+int tile_w(int tile);
+int tile_h(int tile);
+int hb_value(int idx);
+int chunk_value(int idx);
+bool t_supported(int t);
+
+// Launchers (all asynchronous on `s`).  `tab` is a device array of nf frames;
+// the *max* arguments bound the per-frame sizes and size the grids.
+hipError_t launch_diffuse(const FrameDev* tab, int nf, int maxW, int maxH, int iters_max,
+                          const Tuning& tu, hipStream_t s);
+hipError_t launch_normals(const FrameDev* tab, int nf, int maxW, int maxH, hipStream_t s);
+hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, hipStream_t s);
+hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_hyps, int precision,
+                        const Tuning& tu, hipStream_t s, hipEvent_t score_start = nullptr,
+                        hipEvent_t score_end = nullptr);
+hipError_t launch_hyp_from_triples(const FrameDev* tab, const int32_t* triples, int n, hipStream_t s);
+hipError_t launch_score_only(const FrameDev* tab, int max_px, int n, int precision, const Tuning& tu,
+                             hipStream_t s);
+
+}  // namespace ppk

@@ -1,0 +1,850 @@
+// HIP kernels of the plane-extraction path for gfx950 (MI355X, wave64).
+//
+// Stage map (arXiv 2411.01919):
+//   k_diffuse        Perona-Malik diffusion, Eq. 1 / Alg. 1 (LDS halo tiles,
+//                    T iterations fused per pass, FP32 on delta = I - I0)
+//   k_normals        back-projection (Alg. 2) + Sobel normal image (Eq. 2)
+//   k_valid_*        row-major list of depth-valid pixels (Alg. 2 point set)
+//   k_hypgen         3-point hypotheses from Philox4x64-10 (Alg. 2)
+//   k_score          inlier counts, point-to-plane distance < t (Eq. 3, Alg. 2)
+//   k_refit_*        selection + least-squares refit (FP64 moments, Jacobi)
+//   k_apply          remove / label the refit plane's inliers, next round
+//
+// Every kernel takes a device table of FrameDev and reads its frame from
+// blockIdx.z, so one launch serves one frame or a ragged batch alike.
+
+#include <math.h>
+
+#include "pp_internal.h"
+
+namespace ppk {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long w = __shfl_xor(v, o);
+        v = v > w ? v : w;
+    }
+    return v;
+}
+
+// Sum over the 256 threads of a block; every thread gets the total.
+__device__ __forceinline__ int block_sum(int v, int* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+    const unsigned l = threadIdx.x & 63;
+    return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+// Stable compaction step for 256 candidates (one per thread): returns this
+// thread's rank among the flagged threads before it; *total gets the count.
+__device__ __forceinline__ int block_rank(bool flag, int* sh, int* total) {
+    const unsigned long long m = __ballot(flag);
+    const int w = threadIdx.x >> 6;
+    const int in_wave = __popcll(m & lanemask_lt());
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = __popcll(m);
+    __syncthreads();
+    int before = 0;
+    for (int i = 0; i < w; ++i) before += sh[i];
+    *total = sh[0] + sh[1] + sh[2] + sh[3];
+    return before + in_wave;
+}
+
+// The canonical FP32 residual n.p + d of a hypothesis plane.  Every scorer
+// and the refit decide |r| < t with exactly this expression.
+__device__ __forceinline__ float canon_res(const float4 h, float x, float y, float z) {
+    return fmaf(h.x, x, fmaf(h.y, y, fmaf(h.z, z, h.w)));
+}
+
+// Refit planes are FP64; their inlier test evaluates n.p + d for FP32 points
+// in compensated FP32 (hi/lo split plane, error-free products, two-sum), which
+// is accurate to ~2^-44 of the largest term.
+struct SplitPlane {
+    float hx, hy, hz, hd, lx, ly, lz, ld;
+};
+
+__device__ __forceinline__ SplitPlane split_plane(const double* p) {
+    SplitPlane s;
+    s.hx = (float)p[0]; s.lx = (float)(p[0] - (double)s.hx);
+    s.hy = (float)p[1]; s.ly = (float)(p[1] - (double)s.hy);
+    s.hz = (float)p[2]; s.lz = (float)(p[2] - (double)s.hz);
+    s.hd = (float)p[3]; s.ld = (float)(p[3] - (double)s.hd);
+    return s;
+}
+
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ float refit_res(const SplitPlane& q, float x, float y, float z) {
+    const float p0 = q.hx * x, e0 = fmaf(q.hx, x, -p0);
+    const float p1 = q.hy * y, e1 = fmaf(q.hy, y, -p1);
+    const float p2 = q.hz * z, e2 = fmaf(q.hz, z, -p2);
+    float s, t0, t1, t2;
+    two_sum(q.hd, p0, s, t0);
+    two_sum(s, p1, s, t1);
+    two_sum(s, p2, s, t2);
+    const float small = ((q.ld + (e0 + e1 + e2)) + (t0 + t1 + t2)) + (q.lx * x + q.ly * y + q.lz * z);
+    return s + small;
+}
+
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64x64->128 multiplies with the published constants, key bumped by the
+// published Weyl increments between rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const uint64_t a = hi1 ^ c[1] ^ k0, b = hi0 ^ c[3] ^ k1;
+        c[0] = a;
+        c[1] = lo1;
+        c[2] = b;
+        c[3] = lo0;
+    }
+}
+
+// FP32 plane through three points (Alg. 2 "fit plane model"): n = e1 x e2
+// normalised, d = -n.p0, camera-facing (d >= 0); degenerate when
+// |e1 x e2| <= 1e-3 |e1||e2|, returned as d = NaN (never an inlier).
+__device__ __forceinline__ float4 plane_from_points(float3 p0, float3 p1, float3 p2) {
+    const float e1x = p1.x - p0.x, e1y = p1.y - p0.y, e1z = p1.z - p0.z;
+    const float e2x = p2.x - p0.x, e2y = p2.y - p0.y, e2z = p2.z - p0.z;
+    const float mx = e1y * e2z - e1z * e2y;
+    const float my = e1z * e2x - e1x * e2z;
+    const float mz = e1x * e2y - e1y * e2x;
+    const float mn = sqrtf(mx * mx + my * my + mz * mz);
+    const float l1 = sqrtf(e1x * e1x + e1y * e1y + e1z * e1z);
+    const float l2 = sqrtf(e2x * e2x + e2y * e2y + e2z * e2z);
+    if (!(mn > 1e-3f * l1 * l2)) return make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
+    float nx = mx / mn, ny = my / mn, nz = mz / mn;
+    float d = -(nx * p0.x + ny * p0.y + nz * p0.z);
+    if (d < 0.f) {
+        nx = -nx; ny = -ny; nz = -nz; d = -d;
+    }
+    return make_float4(nx, ny, nz, d);
+}
+
+__device__ __forceinline__ float3 load_point(const FrameDev& f, int off) {
+    const size_t plane = (size_t)f.H * f.pitch;
+    return make_float3(f.pts[off], f.pts[plane + off], f.pts[2 * plane + off]);
+}
+
+__device__ __forceinline__ bool hyp_valid(const float4 h) { return h.w == h.w; }
+
+// ------------------------------------------------------------------ diffusion
+// One pass = `it` (<= T) explicit iterations on a TX x TY tile whose LDS copy
+// carries a T-pixel halo; iteration k updates the tile grown by T - it + k
+// ... T - k pixels, so the last one is exact on the tile.  The iterate is kept
+// as delta = I - I0 with I0 the integer input: edge differences are
+// (I0_q - I0_p) + (delta_q - delta_p), the first term exact in FP32.
+template <int TX, int TY, int T>
+__global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__ tab, int it, int first, int last,
+                                                     int src, int dst) {
+    const FrameDev& f = tab[blockIdx.z];
+    const int W = f.W, H = f.H;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    if (x0 >= W || y0 >= H) return;
+    constexpr int EW = TX + 2 * T, EH = TY + 2 * T, EN = EW * EH;
+    __shared__ float s_i0[EN];
+    __shared__ float s_d[2][EN];
+    const float* __restrict__ din = f.delta[src];
+    for (int e = threadIdx.x; e < EN; e += kBlock) {
+        const int ex = e % EW, ey = e / EW;
+        const int x = x0 - T + ex, y = y0 - T + ey;
+        float i0 = 0.f, d = 0.f;
+        if (x >= 0 && x < W && y >= 0 && y < H) {
+            i0 = (float)f.depth[(size_t)y * f.pitch + x];
+            if (!first && i0 > 0.f) d = din[(size_t)y * W + x];
+        }
+        s_i0[e] = i0;
+        s_d[0][e] = d;
+        s_d[1][e] = d;
+    }
+    __syncthreads();
+    const float lam = f.lambda, gs = f.g_scale;
+    const bool rational = f.edge_stop == PP_EDGE_RATIONAL;
+    int cur = 0;
+    for (int k = 1; k <= it; ++k) {
+        const int s = T - it + k;
+        for (int e = threadIdx.x; e < EN; e += kBlock) {
+            const int ex = e % EW, ey = e / EW;
+            if (ex < s || ex >= EW - s || ey < s || ey >= EH - s) continue;
+            const float i0 = s_i0[e];
+            if (!(i0 > 0.f)) continue;
+            const float dc = s_d[cur][e];
+            float flux = 0.f;
+            const int nb[4] = {e - 1, e + 1, e - EW, e + EW};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float iq = s_i0[nb[q]];
+                if (!(iq > 0.f)) continue;  // no flux into holes or across the border
+                const float delta = (iq - i0) + (s_d[cur][nb[q]] - dc);
+                const float a = delta * delta * gs;
+                const float g = rational ? 1.0f / (1.0f + a) : exp2f(-a);
+                flux += g * delta;
+            }
+            s_d[cur ^ 1][e] = dc + lam * flux;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    float* __restrict__ dout = f.delta[dst];
+    for (int e = threadIdx.x; e < TX * TY; e += kBlock) {
+        const int tx = e % TX, ty = e / TX;
+        const int x = x0 + tx, y = y0 + ty;
+        if (x >= W || y >= H) continue;
+        const int ee = (ty + T) * EW + (tx + T);
+        const float i0 = s_i0[ee];
+        const float d = i0 > 0.f ? s_d[cur][ee] : 0.f;
+        if (last)
+            f.dmm[(size_t)y * f.pitch + x] = i0 > 0.f ? i0 + d : 0.f;
+        else
+            dout[(size_t)y * W + x] = d;
+    }
+}
+
+// Zero iterations: the diffused image is the input.
+__global__ __launch_bounds__(kBlock) void k_diffuse_copy(const FrameDev* __restrict__ tab) {
+    const FrameDev& f = tab[blockIdx.z];
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= f.W || y >= f.H) return;
+    const size_t o = (size_t)y * f.pitch + x;
+    f.dmm[o] = (float)f.depth[o];
+}
+
+// ------------------------------------------------------------------ normals
+// Back-projection P = z ((u-cx)/fx, (v-cy)/fy, 1) and the Sobel normal
+// n = -(Sx P x Sy P)/|.|.  Because the ray is affine in (u, v) and Sobel
+// weights sum to zero, Sx P = z_c (8/fx, 0, 0) + sum_k wx_k (z_k - z_c) ray_k
+// (and likewise for Sy): evaluating it in that form avoids the cancellation of
+// summing nearly equal points.  Depth is kept in mm (a common scale factor).
+__global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__ tab) {
+    const FrameDev& f = tab[blockIdx.z];
+    const int W = f.W, H = f.H, pitch = f.pitch;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= W || y >= H) return;
+    const size_t o = (size_t)y * pitch + x;
+    const size_t plane = (size_t)H * pitch;
+    const float I = f.dmm[o];
+    const bool dv = I > 0.f;
+    float px = 0.f, py = 0.f, pz = 0.f;
+    if (dv) {
+        const float z = I / 1000.0f;
+        px = z * ((float)x - f.cx) / f.fx;
+        py = z * ((float)y - f.cy) / f.fy;
+        pz = z;
+    }
+    f.pts[o] = px;
+    f.pts[plane + o] = py;
+    f.pts[2 * plane + o] = pz;
+    bool nv = dv && x >= 1 && x <= W - 2 && y >= 1 && y <= H - 2;
+    float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+    if (nv) {
+        float nbv[3][3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) nbv[j][i] = f.dmm[o + (size_t)(j - 1) * pitch + (i - 1)];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) nv = nv && (nbv[j][i] > 0.f);
+        if (nv) {
+            // sums of w * dI * (u - cx), w * dI * (v - cy), w * dI for both kernels
+            float ax = 0.f, bx = 0.f, cx_ = 0.f, ay = 0.f, by = 0.f, cy_ = 0.f;
+            const float wrow[3] = {1.f, 2.f, 1.f};
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const float wx = (float)(i - 1) * wrow[j];  // Sobel x: [-1 0 1] x [1 2 1]^T
+                    const float wy = (float)(j - 1) * wrow[i];  // Sobel y: its transpose
+                    if (wx == 0.f && wy == 0.f) continue;
+                    const float dI = nbv[j][i] - I;
+                    const float uu = (float)(x + i - 1) - f.cx;
+                    const float vv = (float)(y + j - 1) - f.cy;
+                    ax += wx * dI * uu; bx += wx * dI * vv; cx_ += wx * dI;
+                    ay += wy * dI * uu; by += wy * dI * vv; cy_ += wy * dI;
+                }
+            const float sxx = (8.f * I + ax) / f.fx, sxy = bx / f.fy, sxz = cx_;
+            const float syx = ay / f.fx, syy = (8.f * I + by) / f.fy, syz = cy_;
+            const float mx = sxy * syz - sxz * syy;
+            const float my = sxz * syx - sxx * syz;
+            const float mz = sxx * syy - sxy * syx;
+            const float mn = sqrtf(mx * mx + my * my + mz * mz);
+            nv = mn > 0.f;
+            if (nv) {
+                n0 = -mx / mn;
+                n1 = -my / mn;
+                n2 = -mz / mn;
+            }
+        }
+    }
+    f.nrm[o] = n0;
+    f.nrm[plane + o] = n1;
+    f.nrm[2 * plane + o] = n2;
+    f.valid[o] = (uint8_t)((dv ? 1 : 0) | (nv ? 2 : 0));
+}
+
+// ------------------------------------------------------------------ valid list
+// Row-major list L of depth-valid pixels (the fixed per-frame point set the
+// sampler indexes) plus the round-0 point list; labels start at -1.
+__global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restrict__ tab) {
+    __shared__ int sh[4];
+    const FrameDev& f = tab[blockIdx.z];
+    const int npx = f.W * f.H;
+    const int nch = (npx + kValidChunk - 1) / kValidChunk;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        int cnt = 0;
+        for (int i = threadIdx.x; i < kValidChunk; i += kBlock) {
+            const int p = c * kValidChunk + i;
+            if (p < npx) {
+                const int y = p / f.W, x = p - y * f.W;
+                cnt += f.valid[(size_t)y * f.pitch + x] & 1;
+            }
+        }
+        cnt = block_sum(cnt, sh);
+        if (threadIdx.x == 0) f.chunk_cnt[c] = cnt;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __restrict__ tab) {
+    __shared__ int sh[4];
+    const FrameDev& f = tab[blockIdx.z];
+    const int npx = f.W * f.H;
+    const int nch = (npx + kValidChunk - 1) / kValidChunk;
+    const size_t plane = (size_t)f.H * f.pitch;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        int before = 0;
+        for (int i = threadIdx.x; i < c; i += kBlock) before += f.chunk_cnt[i];
+        before = block_sum(before, sh);
+        int run = before;
+        for (int s = 0; s < kValidChunk; s += kBlock) {
+            const int p = c * kValidChunk + s + threadIdx.x;
+            bool v = false;
+            int off = 0;
+            if (p < npx) {
+                const int y = p / f.W, x = p - y * f.W;
+                off = y * f.pitch + x;
+                v = f.valid[off] & 1;
+                f.labels[off] = -1;
+            }
+            int tot;
+            const int rank = block_rank(v, sh, &tot);
+            if (v) {
+                const int k = run + rank;
+                f.L[k] = off;
+                f.list[0][k] = make_float4(f.pts[off], f.pts[plane + off], f.pts[2 * plane + off], __int_as_float(off));
+                if (f.dbg.valid_list) f.dbg.valid_list[k] = off;
+            }
+            run += tot;
+        }
+        if (c == nch - 1 && threadIdx.x == 0) {
+            RoundState* st = f.st;
+            st->M0 = run;
+            st->M[0] = run;
+            st->active[0] = (run >= 3 && f.max_planes >= 1) ? 1 : 0;
+            for (int r = 1; r <= kMaxRounds; ++r) st->active[r] = 0;
+            f.n_planes[0] = 0;
+            if (f.dbg.n_valid) f.dbg.n_valid[0] = run;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ hypotheses
+// Alg. 2 "select random subset of 3 points": word w of Philox block
+// (j, r, b, 0) under key (seed, frame) picks list position floor(w * M0 / 2^64);
+// it is skipped if that pixel is already assigned or already chosen; 16
+// blocks at most.  The list L is fixed per frame, so the draws of round r do
+// not depend on how many points earlier rounds removed.
+__global__ __launch_bounds__(kBlock) void k_hypgen(const FrameDev* __restrict__ tab, int r) {
+    const FrameDev& f = tab[blockIdx.z];
+    const RoundState* st = f.st;
+    if (!st->active[r]) return;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= f.hyps) return;
+    const uint64_t M0 = (uint64_t)st->M0;
+    int slot[3] = {-1, -1, -1};
+    int got = 0;
+    for (int b = 0; b < 16 && got < 3; ++b) {
+        uint64_t c[4] = {(uint64_t)j, (uint64_t)r, (uint64_t)b, 0ull};
+        philox4x64_10(c, f.seed, f.frame_id);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (got >= 3) break;
+            const int k = (int)__umul64hi(c[q], M0);
+            if (f.labels[f.L[k]] >= 0) continue;
+            if (k == slot[0] || k == slot[1]) continue;
+            slot[got++] = k;
+        }
+    }
+    float4 h = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
+    if (got == 3) h = plane_from_points(load_point(f, f.L[slot[0]]), load_point(f, f.L[slot[1]]), load_point(f, f.L[slot[2]]));
+    f.hyp[j] = h;
+    f.counts[j] = 0;
+    f.triples[3 * j + 0] = got == 3 ? slot[0] : -1;
+    f.triples[3 * j + 1] = got == 3 ? slot[1] : -1;
+    f.triples[3 * j + 2] = got == 3 ? slot[2] : -1;
+    if (f.dbg.hyps) reinterpret_cast<float4*>(f.dbg.hyps)[(size_t)r * f.hyps + j] = h;
+    if (f.dbg.triples) {
+        int32_t* t = f.dbg.triples + ((size_t)r * f.hyps + j) * 3;
+        t[0] = got == 3 ? slot[0] : -1;
+        t[1] = got == 3 ? slot[1] : -1;
+        t[2] = got == 3 ? slot[2] : -1;
+    }
+}
+
+// Planes of caller-given triples of pixel offsets (debug scoring).
+__global__ __launch_bounds__(kBlock) void k_hyp_from_triples(const FrameDev* __restrict__ tab,
+                                                              const int32_t* __restrict__ tri, int n) {
+    const FrameDev& f = tab[0];
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const float4 h = plane_from_points(load_point(f, tri[3 * j]), load_point(f, tri[3 * j + 1]), load_point(f, tri[3 * j + 2]));
+    f.hyp[j] = h;
+    f.counts[j] = 0;
+}
+
+// ------------------------------------------------------------------ scoring
+// count_j = #{i in R_r : |n_j . p_i + d_j| < t}.  A block owns HB hypotheses
+// (uniform: scalar loads into SGPRs) and a strided share of the points, one
+// point per lane; each (point, hypothesis) costs 3 FMA + compare + add.
+// Per-lane counters are wave-reduced once per block and added to the global
+// count with one integer atomic per wave and hypothesis (order-free).
+template <int HB>
+__global__ __launch_bounds__(kBlock) void k_score(const FrameDev* __restrict__ tab, int r) {
+    const FrameDev& f = tab[blockIdx.z];
+    const RoundState* st = f.st;
+    if (!st->active[r]) return;
+    const int M = st->M[r];
+    const int h0 = blockIdx.y * HB;
+    if (h0 >= f.hyps) return;
+    const int start = blockIdx.x * kBlock;
+    if (start >= M) return;
+    const float4* __restrict__ pts = f.list[r & 1];
+    float4 h[HB];
+#pragma unroll
+    for (int i = 0; i < HB; ++i) h[i] = (h0 + i < f.hyps) ? f.hyp[h0 + i] : make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
+    const float t = f.thresh;
+    int cnt[HB];
+#pragma unroll
+    for (int i = 0; i < HB; ++i) cnt[i] = 0;
+    const int stride = gridDim.x * kBlock;
+    for (int i = start + threadIdx.x; i < M; i += stride) {
+        const float4 p = pts[i];
+#pragma unroll
+        for (int k = 0; k < HB; ++k) cnt[k] += fabsf(canon_res(h[k], p.x, p.y, p.z)) < t ? 1 : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < HB; ++k) {
+        const int c = wave_sum(cnt[k]);
+        if ((threadIdx.x & 63) == 0 && c != 0 && h0 + k < f.hyps) atomicAdd(&f.counts[h0 + k], c);
+    }
+}
+
+// ------------------------------------------------------------------ refit
+// Selection (Alg. 2 "best model", read as: most inliers, ties to the lowest
+// index) is recomputed by every block from the counts; then the FP64 moments
+// (n, sum q, sum q q^T with q = p - p0 of j*) of j*'s inliers are summed per
+// fixed chunk of the point list, in a fixed order.
+__device__ __forceinline__ int select_jstar(const FrameDev& f, unsigned long long* sh) {
+    unsigned long long best = 0ull;
+    for (int j = threadIdx.x; j < f.hyps; j += kBlock) {
+        if (!hyp_valid(f.hyp[j])) continue;
+        const unsigned long long key = ((unsigned long long)(uint32_t)f.counts[j] << 32) | (0xFFFFFFFFull - (uint32_t)j);
+        best = key > best ? key : best;
+    }
+    best = wave_max_u64(best);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = best;
+    __syncthreads();
+    best = sh[0];
+    for (int i = 1; i < 4; ++i) best = sh[i] > best ? sh[i] : best;
+    if (best == 0ull) return -1;
+    return (int)(0xFFFFFFFFull - (best & 0xFFFFFFFFull));
+}
+
+__global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __restrict__ tab, int r) {
+    __shared__ unsigned long long shk[4];
+    __shared__ double shd[4][10];
+    const FrameDev& f = tab[blockIdx.z];
+    RoundState* st = f.st;
+    if (!st->active[r]) return;
+    const int M = st->M[r];
+    const int nch = (M + kRefitChunk - 1) / kRefitChunk;
+    if ((int)blockIdx.x >= nch) return;
+    if (blockIdx.x == 0 && f.dbg.counts)
+        for (int j = threadIdx.x; j < f.hyps; j += kBlock) f.dbg.counts[(size_t)r * f.hyps + j] = f.counts[j];
+    const int js = select_jstar(f, shk);
+    if (js < 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->stop[r] = 1;
+            if (f.dbg.round_info) {
+                int32_t* ri = f.dbg.round_info + 4 * r;
+                ri[0] = -1; ri[1] = 0; ri[2] = 0; ri[3] = 1;
+            }
+        }
+        return;
+    }
+    const float4 h = f.hyp[js];
+    const float3 p0 = load_point(f, f.L[f.triples[3 * js]]);
+    const double sx = p0.x, sy = p0.y, sz = p0.z;
+    const float t = f.thresh;
+    const float4* __restrict__ pts = f.list[r & 1];
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const int e = min(M, (c + 1) * kRefitChunk);
+        for (int i = c * kRefitChunk + threadIdx.x; i < e; i += kBlock) {
+            const float4 p = pts[i];
+            if (!(fabsf(canon_res(h, p.x, p.y, p.z)) < t)) continue;
+            const double qx = (double)p.x - sx, qy = (double)p.y - sy, qz = (double)p.z - sz;
+            m[0] += 1.0;
+            m[1] += qx; m[2] += qy; m[3] += qz;
+            m[4] += qx * qx; m[5] += qx * qy; m[6] += qx * qz;
+            m[7] += qy * qy; m[8] += qy * qz; m[9] += qz * qz;
+            if (f.dbg.masks) {
+                const int off = __float_as_int(p.w);
+                const int y = off / f.pitch, x = off - y * f.pitch;
+                f.dbg.masks[(size_t)r * f.W * f.H + (size_t)y * f.W + x] |= 1;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 10; ++k) m[k] = wave_sum_d(m[k]);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0)
+            for (int k = 0; k < 10; ++k) shd[threadIdx.x >> 6][k] = m[k];
+        __syncthreads();
+        if (threadIdx.x < 10) {
+            const int k = threadIdx.x;
+            f.partials[(size_t)c * 10 + k] = ((shd[0][k] + shd[1][k]) + shd[2][k]) + shd[3][k];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->stop[r] = 0;
+        st->jstar[r] = js;
+        st->shift[0] = sx; st->shift[1] = sy; st->shift[2] = sz;
+    }
+}
+
+// Symmetric 3x3 eigenproblem by cyclic Jacobi rotations in the tau form
+// (a'_rp = a_rp - s (a_rq + tau a_rp), tau = s / (1 + c)); columns of v are
+// the eigenvectors.
+__device__ void jacobi3(double a[3][3], double v[3][3]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) v[i][j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+        const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+        if (off == 0.0 || off <= 1e-40 * dia) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                const double apq = a[p][q];
+                if (apq == 0.0) continue;
+                const double theta = 0.5 * (a[q][q] - a[p][p]) / apq;
+                double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
+                if (theta < 0.0) t = -t;
+                const double c = 1.0 / sqrt(1.0 + t * t), s = t * c, tau = s / (1.0 + c);
+                a[p][p] -= t * apq;
+                a[q][q] += t * apq;
+                a[p][q] = a[q][p] = 0.0;
+                const int o = 3 - p - q;  // the remaining index
+                const double g = a[o][p], hh = a[o][q];
+                a[o][p] = a[p][o] = g - s * (hh + g * tau);
+                a[o][q] = a[q][o] = hh + s * (g - hh * tau);
+                for (int k = 0; k < 3; ++k) {
+                    const double vg = v[k][p], vh = v[k][q];
+                    v[k][p] = vg - s * (vh + vg * tau);
+                    v[k][q] = vh + s * (vg - vh * tau);
+                }
+            }
+    }
+}
+
+// Reduce the chunk moments (fixed order), solve for the least-squares plane:
+// centroid c = shift + S/n, scatter C = Q - S S^T / n, normal = eigenvector
+// of the smallest eigenvalue, d = -n.c, flipped so that d >= 0.
+__device__ void solve_refit(const FrameDev& f, int M, double* plane, double* centroid, double* nmom) {
+    const int nch = (M + kRefitChunk - 1) / kRefitChunk;
+    double m[10];
+    for (int k = 0; k < 10; ++k) {
+        double s = 0.0;
+        for (int c = 0; c < nch; ++c) s += f.partials[(size_t)c * 10 + k];
+        m[k] = s;
+    }
+    const double n = m[0];
+    const double mx = m[1] / n, my = m[2] / n, mz = m[3] / n;
+    double a[3][3];
+    a[0][0] = m[4] - m[1] * mx; a[0][1] = m[5] - m[1] * my; a[0][2] = m[6] - m[1] * mz;
+    a[1][1] = m[7] - m[2] * my; a[1][2] = m[8] - m[2] * mz; a[2][2] = m[9] - m[3] * mz;
+    a[1][0] = a[0][1]; a[2][0] = a[0][2]; a[2][1] = a[1][2];
+    double v[3][3];
+    jacobi3(a, v);
+    int kmin = 0;
+    if (a[1][1] < a[kmin][kmin]) kmin = 1;
+    if (a[2][2] < a[kmin][kmin]) kmin = 2;
+    double nx = v[0][kmin], ny = v[1][kmin], nz = v[2][kmin];
+    const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+    nx /= nn; ny /= nn; nz /= nn;
+    const RoundState* st = f.st;
+    const double cx = st->shift[0] + mx, cy = st->shift[1] + my, cz = st->shift[2] + mz;
+    double d = -(nx * cx + ny * cy + nz * cz);
+    if (d < 0.0) {
+        nx = -nx; ny = -ny; nz = -nz; d = -d;
+    }
+    plane[0] = nx; plane[1] = ny; plane[2] = nz; plane[3] = d;
+    centroid[0] = cx; centroid[1] = cy; centroid[2] = cz;
+    *nmom = n;
+}
+
+__global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restrict__ tab, int r) {
+    __shared__ double s_plane[4], s_cent[3], s_n;
+    __shared__ int sh[4];
+    const FrameDev& f = tab[blockIdx.z];
+    RoundState* st = f.st;
+    if (!st->active[r] || st->stop[r]) return;
+    const int M = st->M[r];
+    const int nch = (M + kRefitChunk - 1) / kRefitChunk;
+    if ((int)blockIdx.x >= nch) return;
+    if (threadIdx.x == 0) solve_refit(f, M, s_plane, s_cent, &s_n);
+    __syncthreads();
+    const SplitPlane q = split_plane(s_plane);
+    const float t = f.thresh;
+    const float4* __restrict__ pts = f.list[r & 1];
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        int cnt = 0;
+        const int e = min(M, (c + 1) * kRefitChunk);
+        for (int i = c * kRefitChunk + threadIdx.x; i < e; i += kBlock) {
+            const float4 p = pts[i];
+            cnt += fabsf(refit_res(q, p.x, p.y, p.z)) < t ? 1 : 0;
+        }
+        cnt = block_sum(cnt, sh);
+        if (threadIdx.x == 0) f.chunk_cnt[c] = cnt;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        for (int k = 0; k < 4; ++k) st->plane[k] = s_plane[k];
+        for (int k = 0; k < 3; ++k) st->centroid[k] = s_cent[k];
+        st->s_count = (int)s_n;
+    }
+}
+
+// F = the refit plane's inliers among R_r.  If |F| >= min_inliers: label F
+// with r, write the plane record, and compact the survivors (in order) into
+// the next round's list; otherwise the frame stops without emitting.
+__global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ tab, int r) {
+    __shared__ int sh[4];
+    const FrameDev& f = tab[blockIdx.z];
+    RoundState* st = f.st;
+    if (!st->active[r] || st->stop[r]) return;
+    const int M = st->M[r];
+    const int nch = (M + kRefitChunk - 1) / kRefitChunk;
+    if ((int)blockIdx.x >= nch) return;
+    int ftot = 0;
+    for (int c = threadIdx.x; c < nch; c += kBlock) ftot += f.chunk_cnt[c];
+    ftot = block_sum(ftot, sh);
+    const bool emit = ftot >= f.min_inliers;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int next = M - (emit ? ftot : 0);
+        if (emit) {
+            pp_plane pl;
+            for (int k = 0; k < 3; ++k) pl.n[k] = st->plane[k];
+            pl.d = st->plane[3];
+            for (int k = 0; k < 3; ++k) pl.centroid[k] = st->centroid[k];
+            pl.inliers = ftot;
+            pl.hyp_index = st->jstar[r];
+            f.planes[r] = pl;
+            f.n_planes[0] = r + 1;
+        }
+        st->M[r + 1] = next;
+        st->active[r + 1] = (emit && next >= 3 && r + 1 < f.max_planes) ? 1 : 0;
+        if (f.dbg.round_info) {
+            int32_t* ri = f.dbg.round_info + 4 * r;
+            ri[0] = st->jstar[r]; ri[1] = st->s_count; ri[2] = ftot; ri[3] = emit ? 0 : 2;
+        }
+    }
+    if (!emit) return;
+    const SplitPlane q = split_plane(st->plane);
+    const float t = f.thresh;
+    const float4* __restrict__ pts = f.list[r & 1];
+    float4* __restrict__ out = f.list[(r + 1) & 1];
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        int before = 0;
+        for (int i = threadIdx.x; i < c; i += kBlock) before += kRefitChunk - f.chunk_cnt[i];
+        before = block_sum(before, sh);
+        int run = before;
+        const int e = min(M, (c + 1) * kRefitChunk);
+        for (int s = c * kRefitChunk; s < e; s += kBlock) {
+            const int i = s + threadIdx.x;
+            bool keep = false;
+            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (i < e) {
+                p = pts[i];
+                const bool inF = fabsf(refit_res(q, p.x, p.y, p.z)) < t;
+                keep = !inF;
+                if (inF) {
+                    const int off = __float_as_int(p.w);
+                    f.labels[off] = (int8_t)r;
+                    if (f.dbg.masks) {
+                        const int y = off / f.pitch, x = off - y * f.pitch;
+                        f.dbg.masks[(size_t)r * f.W * f.H + (size_t)y * f.W + x] |= 2;
+                    }
+                }
+            }
+            int tot;
+            const int rank = block_rank(keep, sh, &tot);
+            if (keep) out[run + rank] = p;
+            run += tot;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+static const int kTileW[kNumTiles] = {64, 128, 64, 128};
+static const int kTileH[kNumTiles] = {16, 16, 32, 32};
+static const int kHB[kNumHB] = {8, 16, 32};
+static const int kChunk[kNumChunk] = {1024, 2048, 4096, 8192};
+
+int tile_w(int t) { return kTileW[t]; }
+int tile_h(int t) { return kTileH[t]; }
+int hb_value(int i) { return kHB[i]; }
+int chunk_value(int i) { return kChunk[i]; }
+bool t_supported(int t) { return t == 1 || t == 2 || t == 3 || t == 4 || t == 5 || t == 8 || t == 10; }
+
+template <int TX, int TY, int T>
+static void diffuse_pass(const FrameDev* tab, int nf, int maxW, int maxH, int it, int first, int last, int src,
+                         int dst, hipStream_t s) {
+    dim3 grid((maxW + TX - 1) / TX, (maxH + TY - 1) / TY, nf);
+    hipLaunchKernelGGL((k_diffuse<TX, TY, T>), grid, dim3(kBlock), 0, s, tab, it, first, last, src, dst);
+}
+
+template <int TX, int TY>
+static void diffuse_pass_t(int T, const FrameDev* tab, int nf, int maxW, int maxH, int it, int first, int last,
+                           int src, int dst, hipStream_t s) {
+    switch (T) {
+        case 1: diffuse_pass<TX, TY, 1>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        case 2: diffuse_pass<TX, TY, 2>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        case 3: diffuse_pass<TX, TY, 3>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        case 4: diffuse_pass<TX, TY, 4>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        case 5: diffuse_pass<TX, TY, 5>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        case 8: diffuse_pass<TX, TY, 8>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        default: diffuse_pass<TX, TY, 10>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+    }
+}
+
+// All frames of a table run max(iters) iterations in passes of T; a frame
+// with fewer iterations must not be mixed with others (the batch path groups
+// frames by iteration count).
+hipError_t launch_diffuse(const FrameDev* tab, int nf, int maxW, int maxH, int iters, const Tuning& tu,
+                          hipStream_t s) {
+    if (iters <= 0) {
+        hipLaunchKernelGGL(k_diffuse_copy, dim3((maxW + 63) / 64, (maxH + 3) / 4, nf), dim3(kBlock), 0, s, tab);
+        return hipGetLastError();
+    }
+    const int T = tu.diffuse_t;
+    int done = 0, src = 0, pass = 0;
+    while (done < iters) {
+        const int it = iters - done < T ? iters - done : T;
+        const int first = done == 0, last = done + it == iters;
+        const int dst = src ^ 1;
+        switch (tu.diffuse_tile) {
+            case 0: diffuse_pass_t<64, 16>(T, tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+            case 1: diffuse_pass_t<128, 16>(T, tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+            case 2: diffuse_pass_t<64, 32>(T, tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+            default: diffuse_pass_t<128, 32>(T, tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        }
+        done += it;
+        src = dst;
+        ++pass;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_normals(const FrameDev* tab, int nf, int maxW, int maxH, hipStream_t s) {
+    hipLaunchKernelGGL(k_normals, dim3((maxW + 63) / 64, (maxH + 3) / 4, nf), dim3(kBlock), 0, s, tab);
+    return hipGetLastError();
+}
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, hipStream_t s) {
+    const int nch = (max_px + kValidChunk - 1) / kValidChunk;
+    const int gx = clampi(nch, 1, 1024);
+    hipLaunchKernelGGL(k_valid_count, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab);
+    hipLaunchKernelGGL(k_valid_scatter, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab);
+    return hipGetLastError();
+}
+
+template <int HB>
+static void score_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target, hipStream_t s) {
+    const int groups = (max_hyps + HB - 1) / HB;
+    const int per_frame_cap = clampi(16384 / (nf > 0 ? nf : 1), 8, 4096);
+    const int bx = clampi((max_pts + target - 1) / target, 1, clampi(per_frame_cap / groups, 1, 1024));
+    hipLaunchKernelGGL((k_score<HB>), dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
+}
+
+static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, const Tuning& tu,
+                           hipStream_t s) {
+    const int target = chunk_value(tu.score_chunk);
+    switch (tu.score_hb) {
+        case 0: score_launch<8>(tab, nf, r, max_pts, max_hyps, target, s); break;
+        case 1: score_launch<16>(tab, nf, r, max_pts, max_hyps, target, s); break;
+        default: score_launch<32>(tab, nf, r, max_pts, max_hyps, target, s); break;
+    }
+}
+
+hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_hyps, int precision,
+                        const Tuning& tu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    (void)precision;
+    hipLaunchKernelGGL(k_hypgen, dim3((max_hyps + kBlock - 1) / kBlock, 1, nf), dim3(kBlock), 0, s, tab, r);
+    if (ev0) (void)hipEventRecord(ev0, s);
+    score_dispatch(tab, nf, r, max_px, max_hyps, tu, s);
+    if (ev1) (void)hipEventRecord(ev1, s);
+    const int nch = (max_px + kRefitChunk - 1) / kRefitChunk;
+    const int gx = clampi(nch, 1, 1024);
+    hipLaunchKernelGGL(k_refit_moments, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
+    hipLaunchKernelGGL(k_refit_final, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
+    hipLaunchKernelGGL(k_apply, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_hyp_from_triples(const FrameDev* tab, const int32_t* triples, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_hyp_from_triples, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, tab, triples, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_score_only(const FrameDev* tab, int max_px, int n, int precision, const Tuning& tu, hipStream_t s) {
+    (void)precision;
+    score_dispatch(tab, 1, 0, max_px, n, tu, s);
+    return hipGetLastError();
+}
+
+}  // namespace ppk

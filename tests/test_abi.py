@@ -1,0 +1,117 @@
+"""The C ABI on the CPU: libpp.so loads, exports every entry point pp.h
+declares, its ctypes mirrors match the C layouts, and calls that need no GPU
+behave as documented (no device -> PP_E_NODEVICE, bad jobs -> PP_E_INVAL)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pp.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pp_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_entry_point():
+    from paper_2411_01919_amd import _native as N
+    L = N.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(N.SIGNATURES), set(names) ^ set(N.SIGNATURES)
+
+
+def test_ctypes_structures_match_the_c_layout(tmp_path):
+    from paper_2411_01919_amd import _native as N
+    structs = {"pp_intrinsics": N.Intrinsics, "pp_frame_desc": N.FrameDesc, "pp_diffuse_params": N.DiffuseParams,
+               "pp_ransac_params": N.RansacParams, "pp_plane": N.Plane, "pp_ransac_debug": N.RansacDebug,
+               "pp_frame_job": N.FrameJob, "pp_tuning": N.Tuning}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pp.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        cfields = [f for f, _ in py._fields_]
+        for pf in cfields:
+            cf = "lambda" if pf == "lam" else pf
+            lines.append(f'printf("{cname}.{pf} %zu\\n", offsetof({cname}, {cf}));')
+    lines.append("return 0;}")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split("\n")
+    got = dict(l.split() for l in out if l.strip())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for pf, _ in py._fields_:
+            assert int(got[f"{cname}.{pf}"]) == getattr(py, pf).offset, (cname, pf)
+
+
+def test_status_strings():
+    from paper_2411_01919_amd import _native as N
+    assert N.status_string(0) == "ok"
+    assert N.status_string(N.PP_E_INVAL) == "invalid argument"
+    assert N.status_string(N.PP_E_NODEVICE) == "no GPU device"
+
+
+def _have_gpu():
+    import torch
+    return torch.cuda.is_available()
+
+
+def test_context_without_a_gpu_reports_no_device():
+    if _have_gpu():
+        pytest.skip("a GPU is present")
+    from paper_2411_01919_amd import _native as N
+    h = N.c_vp()
+    s = N.lib().pp_ctx_create(0, ctypes.byref(h))
+    assert s == N.PP_E_NODEVICE and not h.value
+    assert b"no HIP device" in N.lib().pp_last_error(None)
+
+
+def test_calls_on_a_null_context_are_invalid():
+    from paper_2411_01919_amd import _native as N
+    L = N.lib()
+    d = N.FrameDesc(8, 8, 8)
+    p = N.DiffuseParams(1, 0.2, 30.0, 0)
+    assert L.pp_diffuse(None, 1, 1, d, ctypes.byref(p), None) == N.PP_E_INVAL
+    assert L.pp_ctx_destroy(None) == N.PP_E_INVAL
+    assert L.pp_batch_run(None, 1, None, None) == N.PP_E_INVAL
+
+
+def _job(**kw):
+    from paper_2411_01919_amd import _native as N
+    j = N.FrameJob(1, N.FrameDesc(64, 48, 64), N.Intrinsics(50.0, 50.0, 32.0, 24.0), N.DiffuseParams(10, 0.2, 30.0, 0),
+                   N.RansacParams(12, 256, 50, 0.01, 1, 2, 0, 0.0), 1, 1, 1, 1, 1, 1, 1)
+    for k, v in kw.items():
+        obj, field = (j, k) if "." not in k else (getattr(j, k.split(".")[0]), k.split(".")[1])
+        setattr(obj, field, v)
+    return j
+
+
+@pytest.mark.parametrize("change", [
+    {}, {"desc.width": 2}, {"desc.height": 0}, {"desc.pitch_px": 10}, {"desc.width": 20000},
+    {"diffuse.lam": 0.3}, {"diffuse.lam": 0.0}, {"diffuse.kappa_mm": 0.0}, {"diffuse.iters": -1},
+    {"diffuse.edge_stop": 5}, {"ransac.hyps_per_plane": 0}, {"ransac.thresh_m": 0.0}, {"ransac.max_planes": 0},
+    {"ransac.max_planes": 128}, {"ransac.min_inliers": 0}, {"K.fx": 0.0}, {"depth": None}, {"labels": None},
+])
+def test_job_validation_is_host_only(change):
+    from paper_2411_01919_amd import _native as N
+    j = _job(**change)
+    want = N.PP_OK if not change else N.PP_E_INVAL
+    assert N.lib().pp_validate_job(ctypes.byref(j)) == want
+
+
+def test_product_package_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2411_01919_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt and "orc_" not in txt, fn

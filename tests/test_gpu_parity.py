@@ -1,0 +1,411 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Tolerances: diffused depth <= 1e-3 mm max-abs with holes exactly 0; points
+<= 1e-6 m; normals <= 1e-4 rad where both are valid and well conditioned;
+hypothesis triples bit-exact; counts within the band of residuals whose side
+of t FP32 rounding may flip; refit planes 1e-9 against the oracle's refit of
+the GPU's own inlier set; inlier masks bit-exact outside the near-threshold
+band.
+"""
+import numpy as np
+import pytest
+
+import scenes
+from gpu_util import cfg_params, hyp_eps, log, run_plain, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_01919_amd as pp
+    pp.default_context(0)
+    return pp
+
+
+# ------------------------------------------------------------------ diffusion
+@pytest.mark.parametrize("cid,k,edge", [(1, 0, 0), (1, 1, 1), (2, 0, 0), (3, 2, 0)])
+def test_diffusion_matches_oracle(pp, orc, cid, k, edge):
+    log(f"diffusion parity cfg={cid} k={k} edge={edge}")
+    f = scenes.make_frame(cid, k)
+    cfg = scenes.CONFIGS[cid]
+    out = pp.diffuse(to_dev(f.depth), cfg.diffuse_iters, cfg.lam, cfg.kappa_mm, edge).cpu().numpy()
+    ref = orc.diffuse(f.depth, cfg.diffuse_iters, cfg.lam, cfg.kappa_mm, edge)
+    holes = f.depth == 0
+    assert np.all(out[holes] == 0.0)
+    err = np.abs(out.astype(np.float64) - ref)
+    log(f"  max |dI| = {err.max():.3e} mm")
+    assert err.max() <= 1e-3
+    # conservation at rounding level: the summed change is bounded by one ulp per pixel
+    drift = abs(out.astype(np.float64).sum() - f.depth.astype(np.float64).sum())
+    assert drift <= np.spacing(out[~holes]).astype(np.float64).sum()
+
+
+@pytest.mark.parametrize("iters", [1, 7, 20])
+def test_constant_image_is_a_fixed_point(pp, iters):
+    img = np.full((61, 97), 2345, np.uint16)
+    img[np.random.default_rng(iters).random(img.shape) < 0.1] = 0
+    out = pp.diffuse(to_dev(img), iters, 0.25, 30.0).cpu().numpy()
+    assert np.array_equal(out, img.astype(np.float32))
+
+
+def test_all_tunings_give_bitwise_identical_diffusion(pp):
+    f = scenes.make_frame(2, 1)
+    ctx = pp.Context(0)
+    outs = []
+    for tile in (1, 2, 3, 4):
+        for T in (1, 3, 5, 10):
+            ctx.set_tuning(diffuse_tile=tile, diffuse_t=T)
+            outs.append(pp.diffuse(to_dev(f.depth), 20, ctx=ctx).cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    ctx.close()
+
+
+# ------------------------------------------------------------------ normals
+@pytest.mark.parametrize("cid,k", [(1, 0), (2, 0), (3, 1)])
+def test_points_and_normals_match_oracle(pp, orc, cid, k):
+    log(f"normals parity cfg={cid} k={k}")
+    f = scenes.make_frame(cid, k)
+    cfg = scenes.CONFIGS[cid]
+    K = f.K
+    dmm = pp.diffuse(to_dev(f.depth), cfg.diffuse_iters, cfg.lam, cfg.kappa_mm)
+    pts, nrm, valid = pp.normals(dmm, (K.fx, K.fy, K.cx, K.cy))
+    dmm, pts, nrm, valid = (t.cpu().numpy() for t in (dmm, pts, nrm, valid))
+    P, v = orc.backproject(dmm.astype(np.float64), K)
+    assert np.array_equal(valid & 1, v)
+    assert np.max(np.abs(pts - P)) <= 1e-6
+    N, nv, gx, gy = orc.normals(P, v, with_grad=True)
+    assert np.array_equal((valid >> 1) & 1, nv)
+    both = nv > 0
+    m = np.linalg.norm(np.cross(gx.reshape(3, -1).T, gy.reshape(3, -1).T), axis=1).reshape(nv.shape)
+    well = both & (m >= 1e-2 * np.linalg.norm(gx, axis=0) * np.linalg.norm(gy, axis=0))
+    # angle between unit vectors as atan2(|a x b|, a.b): arccos of a dot product
+    # would read the 1e-7 norm error of an FP32 unit vector as 5e-4 rad
+    g = nrm.astype(np.float64)
+    g = g / np.where(both, np.linalg.norm(g, axis=0), 1.0)
+    cr = np.linalg.norm(np.cross(N.reshape(3, -1).T, g.reshape(3, -1).T), axis=1).reshape(nv.shape)
+    ang = np.arctan2(cr, np.einsum("chw,chw->hw", N, g))[well]
+    log(f"  normals: {well.sum()} well-conditioned of {both.sum()}, max angle {ang.max():.2e} rad, "
+        f"grazing {both.sum() - well.sum()} reported apart")
+    assert ang.max() <= 1e-4
+    # end to end against the oracle's own diffusion
+    Po, _ = orc.backproject(orc.diffuse(f.depth, cfg.diffuse_iters, cfg.lam, cfg.kappa_mm), K)
+    assert np.max(np.abs(pts - Po)) <= 2e-6
+
+
+# ------------------------------------------------------------------ RANSAC, round by round
+def _follow(pp, orc, frame, cid, k, rounds=None, **over):
+    H, W = frame.depth.shape
+    dc, rc = cfg_params(cid, W, H, k, **over)
+    g = run_plain(frame, dc, rc)
+    P = g["points"].astype(np.float64)
+    valid = g["valid"] & 1
+    L = orc.valid_list(valid)
+    dbg = g["dbg"]
+    assert dbg["n_valid"][0] == len(L)
+    assert np.array_equal(dbg["valid_list"][:len(L)], L)
+    prm = orc.RansacParams(rc.hyps, rc.max_planes, rc.min_inliers, rc.thresh_m, rc.seed, rc.frame_id)
+    labels = g["labels"]
+    Xall = P.reshape(3, -1)
+    pmax = float(np.max(np.linalg.norm(Xall[:, L], axis=0))) if len(L) else 0.0
+    n_rounds = rounds or rc.max_planes
+    ran = 0
+    for r in range(n_rounds):
+        info = dbg["round_info"][r]
+        if info[3] < 0:
+            assert r == g["n_planes"]  # rounds stop right after the last emitted plane
+            break
+        ran += 1
+        assigned = ((labels >= 0) & (labels < r)).astype(np.uint8)
+        tr_g = dbg["triples"][r]
+        hy_g = dbg["hyps"][r].astype(np.float64)
+        ct_g = dbg["counts"][r]
+        # hypotheses: triples bit-exact; planes close
+        tr_o, pl_o, hv_o = orc.hypotheses(P, L, assigned, prm, r)
+        gave_up = (tr_o < 0).any(axis=1)
+        assert np.array_equal(tr_g[~gave_up], tr_o[~gave_up])
+        assert np.all(tr_g[gave_up] == -1)
+        hv_g = ~np.isnan(hy_g[:, 3])
+        assert np.array_equal(hv_g, hv_o > 0)
+        eps = hyp_eps(pl_o, tr_o, L, P, pmax)
+        # FP32 planes: the residual they imply anywhere in the frame stays inside the band
+        # (a plane through the camera centre, d ~ 0, may come out with either sign)
+        dn = np.minimum(np.linalg.norm(hy_g[:, :3] - pl_o[:, :3], axis=1) * pmax + np.abs(hy_g[:, 3] - pl_o[:, 3]),
+                        np.linalg.norm(hy_g[:, :3] + pl_o[:, :3], axis=1) * pmax + np.abs(hy_g[:, 3] + pl_o[:, 3]))
+        assert np.all(dn[hv_g] <= eps[hv_g])
+        res = orc.ransac_round(P, L, assigned, prm, r, eps)
+        assert res.jstar >= 0 or info[3] == 1
+        if info[3] == 1:
+            assert not hv_o.any()
+            break
+        # counts inside the near-threshold band of each hypothesis
+        lo, hi = res.counts_lo, res.counts_hi
+        bad = (ct_g < lo) | (ct_g > hi)
+        assert not bad.any(), (r, np.flatnonzero(bad)[:5])
+        js = int(info[0])
+        assert js == int(np.flatnonzero(hv_g & (ct_g == ct_g[hv_g].max()))[0])
+        assert hi[js] >= lo[hv_o > 0].max()  # a legitimate winner
+        # S = inliers of j*: consistent with its count, and with the oracle's set outside the band
+        S = (dbg["masks"][r].reshape(H, W) & 1) > 0
+        assert S.sum() == ct_g[js] == info[1]
+        Xr = Xall[:, L]
+        d_or = np.abs(pl_o[js, :3] @ Xr + pl_o[js, 3])
+        near = np.abs(d_or - rc.thresh_m) <= eps[js]
+        S_or = np.zeros(H * W, bool)
+        S_or[L] = (d_or < rc.thresh_m) & (assigned.reshape(-1)[L] == 0)
+        diff = (S.reshape(-1) != S_or)
+        nearpx = np.zeros(H * W, bool)
+        nearpx[L] = near
+        assert not (diff & ~nearpx).any()
+        # refit: the GPU plane is the least-squares plane of its own S
+        pl_ref, ce_ref = orc.refit(P, np.flatnonzero(S.reshape(-1)).astype(np.int32))
+        Fm = (dbg["masks"][r].reshape(H, W) & 2) > 0
+        if info[3] == 0:
+            gp = g["planes"][r]
+            gpl = np.append(gp["n"], gp["d"])
+            assert np.max(np.abs(gpl - pl_ref)) <= 1e-9 * max(1.0, abs(pl_ref[3]))
+            assert np.max(np.abs(gp["centroid"] - ce_ref)) <= 1e-9
+            assert gp["hyp_index"] == js and gp["inliers"] == Fm.sum() == info[2]
+            # F: the refit plane's inliers (compensated FP32) agree with float64 away from t
+            dist = np.abs(gpl[:3] @ Xr + gpl[3])
+            F64 = np.zeros(H * W, bool)
+            F64[L] = (dist < rc.thresh_m) & (assigned.reshape(-1)[L] == 0)
+            nearF = np.zeros(H * W, bool)
+            nearF[L] = np.abs(dist - rc.thresh_m) <= 1e-7
+            assert not ((Fm.reshape(-1) != F64) & ~nearF).any()
+            assert np.array_equal(labels == r, Fm)
+            # and with the oracle's own round when both picked the same hypothesis
+            if res.jstar == js and not diff.any():
+                assert np.max(np.abs(gpl - res.plane)) <= 1e-6 * max(1.0, res.plane[3])
+                dF = Fm.reshape(-1) != res.fmask.reshape(-1)
+                dist_or = np.zeros(H * W)
+                dist_or[L] = np.abs(res.plane[:3] @ Xr + res.plane[3])
+                assert not (dF & (np.abs(dist_or - rc.thresh_m) > 1e-6)).any()
+        else:
+            assert info[2] < rc.min_inliers and g["n_planes"] == r
+            assert not (labels == r).any()
+            break
+    log(f"  followed {ran} rounds, {g['n_planes']} planes")
+    return g
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_ransac_follow_mode_160x120(pp, orc, k):
+    log(f"ransac follow mode cfg=1 k={k}")
+    f = scenes.make_frame(1, k)
+    g = _follow(pp, orc, f, 1, k)
+    assert g["n_planes"] >= 3
+
+
+def test_ransac_follow_mode_640x480(pp, orc):
+    log("ransac follow mode cfg=2 k=0")
+    f = scenes.make_frame(2, 0)
+    g = _follow(pp, orc, f, 2, 0)
+    assert g["n_planes"] >= 6
+
+
+def test_ransac_follow_mode_spiral_mixed_size(pp, orc):
+    log("ransac follow mode cfg=3 k=0 (424x240)")
+    f = scenes.make_frame(3, 0)
+    _follow(pp, orc, f, 3, 0, hyps=512)
+
+
+def test_ransac_few_hypotheses_and_one_plane(pp, orc):
+    f = scenes.make_frame(1, 3)
+    _follow(pp, orc, f, 1, 3, hyps=1, max_planes=1)
+    _follow(pp, orc, f, 1, 3, hyps=37, max_planes=3)
+
+
+def test_min_inliers_above_every_plane_emits_nothing(pp, orc):
+    f = scenes.make_frame(1, 0)
+    g = _follow(pp, orc, f, 1, 0, min_inliers=10 ** 6)
+    assert g["n_planes"] == 0 and np.all(g["labels"] == -1)
+    assert g["dbg"]["round_info"][0][3] == 2
+
+
+# ------------------------------------------------------------------ free-running against the oracle pipeline
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_full_pipeline_matches_the_oracle_pipeline(pp, orc, k):
+    log(f"free-running pipeline cfg=1 k={k}")
+    f = scenes.make_frame(1, k)
+    H, W = f.depth.shape
+    dc, rc = cfg_params(1, W, H, k)
+    g = run_plain(f, dc, rc)
+    prm = orc.RansacParams(rc.hyps, rc.max_planes, rc.min_inliers, rc.thresh_m, rc.seed, rc.frame_id)
+    o = orc.pipeline(f.depth, f.K, dc.iters, dc.lam, dc.kappa_mm, prm)
+    n = min(g["n_planes"], o.ransac.n_planes)
+    same = 0
+    for r in range(n):
+        gp = np.append(g["planes"][r]["n"], g["planes"][r]["d"])
+        if np.max(np.abs(gp - o.ransac.planes[r])) <= 1e-6 * max(1.0, o.ransac.planes[r][3]):
+            same += 1
+        else:
+            break
+    agree = (g["labels"] == o.ransac.labels).mean()
+    log(f"  planes gpu={g['n_planes']} oracle={o.ransac.n_planes} identical-prefix={same} label agreement={agree:.6f}")
+    assert g["n_planes"] == o.ransac.n_planes and same == n
+    assert agree >= 0.9999
+
+
+# ------------------------------------------------------------------ brute force over triples
+def test_scored_triples_match_brute_force(pp, orc):
+    """Every triple of a 9x8 crop scored against its points: counts within the
+    near-threshold band of the float64 counts, planes close."""
+    import itertools
+    import torch
+    f = scenes.make_frame(1, 0)
+    crop = f.depth[70:78, 60:69].copy()
+    K = scenes.Intrinsics(f.K.fx, f.K.fy, f.K.cx - 60, f.K.cy - 70)
+    dmm = pp.diffuse(to_dev(crop), 0)
+    pts, nrm, valid = pp.normals(dmm, (K.fx, K.fy, K.cx, K.cy))
+    P = pts.cpu().numpy().astype(np.float64)
+    v = valid.cpu().numpy() & 1
+    L = orc.valid_list(v)
+    trip = np.array(list(itertools.combinations(range(len(L)), 3)), dtype=np.int32)
+    offs = L[trip].astype(np.int32)
+    planes, counts = pp.score_triples(pts, valid, torch.from_numpy(offs).cuda(), 0.01)
+    planes, counts = planes.cpu().numpy().astype(np.float64), counts.cpu().numpy()
+    X = P.reshape(3, -1)[:, L]
+    e1 = X[:, trip[:, 1]] - X[:, trip[:, 0]]
+    e2 = X[:, trip[:, 2]] - X[:, trip[:, 0]]
+    m = np.cross(e1.T, e2.T)
+    mn = np.linalg.norm(m, axis=1)
+    ok = mn > 1e-3 * np.linalg.norm(e1, axis=0) * np.linalg.norm(e2, axis=0)
+    nrm64 = m / np.where(mn > 0, mn, 1)[:, None]
+    d64 = -np.einsum("ij,ji->i", nrm64, X[:, trip[:, 0]])
+    flip = d64 < 0
+    nrm64[flip] *= -1
+    d64[flip] *= -1
+    pl64 = np.column_stack([nrm64, d64])
+    hv = ~np.isnan(planes[:, 3])
+    assert np.array_equal(hv, ok)
+    # triples on one image row span a plane through the camera centre (d ~ 0): sign is free
+    dpl = np.minimum(np.abs(planes - pl64).max(1), np.abs(planes + pl64).max(1))
+    assert np.max(dpl[ok]) <= 1e-4
+    pmax = float(np.max(np.linalg.norm(X, axis=0)))
+    eps = hyp_eps(pl64, trip, np.arange(len(L)), X.reshape(3, 1, -1), pmax)
+    c, lo, hi, _ = orc.score(X.reshape(3, 1, -1).copy(), np.arange(len(L), dtype=np.int32),
+                             np.zeros((1, len(L)), np.uint8), pl64, ok.astype(np.uint8), 0.01, eps)
+    assert np.all((counts >= lo) & (counts <= hi))
+    log(f"  {len(trip)} triples, {int((counts != c).sum())} differ from float64 within the band")
+
+
+# ------------------------------------------------------------------ equivalence of the execution forms
+def _batch_frames(pp, frames_spec):
+    outs = []
+    for cid, k in frames_spec:
+        f = scenes.make_frame(cid, k)
+        H, W = f.depth.shape
+        dc, rc = cfg_params(cid, W, H, k)
+        outs.append((f, pp.make_outputs(to_dev(f.depth), (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc)))
+    return outs
+
+
+def _snapshot(fo):
+    return [t.cpu().numpy().copy() for t in (fo.depth_mm, fo.points, fo.normals, fo.valid, fo.planes, fo.n_planes,
+                                              fo.labels)]
+
+
+def test_batch_graph_eager_and_plain_are_bitwise_equal(pp):
+    import torch
+    spec = [(1, 0), (2, 0), (3, 0), (1, 1), (3, 2), (2, 1)]
+    frames = _batch_frames(pp, spec)
+    for _, fo in frames:
+        pp.run_frame(fo)
+    torch.cuda.synchronize()
+    plain = [_snapshot(fo) for _, fo in frames]
+    for mode in ("eager", "graph", "graph"):
+        for _, fo in frames:
+            for t in (fo.depth_mm, fo.points, fo.normals, fo.planes, fo.labels):
+                t.zero_()
+        pp.batch_run([fo for _, fo in frames], graph=(mode == "graph"))
+        torch.cuda.synchronize()
+        for (f, fo), ref in zip(frames, plain):
+            got = _snapshot(fo)
+            for a, b in zip(got, ref):
+                assert np.array_equal(a, b), mode
+    log(f"  batch of {len(spec)} ragged frames: plain == eager == graph (x2)")
+
+
+def test_shuffled_batch_and_repeats_are_deterministic(pp):
+    import torch
+    spec = [(3, 1), (1, 2), (2, 2), (1, 3)]
+    frames = _batch_frames(pp, spec)
+    pp.batch_run([fo for _, fo in frames])
+    torch.cuda.synchronize()
+    ref = [_snapshot(fo) for _, fo in frames]
+    order = [2, 0, 3, 1]
+    pp.batch_run([frames[i][1] for i in order])
+    pp.batch_run([frames[i][1] for i in order])
+    torch.cuda.synchronize()
+    for (f, fo), r in zip(frames, ref):
+        for a, b in zip(_snapshot(fo), r):
+            assert np.array_equal(a, b)
+
+
+def test_scoring_tunings_give_identical_planes(pp):
+    import torch
+    f = scenes.make_frame(2, 2)
+    H, W = f.depth.shape
+    dc, rc = cfg_params(2, W, H, 2)
+    ref = None
+    ctx = pp.Context(0)
+    for hb in (1, 2, 3):
+        for ch in (1, 4):
+            ctx.set_tuning(score_hb=hb, score_chunk=ch)
+            fo = pp.make_outputs(to_dev(f.depth), (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc)
+            pp.run_frame(fo, ctx=ctx)
+            torch.cuda.synchronize()
+            snap = _snapshot(fo)
+            if ref is None:
+                ref = snap
+            for a, b in zip(snap, ref):
+                assert np.array_equal(a, b)
+    ctx.close()
+
+
+# ------------------------------------------------------------------ edge cases
+def test_empty_and_tiny_frames(pp):
+    import torch
+    dc_args = dict(iters=5)
+    for shape, fill in [((120, 160), 0), ((3, 3), 1500), ((3, 5), 0), ((61, 97), None)]:
+        if fill is None:
+            img = scenes.make_frame(1, 0).depth[:61, :97].copy()
+        else:
+            img = np.full(shape, fill, np.uint16)
+        H, W = img.shape
+        dc, rc = cfg_params(1, W, H, 0, **dc_args)
+        fo = pp.make_outputs(to_dev(img), (100.0, 100.0, W / 2, H / 2), dc, rc)
+        pp.run_frame(fo)
+        torch.cuda.synchronize()
+        n = int(fo.n_planes.cpu().item())
+        lab = fo.labels.cpu().numpy()
+        if fill == 0:
+            assert n == 0 and np.all(lab == -1)
+        assert np.all(lab[img == 0] == -1)
+        log(f"  {shape} fill={fill}: {n} planes")
+
+
+def test_invalid_arguments_are_rejected_before_launch(pp):
+    import torch
+    from paper_2411_01919_amd import _native as N
+    d = torch.zeros((10, 10), dtype=torch.int16, device="cuda")
+    with pytest.raises(pp.PPError) as e:
+        pp.diffuse(d, 5, lam=0.3)
+    assert e.value.status == N.PP_E_INVAL
+    with pytest.raises(pp.PPError) as e:
+        pp.diffuse(d[:2, :2].contiguous(), 5)
+    assert e.value.status == N.PP_E_INVAL
+    pts = torch.zeros((3, 10, 10), device="cuda")
+    valid = torch.zeros((10, 10), dtype=torch.uint8, device="cuda")
+    with pytest.raises(pp.PPError) as e:
+        pp.ransac_planes(pts, valid, pp.RansacConfig(max_planes=200))
+    assert e.value.status == N.PP_E_INVAL
+    # the context is still usable afterwards
+    out = pp.diffuse(d, 1)
+    torch.cuda.synchronize()
+    assert float(out.abs().sum().item()) == 0.0
