@@ -124,27 +124,37 @@ def main():
     ctx = pp.default_context(0)
     stream = torch.cuda.current_stream()
 
-    # ---------------------------------------------------------------- batched (graph) path
-    ctx.set_stage_timing(True)
+    # ---------------------------------------------------------------- batched (graph) path: the value
     for i in range(args.warmup):
         pp.batch_run(outs, graph=True, ctx=ctx)
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
-    score_ms, score_launches = 0.0, 0
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         pp.batch_run(outs, graph=True, ctx=ctx)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    batched_fps = args.batch * args.steps / (t1 - t0)
+    log(f"batched (graph): {ms_per_step:.2f} ms/step, {batched_fps:.1f} frames/s")
+
+    # ---------------------------------------------------------------- same batches launched eagerly, with HIP
+    # events around every scoring launch on the launching stream (the roofline's kernel time)
+    ctx.set_stage_timing(True)
+    pp.batch_run(outs, graph=False, ctx=ctx)
+    torch.cuda.synchronize()
+    score_ms, score_launches = 0.0, 0
+    t2 = time.perf_counter()
+    for i in range(args.steps):
+        pp.batch_run(outs, graph=False, ctx=ctx)
         stream.synchronize()
         ms, n = ctx.stage_time()
         score_ms += ms
         score_launches += n
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    t3 = time.perf_counter()
     ctx.set_stage_timing(False)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    batched_fps = args.batch * args.steps / (t1 - t0)
-    log(f"batched: {ms_per_step:.2f} ms/step, {batched_fps:.1f} frames/s")
+    eager_fps = args.batch * args.steps / (t3 - t2)
+    log(f"batched (eager, timed): {eager_fps:.1f} frames/s, scoring {score_ms / args.steps:.3f} ms/step")
 
     # algorithmic work of one step (from the step's own outputs)
     res_step, planes_tot = 0, 0
@@ -204,6 +214,7 @@ def main():
         "config": {"workload": "640x480 straight staircase, 20 diffusion iterations, sequential RANSAC up to "
                                "12 planes x 1024 hypotheses, t = 10 mm",
                    "batch_frames": args.batch, "form": "batched, one HIP graph replay per step",
+                   "eager_batched_frames_per_s": round(eager_fps, 2),
                    "mpixel_per_s": round(batched_fps * W * H / 1e6, 2),
                    "planes_per_frame": round(planes_tot / len(outs), 2)},
         "plain": plain,

@@ -57,7 +57,8 @@ enum {
     PP_E_NODEVICE = -5,     /* no usable GPU */
     PP_E_CLOSED = -6,       /* server/stream closed or destroyed */
     PP_E_UNSUPPORTED = -7,  /* valid request outside what this build implements */
-    PP_E_TIMEOUT = -8       /* pp_poll waited timeout_us without a result */
+    PP_E_TIMEOUT = -8,      /* reserved */
+    PP_E_AGAIN = -9         /* pp_submit: the stream's staging is full; poll results, then retry */
 };
 
 typedef struct pp_ctx pp_ctx;
@@ -72,8 +73,17 @@ enum { PP_EDGE_EXP = 0, PP_EDGE_RATIONAL = 1 };
 typedef struct { int32_t iters; float lambda; float kappa_mm; int32_t edge_stop; } pp_diffuse_params;
 
 /* Inlier scoring arithmetic.  Every form decides |n.p + d| < t exactly as the
- * canonical FP32 residual fmaf(nx,x, fmaf(ny,y, fmaf(nz,z,d))) does: the fast
- * forms recheck residuals within recheck_band_m of t with that formula. */
+ * canonical FP32 residual fmaf(nx,x, fmaf(ny,y, fmaf(nz,z,d))) does, so all
+ * forms return identical counts, planes and labels:
+ *  PP_SCORE_FP32      the canonical formula on the vector ALUs;
+ *  PP_SCORE_MFMA_F32  the contraction on FP32 matrix cores; residuals within
+ *                     max(recheck_band_m, 16 * 2^-24 * (max|p|_1 + |d|)) of t
+ *                     are recomputed canonically;
+ *  PP_SCORE_BF16/FP16 tile-centred points and normals in BF16/FP16 on the
+ *                     matrix cores with FP32 accumulation; residuals within
+ *                     recheck_band_m of t, and every point whose bound on the
+ *                     low-precision error exceeds it, are recomputed
+ *                     canonically (recheck_band_m = 0.002 is the 2 mm form). */
 enum { PP_SCORE_FP32 = 0, PP_SCORE_MFMA_F32 = 1, PP_SCORE_BF16 = 2, PP_SCORE_FP16 = 3 };
 
 /* Alg. 2 "RANSAC parameters".  Hypotheses draw from Philox4x64-10 keyed by
@@ -193,7 +203,8 @@ typedef struct {
  * makes no HIP call.  PP_OK or PP_E_INVAL. */
 pp_status pp_validate_job(const pp_frame_job* job);
 
-/* A ragged batch of frames (any mix of sizes and parameters) run together:
+/* A ragged batch of frames (any mix of sizes and parameters, one scoring
+ * precision per batch) run together:
  * each stage is one launch over all frames, and the whole sequence is
  * captured once per batch layout into a HIP graph and replayed.  Results are
  * bitwise identical to running each frame alone.  jobs is a host array. */
@@ -219,12 +230,77 @@ pp_status pp_get_tuning(const pp_ctx* ctx, pp_tuning* out);
 /* Number of choices per knob (for the autotuner's search space). */
 pp_status pp_tuning_space(int32_t* n_tiles, int32_t* max_t, int32_t* n_hb, int32_t* n_chunk);
 
+/* ---------------------------------------------------------------- serving */
+/* A server runs frames from several camera streams as they arrive.  A
+ * scheduler thread admits queued frames in arrival order whenever their
+ * device block (inputs, outputs and scratch) fits the HBM budget, groups the
+ * admitted frames into ragged batches of up to max_batch, and launches each
+ * batch (all four steps, pp_batch_run) on one of `lanes` HIP streams, so
+ * frames arriving while others run are admitted as memory frees up and
+ * overlap with them on the device.  A frame's results do not depend on what
+ * it was batched with.  pp_submit and pp_poll are thread-safe. */
+typedef struct pp_server pp_server;
+
+typedef struct {
+    int32_t device;
+    uint64_t hbm_budget_bytes;  /* arena for frames in flight, allocated once at create */
+    int32_t max_batch;          /* frames per launch, 1..1024 */
+    int32_t lanes;              /* batches in flight at once, 1..4 */
+    int32_t staging_frames;     /* pinned host slots per stream (queued + unpolled frames), 1..1024 */
+    int32_t use_graphs;         /* 1: replay cached HIP graphs per batch layout; 0: eager launches */
+    int32_t dry_run_us;         /* > 0: no GPU is touched; each batch "completes" after this many us
+                                   with no planes -- exercises admission and scheduling only */
+} pp_server_cfg;
+
+/* Caller-owned host buffers filled by pp_poll. */
+typedef struct {
+    pp_plane* planes;     /* [max_planes] of the frame's stream (NULL: skip) */
+    int32_t* n_planes;    /* [1] (NULL: skip) */
+    int8_t* labels;       /* [height*width] (NULL: skip) */
+    int32_t stream_id;
+    uint64_t frame_id;
+    double latency_us;    /* pp_submit -> results on the host */
+} pp_result;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, cancelled, launches;
+    double mean_batch;            /* frames per launch */
+    double p50_us, p99_us, max_us;/* latency of completed frames (last 65536) */
+    uint64_t hbm_in_use, hbm_peak;/* arena bytes */
+    int32_t queued, in_flight;
+} pp_server_stats;
+
+/* PP_E_INVAL for bad cfg, PP_E_NODEVICE without a GPU (unless dry_run_us > 0). */
+pp_status pp_server_create(const pp_server_cfg* cfg, pp_server** out);
+/* Stops the scheduler, waits for batches on the device, frees everything. */
+pp_status pp_server_destroy(pp_server* s);
+const char* pp_server_last_error(const pp_server* s);
+/* Register camera stream stream_id (unique for the server's lifetime): frame
+ * size (pitch_px == width), intrinsics and parameters.  PP_E_BUDGET if one
+ * frame of it can never fit the budget. */
+pp_status pp_stream_open(pp_server* s, int32_t stream_id, pp_frame_desc desc, pp_intrinsics K,
+                         const pp_diffuse_params* dp, const pp_ransac_params* rp);
+/* Queued frames of the stream are cancelled (their polls return PP_E_CLOSED);
+ * launched frames complete and stay pollable. */
+pp_status pp_stream_close(pp_server* s, int32_t stream_id);
+/* Copy a host uint16 [height][width] frame into pinned staging and queue it;
+ * never blocks.  frame_id keys the frame's hypotheses.  *ticket identifies
+ * the result.  PP_E_AGAIN when the stream's staging is full. */
+pp_status pp_submit(pp_server* s, int32_t stream_id, const uint16_t* depth_host, uint64_t frame_id,
+                    uint64_t* ticket);
+/* Wait up to timeout_us (0: don't wait) for the ticket: PP_OK with the results
+ * copied into *out (the ticket is then released), PP_PENDING if not ready,
+ * PP_E_CLOSED if cancelled, PP_E_HIP if its batch failed. */
+pp_status pp_poll(pp_server* s, uint64_t ticket, pp_result* out, int32_t timeout_us);
+pp_status pp_server_stats_get(pp_server* s, pp_server_stats* out);
+
 /* ---------------------------------------------------------------- timing */
 /* Stage timing: while enabled, every launch of the inlier-scoring kernel
- * (one per RANSAC round) is bracketed by HIP events recorded on the launching
- * stream, also inside captured graphs.  pp_stage_time returns the summed
- * elapsed ms of those launches in the most recent run on ctx and their number;
- * the caller must have synchronised the stream first. */
+ * (one per RANSAC round) made by pp_ransac_planes or pp_batch_run_eager is
+ * bracketed by HIP events recorded on the launching stream (graph replays of
+ * pp_batch_run are not instrumented).  pp_stage_time returns the summed
+ * elapsed ms of those launches in the most recent instrumented run on ctx and
+ * their number; the caller must have synchronised the stream first. */
 pp_status pp_set_stage_timing(pp_ctx* ctx, int32_t enable);
 pp_status pp_stage_time(pp_ctx* ctx, float* total_ms, int32_t* launches);
 

@@ -19,7 +19,7 @@ from ._native import (PP_EDGE_EXP, PP_EDGE_RATIONAL, PP_SCORE_BF16, PP_SCORE_FP1
                       PP_SCORE_MFMA_F32, LibraryMissing)
 
 __all__ = [
-    "PPError", "Context", "RansacConfig", "DiffuseConfig", "default_context", "diffuse", "normals",
+    "PPError", "Server", "Context", "RansacConfig", "DiffuseConfig", "default_context", "diffuse", "normals",
     "ransac_planes", "ransac_planes_debug", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
     "planes_to_numpy", "PP_SCORE_FP32", "PP_SCORE_MFMA_F32", "PP_SCORE_BF16", "PP_SCORE_FP16",
 ]
@@ -328,3 +328,85 @@ def run_frame(fo: FrameOutputs, ctx: Optional[Context] = None, stream=None):
             ctx=ctx, stream=stream)
     normals(fo.depth_mm, fo.K, fo.points, fo.normals, fo.valid, ctx=ctx, stream=stream)
     ransac_planes(fo.points, fo.valid, fo.ransac, fo.planes, fo.n_planes, fo.labels, ctx=ctx, stream=stream)
+
+
+class Server:
+    """The serving runtime (pp_server_*): camera streams submit host frames,
+    results come back through poll().  dry_run_us > 0 exercises admission and
+    scheduling without touching a GPU (no planes are computed)."""
+
+    def __init__(self, hbm_budget_bytes: int = 8 << 30, max_batch: int = 32, lanes: int = 2,
+                 staging_frames: int = 64, use_graphs: bool = True, device: int = 0, dry_run_us: int = 0):
+        cfg = N.ServerCfg(int(device), int(hbm_budget_bytes), int(max_batch), int(lanes), int(staging_frames),
+                          1 if use_graphs else 0, int(dry_run_us))
+        h = N.c_vp()
+        s = N.lib().pp_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if s != N.PP_OK:
+            raise PPError(s, "pp_server_create")
+        self.h = h
+        self.streams = {}
+
+    def close(self):
+        if self.h:
+            N.lib().pp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, s):
+        if s != N.PP_OK:
+            raise PPError(s, N.lib().pp_server_last_error(self.h).decode())
+
+    def open_stream(self, stream_id: int, W: int, H: int, K, diffuse_cfg: DiffuseConfig, ransac_cfg: RansacConfig):
+        dp, rp = diffuse_cfg.c(), ransac_cfg.c()
+        self._check(N.lib().pp_stream_open(self.h, int(stream_id), _desc(H, W), N.Intrinsics(*[float(x) for x in K]),
+                                           ctypes.byref(dp), ctypes.byref(rp)))
+        self.streams[stream_id] = (W, H, ransac_cfg.max_planes)
+
+    def close_stream(self, stream_id: int):
+        self._check(N.lib().pp_stream_close(self.h, int(stream_id)))
+
+    def submit(self, stream_id: int, depth_u16, frame_id: int) -> int:
+        """Queue a host uint16 [H][W] frame; returns a ticket.  Raises PPError
+        (status PP_E_AGAIN) when the stream's staging is full."""
+        import numpy as np
+        a = np.ascontiguousarray(depth_u16, dtype=np.uint16)
+        W, H, _ = self.streams[stream_id]
+        if a.shape != (H, W):
+            raise ValueError(f"frame shape {a.shape} != {(H, W)}")
+        t = N.c_u64()
+        self._check(N.lib().pp_submit(self.h, int(stream_id), a.ctypes.data, int(frame_id), ctypes.byref(t)))
+        return t.value
+
+    def try_submit(self, stream_id: int, depth_u16, frame_id: int):
+        """submit() that returns None instead of raising when staging is full."""
+        try:
+            return self.submit(stream_id, depth_u16, frame_id)
+        except PPError as e:
+            if e.status == N.PP_E_AGAIN:
+                return None
+            raise
+
+    def poll(self, ticket: int, stream_id: int, timeout_us: int = 0, labels: bool = True):
+        """None while pending; else dict(n_planes, planes (raw bytes), labels, latency_us, frame_id)."""
+        import numpy as np
+        W, H, mp = self.streams[stream_id]
+        planes = (N.Plane * mp)()
+        n = N.c_i32()
+        lab = np.empty((H, W), dtype=np.int8) if labels else None
+        res = N.Result(ctypes.addressof(planes), ctypes.addressof(n), lab.ctypes.data if labels else None, 0, 0, 0.0)
+        s = N.lib().pp_poll(self.h, int(ticket), ctypes.byref(res), int(timeout_us))
+        if s == N.PP_PENDING:
+            return None
+        self._check(s)
+        return dict(n_planes=n.value, planes=bytes(planes), labels=lab, latency_us=res.latency_us,
+                    frame_id=res.frame_id, stream_id=res.stream_id)
+
+    def stats(self) -> dict:
+        st = N.ServerStats()
+        self._check(N.lib().pp_server_stats_get(self.h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in N.ServerStats._fields_}

@@ -16,6 +16,7 @@ c_i32, c_u64, c_f32, c_f64, c_vp = ctypes.c_int32, ctypes.c_uint64, ctypes.c_flo
 PP_OK, PP_PENDING = 0, 1
 PP_E_INVAL, PP_E_NOMEM, PP_E_BUDGET, PP_E_HIP, PP_E_NODEVICE, PP_E_CLOSED, PP_E_UNSUPPORTED, PP_E_TIMEOUT = \
     -1, -2, -3, -4, -5, -6, -7, -8
+PP_E_AGAIN = -9
 PP_EDGE_EXP, PP_EDGE_RATIONAL = 0, 1
 PP_SCORE_FP32, PP_SCORE_MFMA_F32, PP_SCORE_BF16, PP_SCORE_FP16 = 0, 1, 2, 3
 
@@ -56,6 +57,22 @@ class Tuning(ctypes.Structure):
     _fields_ = [("diffuse_tile", c_i32), ("diffuse_t", c_i32), ("score_hb", c_i32), ("score_chunk", c_i32)]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("device", c_i32), ("hbm_budget_bytes", c_u64), ("max_batch", c_i32), ("lanes", c_i32),
+                ("staging_frames", c_i32), ("use_graphs", c_i32), ("dry_run_us", c_i32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("planes", c_vp), ("n_planes", c_vp), ("labels", c_vp), ("stream_id", c_i32),
+                ("frame_id", c_u64), ("latency_us", c_f64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_u64), ("completed", c_u64), ("rejected", c_u64), ("cancelled", c_u64),
+                ("launches", c_u64), ("mean_batch", c_f64), ("p50_us", c_f64), ("p99_us", c_f64), ("max_us", c_f64),
+                ("hbm_in_use", c_u64), ("hbm_peak", c_u64), ("queued", c_i32), ("in_flight", c_i32)]
+
+
 # name -> (restype, argtypes); exactly the entry points pp.h declares
 SIGNATURES = {
     "pp_ctx_create": (c_i32, [c_i32, ctypes.POINTER(c_vp)]),
@@ -75,6 +92,15 @@ SIGNATURES = {
     "pp_get_tuning": (c_i32, [c_vp, ctypes.POINTER(Tuning)]),
     "pp_tuning_space": (c_i32, [ctypes.POINTER(c_i32)] * 4),
     "pp_set_stage_timing": (c_i32, [c_vp, c_i32]),
+    "pp_server_create": (c_i32, [ctypes.POINTER(ServerCfg), ctypes.POINTER(c_vp)]),
+    "pp_server_destroy": (c_i32, [c_vp]),
+    "pp_server_last_error": (ctypes.c_char_p, [c_vp]),
+    "pp_stream_open": (c_i32, [c_vp, c_i32, FrameDesc, Intrinsics, ctypes.POINTER(DiffuseParams),
+                               ctypes.POINTER(RansacParams)]),
+    "pp_stream_close": (c_i32, [c_vp, c_i32]),
+    "pp_submit": (c_i32, [c_vp, c_i32, c_vp, c_u64, ctypes.POINTER(c_u64)]),
+    "pp_poll": (c_i32, [c_vp, c_u64, ctypes.POINTER(Result), c_i32]),
+    "pp_server_stats_get": (c_i32, [c_vp, ctypes.POINTER(ServerStats)]),
     "pp_stage_time": (c_i32, [c_vp, ctypes.POINTER(c_f32), ctypes.POINTER(c_i32)]),
 }
 

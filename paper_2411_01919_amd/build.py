@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpp.so")
-SOURCES = ["csrc/pp_kernels.hip", "csrc/pp_api.hip"]
+SOURCES = ["csrc/pp_kernels.hip", "csrc/pp_api.hip", "csrc/pp_server.hip"]
 ARCH = os.environ.get("PP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -20,6 +20,8 @@ FLAGS = [
     "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # matrix-core results straight into VGPRs (no accumulation-register round trip)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

@@ -25,6 +25,7 @@ struct Slot {
     size_t bytes = 0;
     size_t px_cap = 0;
     int hyp_cap = 0;
+    bool external = false;  // memory owned by the caller (the server's arena)
 };
 
 struct GraphEntry {
@@ -133,6 +134,7 @@ pp_status ensure_slot(pp_ctx* c, int i, size_t px, int hyps) {
     if ((int)c->slots.size() <= i) c->slots.resize(i + 1);
     Slot& s = c->slots[i];
     if (s.base && s.px_cap >= px && s.hyp_cap >= hyps) return PP_OK;
+    if (s.external) return fail(c, PP_E_INVAL, "external scratch too small for the frame");
     const size_t npx = std::max(px, s.px_cap);
     const int nh = std::max(hyps, s.hyp_cap);
     Layout l = slot_layout(npx, nh);
@@ -277,7 +279,7 @@ pp_status pp_ctx_destroy(pp_ctx* c) {
     for (auto& kv : c->graphs)
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     for (auto& s : c->slots)
-        if (s.base) (void)hipFree(s.base);
+        if (s.base && !s.external) (void)hipFree(s.base);
     if (c->plain_tab) (void)hipFree(c->plain_tab);
     if (c->batch_tab) (void)hipFree(c->batch_tab);
     if (c->debug_scratch) (void)hipFree(c->debug_scratch);
@@ -347,7 +349,6 @@ pp_status pp_set_stage_timing(pp_ctx* c, int32_t enable) {
     if (enable && !c->score_ev[0][0])
         for (int r = 0; r < ppk::kMaxRounds; ++r)
             for (int k = 0; k < 2; ++k) HIPCHK(c, hipEventCreate(&c->score_ev[r][k]));
-    if (c->timing != (enable != 0)) c->graphs.clear();  // captured graphs differ by the event nodes
     c->timing = enable != 0;
     c->timed_rounds = 0;
     return PP_OK;
@@ -414,7 +415,6 @@ static pp_status ransac_common(pp_ctx* c, const float* points_dev, const uint8_t
                                const pp_ransac_params* p, pp_plane* planes_dev, int32_t* n_planes_dev,
                                int8_t* labels_dev, const pp_ransac_debug* dbg, void* stream) {
     pp_status s;
-    if (p->precision != PP_SCORE_FP32) return fail(c, PP_E_UNSUPPORTED, "only PP_SCORE_FP32 scoring is built");
     if ((s = set_device(c)) != PP_OK) return s;
     const size_t px = (size_t)desc.width * desc.height;
     if ((s = ensure_slot(c, 0, px, p->hyps_per_plane)) != PP_OK) return s;
@@ -473,7 +473,6 @@ pp_status pp_debug_score_triples(pp_ctx* c, const float* points_dev, const uint8
         n > (1 << 24) || !(thresh_m > 0.f) || precision < PP_SCORE_FP32 || precision > PP_SCORE_FP16 ||
         !(recheck_band_m >= 0.f))
         return fail(c, PP_E_INVAL, "pp_debug_score_triples: bad argument");
-    if (precision != PP_SCORE_FP32) return fail(c, PP_E_UNSUPPORTED, "only PP_SCORE_FP32 scoring is built");
     if ((s = set_device(c)) != PP_OK) return s;
     const size_t px = (size_t)desc.width * desc.height;
     if ((s = ensure_slot(c, 0, px, 1)) != PP_OK) return s;
@@ -520,12 +519,11 @@ namespace {
 
 bool job_ok(const pp_frame_job& j) {
     return j.depth && j.depth_mm && j.points && j.normals && j.valid && j.planes && j.n_planes && j.labels &&
-           desc_ok(j.desc) && intrinsics_ok(j.K) && diffuse_params_ok(&j.diffuse) && ransac_params_ok(&j.ransac) &&
-           j.ransac.precision == PP_SCORE_FP32;
+           desc_ok(j.desc) && intrinsics_ok(j.K) && diffuse_params_ok(&j.diffuse) && ransac_params_ok(&j.ransac);
 }
 
 struct BatchPlan {
-    int nf = 0, maxW = 0, maxH = 0, max_px = 0, max_hyps = 0, max_rounds = 0;
+    int nf = 0, maxW = 0, maxH = 0, max_px = 0, max_hyps = 0, max_rounds = 0, precision = 0;
     std::vector<int> order;                        // table position -> job index
     std::vector<std::pair<int, int>> iter_groups;  // (first table position, count) with equal iterations
     std::vector<int> group_iters;
@@ -535,6 +533,7 @@ struct BatchPlan {
 BatchPlan plan_batch(const pp_frame_job* jobs, int n, const ppk::Tuning& tu) {
     BatchPlan b;
     b.nf = n;
+    b.precision = jobs[0].ransac.precision;
     b.order.resize(n);
     for (int i = 0; i < n; ++i) b.order[i] = i;
     std::stable_sort(b.order.begin(), b.order.end(),
@@ -553,8 +552,8 @@ BatchPlan plan_batch(const pp_frame_job* jobs, int n, const ppk::Tuning& tu) {
         b.iter_groups.back().second++;
     }
     char buf[256];
-    snprintf(buf, sizeof buf, "n%d W%d H%d px%d h%d r%d t%d.%d.%d.%d", n, b.maxW, b.maxH, b.max_px, b.max_hyps,
-             b.max_rounds, tu.diffuse_tile, tu.diffuse_t, tu.score_hb, tu.score_chunk);
+    snprintf(buf, sizeof buf, "n%d W%d H%d px%d h%d r%d p%d t%d.%d.%d.%d", n, b.maxW, b.maxH, b.max_px, b.max_hyps,
+             b.max_rounds, b.precision, tu.diffuse_tile, tu.diffuse_t, tu.score_hb, tu.score_chunk);
     b.key = buf;
     for (size_t g = 0; g < b.iter_groups.size(); ++g) {
         snprintf(buf, sizeof buf, " g%d:%d:%d", b.iter_groups[g].first, b.iter_groups[g].second, b.group_iters[g]);
@@ -563,16 +562,17 @@ BatchPlan plan_batch(const pp_frame_job* jobs, int n, const ppk::Tuning& tu) {
     return b;
 }
 
-pp_status enqueue_batch(pp_ctx* c, const BatchPlan& b, hipStream_t st) {
+pp_status enqueue_batch(pp_ctx* c, const BatchPlan& b, hipStream_t st, bool capturing) {
     for (size_t g = 0; g < b.iter_groups.size(); ++g)
         HIPCHK(c, ppk::launch_diffuse(c->batch_tab + b.iter_groups[g].first, b.iter_groups[g].second, b.maxW, b.maxH,
                                       b.group_iters[g], c->tuning, st));
     HIPCHK(c, ppk::launch_normals(c->batch_tab, b.nf, b.maxW, b.maxH, st));
     HIPCHK(c, ppk::launch_valid_list(c->batch_tab, b.nf, b.max_px, st));
+    const bool timed = c->timing && !capturing;
     for (int r = 0; r < b.max_rounds; ++r)
-        HIPCHK(c, ppk::launch_round(c->batch_tab, b.nf, r, b.max_px, b.max_hyps, PP_SCORE_FP32, c->tuning, st,
-                                    c->timing ? c->score_ev[r][0] : nullptr, c->timing ? c->score_ev[r][1] : nullptr));
-    if (c->timing) c->timed_rounds = b.max_rounds;
+        HIPCHK(c, ppk::launch_round(c->batch_tab, b.nf, r, b.max_px, b.max_hyps, b.precision, c->tuning, st,
+                                    timed ? c->score_ev[r][0] : nullptr, timed ? c->score_ev[r][1] : nullptr));
+    if (timed) c->timed_rounds = b.max_rounds;
     return PP_OK;
 }
 
@@ -625,22 +625,42 @@ pp_status upload_batch_table(pp_ctx* c, const pp_frame_job* jobs, const BatchPla
     return PP_OK;
 }
 
-pp_status batch_run(pp_ctx* c, int32_t n, const pp_frame_job* jobs, void* stream, bool use_graph) {
+pp_status batch_run(pp_ctx* c, int32_t n, const pp_frame_job* jobs, void* stream, bool use_graph,
+                    void* const* ext_scratch = nullptr) {
     pp_status s = check_ctx(c);
     if (s != PP_OK) return s;
     if (n < 1 || n > 65535 || !jobs) return fail(c, PP_E_INVAL, "pp_batch_run: bad frame count");
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         if (!job_ok(jobs[i])) return fail(c, PP_E_INVAL, "pp_batch_run: bad job " + std::to_string(i));
+        if (jobs[i].ransac.precision != jobs[0].ransac.precision)
+            return fail(c, PP_E_INVAL, "pp_batch_run: all frames of a batch must use one scoring precision");
+    }
     if ((s = set_device(c)) != PP_OK) return s;
     BatchPlan b = plan_batch(jobs, n, c->tuning);
     hipStream_t st = (hipStream_t)stream;
+    if (ext_scratch) {
+        if ((int)c->slots.size() < n + 1) c->slots.resize(n + 1);
+        for (int i = 0; i < n; ++i) {
+            const pp_frame_job& j = jobs[b.order[i]];
+            Slot& sl = c->slots[1 + i];
+            if (sl.base && !sl.external) {
+                HIPCHK(c, hipDeviceSynchronize());
+                HIPCHK(c, hipFree(sl.base));
+            }
+            sl.base = ext_scratch[b.order[i]];
+            sl.px_cap = (size_t)j.desc.width * j.desc.height;
+            sl.hyp_cap = j.ransac.hyps_per_plane;
+            sl.bytes = slot_layout(sl.px_cap, sl.hyp_cap).total;
+            sl.external = true;
+        }
+    }
     if ((s = upload_batch_table(c, jobs, b, st)) != PP_OK) return s;
-    if (!use_graph) return enqueue_batch(c, b, st);
+    if (!use_graph) return enqueue_batch(c, b, st, false);
     auto it = c->graphs.find(b.key);
     if (it == c->graphs.end()) {
         hipGraph_t g = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-        pp_status es = enqueue_batch(c, b, c->capture_stream);
+        pp_status es = enqueue_batch(c, b, c->capture_stream, true);
         hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
         if (es != PP_OK) {
             if (g) (void)hipGraphDestroy(g);
@@ -670,5 +690,24 @@ pp_status pp_batch_run(pp_ctx* c, int32_t n, const pp_frame_job* jobs, void* str
 pp_status pp_batch_run_eager(pp_ctx* c, int32_t n, const pp_frame_job* jobs, void* stream) {
     return batch_run(c, n, jobs, stream, false);
 }
+
+}  // extern "C"
+
+namespace ppk {
+
+size_t frame_scratch_bytes(int width, int height, int hyps) {
+    return slot_layout((size_t)width * height, hyps).total;
+}
+
+pp_status batch_run_external(pp_ctx* c, int n, const pp_frame_job* jobs, void* const* scratch, hipStream_t s,
+                             bool graph) {
+    return batch_run(c, n, jobs, (void*)s, graph, scratch);
+}
+
+const char* ctx_error(const pp_ctx* c) { return c->last_error.c_str(); }
+
+}  // namespace ppk
+
+extern "C" {
 
 }  // extern "C"

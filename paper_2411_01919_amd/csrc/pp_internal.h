@@ -28,7 +28,7 @@ struct RoundState {
     double plane[4];                   // refit plane of the current round
     double centroid[3];
     int32_t s_count;
-    int32_t pad;
+    uint32_t p1max_bits;               // max |x|+|y|+|z| over the frame's points (float bits)
 };
 
 // Everything a kernel needs about one frame.  Kernels read a table of these
@@ -98,5 +98,13 @@ hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_
 hipError_t launch_hyp_from_triples(const FrameDev* tab, const int32_t* triples, int n, hipStream_t s);
 hipError_t launch_score_only(const FrameDev* tab, int max_px, int n, int precision, const Tuning& tu,
                              hipStream_t s);
+
+// Library scratch one frame needs (the server carves it from its arena), and
+// a batch run whose frame slots use caller-provided scratch (scratch[i] for
+// jobs[i], each frame_scratch_bytes() long).
+size_t frame_scratch_bytes(int width, int height, int hyps);
+pp_status batch_run_external(pp_ctx* c, int n, const pp_frame_job* jobs, void* const* scratch, hipStream_t s,
+                             bool graph);
+const char* ctx_error(const pp_ctx* c);
 
 }  // namespace ppk

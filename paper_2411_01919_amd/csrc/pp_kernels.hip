@@ -324,6 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restri
     const FrameDev& f = tab[blockIdx.z];
     const int npx = f.W * f.H;
     const int nch = (npx + kValidChunk - 1) / kValidChunk;
+    if (blockIdx.x == 0 && threadIdx.x == 0) f.st->p1max_bits = 0u;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         int cnt = 0;
         for (int i = threadIdx.x; i < kValidChunk; i += kBlock) {
@@ -361,12 +362,19 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
             }
             int tot;
             const int rank = block_rank(v, sh, &tot);
+            float p1 = 0.f;
             if (v) {
                 const int k = run + rank;
+                const float4 q = make_float4(f.pts[off], f.pts[plane + off], f.pts[2 * plane + off], __int_as_float(off));
                 f.L[k] = off;
-                f.list[0][k] = make_float4(f.pts[off], f.pts[plane + off], f.pts[2 * plane + off], __int_as_float(off));
+                f.list[0][k] = q;
                 if (f.dbg.valid_list) f.dbg.valid_list[k] = off;
+                p1 = fabsf(q.x) + fabsf(q.y) + fabsf(q.z);
             }
+            // frame-wide bound on |p|_1 for the recheck bands of the matrix-core scorers
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) p1 = fmaxf(p1, __shfl_xor(p1, o));
+            if ((threadIdx.x & 63) == 0 && p1 > 0.f) atomicMax(&f.st->p1max_bits, __float_as_uint(p1));
             run += tot;
         }
         if (c == nch - 1 && threadIdx.x == 0) {
@@ -469,6 +477,163 @@ __global__ __launch_bounds__(kBlock) void k_score(const FrameDev* __restrict__ t
     for (int k = 0; k < HB; ++k) {
         const int c = wave_sum(cnt[k]);
         if ((threadIdx.x & 63) == 0 && c != 0 && h0 + k < f.hyps) atomicAdd(&f.counts[h0 + k], c);
+    }
+}
+
+
+// ------------------------------------------------------------------ matrix-core scoring
+// The same counts as k_score, with the contraction n.p + d on the matrix
+// cores.  D = A B (+ C) on v_mfma_f32_16x16x*: 16 points along M (A rows), 16
+// hypotheses along N (B columns); lane l holds D[4*(l/16) + v][l % 16], so
+// every lane counts for one hypothesis.  Each residual whose matrix-core
+// value lies within `band` of t is recomputed with the canonical FP32
+// formula, so every form returns exactly the canonical counts:
+//   PREC 1 (FP32, 16x16x4): A = (x, y, z, 1), B = (nx, ny, nz, d); the two
+//     evaluations differ by rounding only: band_j = 16 u (P1 + |d_j|),
+//     u = 2^-24, P1 = max |p|_1 of the frame.
+//   PREC 2 / 3 (BF16 / FP16, 16x16x16): points centred on the tile's first
+//     point c, A = q = p - c, B = n in the low precision (unit roundoff
+//     u_lp = 2^-8 / 2^-11), C = n.c + d in FP32.  The residual error is at
+//     most (2 u_lp + u_lp^2 + 4u) |q|_1 + 32 u P1; a row (point) whose bound
+//     exceeds the caller's band is rechecked against all its hypotheses.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef short s16x4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short f32_to_bf16_rne(float x) {
+    uint32_t b = __float_as_uint(x);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (short)(b >> 16);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_score_mfma(const FrameDev* __restrict__ tab, int r) {
+    constexpr int G = 4;  // hypothesis groups of 16 per wave
+    const FrameDev& f = tab[blockIdx.z];
+    const RoundState* st = f.st;
+    if (!st->active[r]) return;
+    const int M = st->M[r];
+    const int h0 = blockIdx.y * (16 * G);
+    if (h0 >= f.hyps || M <= 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const float t = f.thresh;
+    const float u = 5.9604645e-8f;
+    const float P1 = __uint_as_float(st->p1max_bits);
+    const float4* __restrict__ pts = f.list[r & 1];
+    const float* __restrict__ ptsf = reinterpret_cast<const float*>(pts);
+    const float qnan = __int_as_float(0x7fc00000);
+    const float4 nanh = make_float4(0.f, 0.f, 0.f, qnan);
+
+    // this lane's hypotheses (column col of each group) and their bands
+    float4 hf[G];
+    float tlo[G], thi[G];
+    float bop[G];     // FP32 B operand: component grp of the hypothesis in column col
+    s16x4_t bbf[G];   // BF16 B operand (lanes 0..15 carry n, others 0)
+    f16x4_t bh[G];    // FP16 B operand
+    int cnt[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const int j = h0 + g * 16 + col;
+        hf[g] = j < f.hyps ? f.hyp[j] : nanh;
+        const float band = PREC == PP_SCORE_MFMA_F32 ? fmaxf(f.band, 16.f * u * (P1 + fabsf(hf[g].w))) : f.band;
+        tlo[g] = t - band;
+        thi[g] = t + band;
+        bop[g] = grp == 0 ? hf[g].x : grp == 1 ? hf[g].y : grp == 2 ? hf[g].z : hf[g].w;
+        s16x4_t zb = {0, 0, 0, 0};
+        f16x4_t zh = {(_Float16)0.f, (_Float16)0.f, (_Float16)0.f, (_Float16)0.f};
+        if (grp == 0) {
+            zb[0] = f32_to_bf16_rne(hf[g].x); zb[1] = f32_to_bf16_rne(hf[g].y); zb[2] = f32_to_bf16_rne(hf[g].z);
+            zh[0] = (_Float16)hf[g].x; zh[1] = (_Float16)hf[g].y; zh[2] = (_Float16)hf[g].z;
+        }
+        bbf[g] = zb;
+        bh[g] = zh;
+        cnt[g] = 0;
+    }
+    const float ulp_lp = PREC == PP_SCORE_BF16 ? 0.00390625f : 0.00048828125f;
+    const float row_coef = 2.f * ulp_lp + ulp_lp * ulp_lp + 4.f * u;
+    const float row_fixed = 32.f * u * P1;
+
+    const int ntiles = (M + 15) >> 4;
+    const int wstride = gridDim.x * 4;
+    for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += wstride) {
+        const int base = tile << 4;
+        const int i = base + col;
+        const int ic = i < M ? i : M - 1;  // loads stay in range; rows past M become NaN
+        f32x4_t D[G];
+        uint32_t unsafe = 0;  // rows whose low-precision error bound exceeds the band
+        if (PREC == PP_SCORE_MFMA_F32) {
+            const float v = ptsf[4 * ic + grp];
+            const float a = i < M ? (grp == 3 ? 1.0f : v) : qnan;
+            const f32x4_t z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int g = 0; g < G; ++g) D[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bop[g], z, 0, 0, 0);
+        } else {
+            const float4 c = pts[base];  // tile anchor
+            const float4 p = pts[ic];
+            const float qx = i < M ? p.x - c.x : qnan, qy = p.y - c.y, qz = p.z - c.z;
+            const bool row_unsafe = i < M && !(row_coef * (fabsf(qx) + fabsf(qy) + fabsf(qz)) + row_fixed < f.band);
+            unsafe = (uint32_t)(__ballot(grp == 0 && row_unsafe) & 0xFFFFull);
+            s16x4_t abf = {0, 0, 0, 0};
+            f16x4_t ah = {(_Float16)0.f, (_Float16)0.f, (_Float16)0.f, (_Float16)0.f};
+            if (PREC == PP_SCORE_BF16) {
+                if (grp == 0) { abf[0] = f32_to_bf16_rne(qx); abf[1] = f32_to_bf16_rne(qy); abf[2] = f32_to_bf16_rne(qz); }
+            } else {
+                if (grp == 0) { ah[0] = (_Float16)qx; ah[1] = (_Float16)qy; ah[2] = (_Float16)qz; }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const float bias = fmaf(hf[g].x, c.x, fmaf(hf[g].y, c.y, fmaf(hf[g].z, c.z, hf[g].w)));
+                const f32x4_t cc = {bias, bias, bias, bias};
+                if (PREC == PP_SCORE_BF16)
+                    D[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(abf, bbf[g], cc, 0, 0, 0);
+                else
+                    D[g] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh[g], cc, 0, 0, 0);
+            }
+        }
+        // definite inliers: |d| < t - band; residuals with t - band <= |d| < t + band only raise a flag
+        uint64_t bandm = 0;  // lane mask, kept in scalar registers
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float a = fabsf(D[g][v]);
+                const bool lo = a < tlo[g];
+                cnt[g] += lo ? 1 : 0;
+                bandm |= __ballot(a < thi[g]) & ~__ballot(lo);
+            }
+        if (bandm != 0ull || unsafe != 0) {
+            // rare: recompute flagged residuals with the canonical formula
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int pi = base + 4 * grp + v;
+                if (pi >= M) continue;
+                const bool row_bad = (unsafe >> (4 * grp + v)) & 1u;
+                bool any = row_bad;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const float a = fabsf(D[g][v]);
+                    any = any || (a >= tlo[g] && a < thi[g]);
+                }
+                if (!any) continue;
+                const float4 p = pts[pi];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const float a = fabsf(D[g][v]);
+                    const bool counted = a < tlo[g];
+                    if (row_bad || (!counted && a < thi[g]))
+                        cnt[g] += (fabsf(canon_res(hf[g], p.x, p.y, p.z)) < t ? 1 : 0) - (counted ? 1 : 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        int c = cnt[g];
+        c += __shfl_xor(c, 16);
+        c += __shfl_xor(c, 32);
+        const int j = h0 + g * 16 + col;
+        if (grp == 0 && c != 0 && j < f.hyps) atomicAdd(&f.counts[j], c);
     }
 }
 
@@ -811,9 +976,21 @@ static void score_launch(const FrameDev* tab, int nf, int r, int max_pts, int ma
     hipLaunchKernelGGL((k_score<HB>), dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
 }
 
-static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, const Tuning& tu,
-                           hipStream_t s) {
+template <int PREC>
+static void score_mfma_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target,
+                              hipStream_t s) {
+    const int groups = (max_hyps + 63) / 64;
+    const int per_frame_cap = clampi(16384 / (nf > 0 ? nf : 1), 8, 4096);
+    const int bx = clampi((max_pts + target - 1) / target, 1, clampi(per_frame_cap / groups, 1, 1024));
+    hipLaunchKernelGGL((k_score_mfma<PREC>), dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
+}
+
+static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int precision,
+                           const Tuning& tu, hipStream_t s) {
     const int target = chunk_value(tu.score_chunk);
+    if (precision == PP_SCORE_MFMA_F32) return score_mfma_launch<PP_SCORE_MFMA_F32>(tab, nf, r, max_pts, max_hyps, target, s);
+    if (precision == PP_SCORE_BF16) return score_mfma_launch<PP_SCORE_BF16>(tab, nf, r, max_pts, max_hyps, target, s);
+    if (precision == PP_SCORE_FP16) return score_mfma_launch<PP_SCORE_FP16>(tab, nf, r, max_pts, max_hyps, target, s);
     switch (tu.score_hb) {
         case 0: score_launch<8>(tab, nf, r, max_pts, max_hyps, target, s); break;
         case 1: score_launch<16>(tab, nf, r, max_pts, max_hyps, target, s); break;
@@ -823,10 +1000,9 @@ static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int 
 
 hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_hyps, int precision,
                         const Tuning& tu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    (void)precision;
     hipLaunchKernelGGL(k_hypgen, dim3((max_hyps + kBlock - 1) / kBlock, 1, nf), dim3(kBlock), 0, s, tab, r);
     if (ev0) (void)hipEventRecord(ev0, s);
-    score_dispatch(tab, nf, r, max_px, max_hyps, tu, s);
+    score_dispatch(tab, nf, r, max_px, max_hyps, precision, tu, s);
     if (ev1) (void)hipEventRecord(ev1, s);
     const int nch = (max_px + kRefitChunk - 1) / kRefitChunk;
     const int gx = clampi(nch, 1, 1024);
@@ -842,8 +1018,7 @@ hipError_t launch_hyp_from_triples(const FrameDev* tab, const int32_t* triples, 
 }
 
 hipError_t launch_score_only(const FrameDev* tab, int max_px, int n, int precision, const Tuning& tu, hipStream_t s) {
-    (void)precision;
-    score_dispatch(tab, 1, 0, max_px, n, tu, s);
+    score_dispatch(tab, 1, 0, max_px, n, precision, tu, s);
     return hipGetLastError();
 }
 

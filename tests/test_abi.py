@@ -32,7 +32,8 @@ def test_ctypes_structures_match_the_c_layout(tmp_path):
     from paper_2411_01919_amd import _native as N
     structs = {"pp_intrinsics": N.Intrinsics, "pp_frame_desc": N.FrameDesc, "pp_diffuse_params": N.DiffuseParams,
                "pp_ransac_params": N.RansacParams, "pp_plane": N.Plane, "pp_ransac_debug": N.RansacDebug,
-               "pp_frame_job": N.FrameJob, "pp_tuning": N.Tuning}
+               "pp_frame_job": N.FrameJob, "pp_tuning": N.Tuning, "pp_server_cfg": N.ServerCfg,
+               "pp_result": N.Result, "pp_server_stats": N.ServerStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pp.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

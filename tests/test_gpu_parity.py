@@ -409,3 +409,62 @@ def test_invalid_arguments_are_rejected_before_launch(pp):
     out = pp.diffuse(d, 1)
     torch.cuda.synchronize()
     assert float(out.abs().sum().item()) == 0.0
+
+
+# ------------------------------------------------------------------ precision forms
+@pytest.mark.parametrize("cid,k", [(1, 0), (2, 1), (3, 1)])
+def test_matrix_core_forms_equal_the_fp32_path_bitwise(pp, cid, k):
+    """FP32-MFMA, BF16 and FP16 scoring (with the recheck band) return the
+    canonical FP32 counts, hence identical planes and labels."""
+    f = scenes.make_frame(cid, k)
+    H, W = f.depth.shape
+    runs = {}
+    for prec, band in [(pp.PP_SCORE_FP32, 0.0), (pp.PP_SCORE_MFMA_F32, 0.0), (pp.PP_SCORE_BF16, 0.002),
+                       (pp.PP_SCORE_FP16, 0.002), (pp.PP_SCORE_BF16, 1e-4), (pp.PP_SCORE_FP16, 0.0)]:
+        dc, rc = cfg_params(cid, W, H, k, precision=prec, recheck_band_m=band)
+        runs[(prec, band)] = run_plain(f, dc, rc)
+    ref = runs[(pp.PP_SCORE_FP32, 0.0)]
+    for key, g in runs.items():
+        assert g["n_planes"] == ref["n_planes"], key
+        assert np.array_equal(g["dbg"]["counts"], ref["dbg"]["counts"]), key
+        assert np.array_equal(g["labels"], ref["labels"]), key
+        for a, b in zip(g["planes"], ref["planes"]):
+            assert np.array_equal(a["n"], b["n"]) and a["d"] == b["d"], key
+    log(f"  cfg={cid} k={k}: {ref['n_planes']} planes identical under every scoring form")
+
+
+@pytest.mark.parametrize("prec,band", [(1, 0.0), (2, 0.002), (3, 0.002), (2, 0.0)])
+def test_matrix_core_counts_of_scored_triples(pp, prec, band):
+    import torch
+    f = scenes.make_frame(2, 0)
+    K = f.K
+    dmm = pp.diffuse(to_dev(f.depth), 20)
+    pts, nrm, valid = pp.normals(dmm, (K.fx, K.fy, K.cx, K.cy))
+    v = valid.cpu().numpy() & 1
+    L = np.flatnonzero(v.reshape(-1))
+    rng = np.random.default_rng(prec)
+    offs = torch.from_numpy(rng.choice(L, size=(777, 3)).astype(np.int32)).cuda()
+    pl_ref, c_ref = pp.score_triples(pts, valid, offs, 0.01)
+    pl, c = pp.score_triples(pts, valid, offs, 0.01, precision=prec, recheck_band_m=band)
+    assert torch.equal(c, c_ref) and torch.equal(pl.isnan(), pl_ref.isnan())
+
+
+def test_batched_bf16_form_equals_plain_fp32(pp):
+    import torch
+    spec = [(2, 3), (3, 0), (4, 1)]
+    ref, outs = [], []
+    for cid, k in spec:
+        f = scenes.make_frame(cid, k)
+        H, W = f.depth.shape
+        dc, rc = cfg_params(cid, W, H, k)
+        fo = pp.make_outputs(to_dev(f.depth), (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc)
+        pp.run_frame(fo)
+        torch.cuda.synchronize()
+        ref.append(_snapshot(fo))
+        dc, rc = cfg_params(cid, W, H, k, precision=pp.PP_SCORE_BF16, recheck_band_m=0.002)
+        outs.append(pp.make_outputs(to_dev(f.depth), (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc))
+    pp.batch_run(outs)
+    torch.cuda.synchronize()
+    for fo, r in zip(outs, ref):
+        for a, b in zip(_snapshot(fo), r):
+            assert np.array_equal(a, b)
