@@ -72,7 +72,7 @@ def load_traffic(kernel_hash):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(frames, cfg, budget_s=12.0, max_frames=4):
+def cpu_baseline(frames, cfg, budget_s=12.0, max_frames=64):
     import oracle
     done, t0 = 0, time.perf_counter()
     for f in frames[:max_frames]:
@@ -89,6 +89,196 @@ def cpu_baseline(frames, cfg, budget_s=12.0, max_frames=4):
                       f"(diffusion, normals, sequential RANSAC), {dt:.1f} s"}
 
 
+def served_bench(pp, duration_s=20.0, seed=5):
+    """Eight simulated cameras (3x 424x240, 3x 640x480, 2x 1280x720) at 30 Hz
+    with Poisson arrivals and 3x bursts (1 s in every 5 s), straight and
+    spiral stair scenes alternating, through the server under an 8 GB budget;
+    then a closed-loop saturation run of the three 640x480 cameras."""
+    import threading
+
+    import scenes
+    cams = [(424, 240)] * 3 + [(640, 480)] * 3 + [(1280, 720)] * 2
+    cfg = scenes.CONFIGS[5]
+    pools = {}
+    for sid, (w, h) in enumerate(cams):
+        pools[sid] = [scenes.make_frame(5, 10 * sid + i, size=(w, h)) for i in range(3)]
+    srv = pp.Server(hbm_budget_bytes=8 << 30, max_batch=32, lanes=2, staging_frames=256, use_graphs=True)
+    for sid, (w, h) in enumerate(cams):
+        f0 = pools[sid][0]
+        dc = pp.DiffuseConfig(cfg.diffuse_iters, cfg.lam, cfg.kappa_mm)
+        rc = pp.RansacConfig(cfg.max_planes, cfg.hyps, cfg.min_inliers(w, h), cfg.thresh_m, cfg.ransac_seed, 0)
+        srv.open_stream(sid, w, h, (f0.K.fx, f0.K.fy, f0.K.cx, f0.K.cy), dc, rc)
+    # warm the graphs of the common batch layouts
+    warm = [srv.submit(sid, pools[sid][0].depth, 0) for sid in range(len(cams))]
+    for sid, t in enumerate(warm):
+        while srv.poll(t, sid, timeout_us=100000, labels=False) is None:
+            pass
+    rng = np.random.default_rng(seed)
+    arrivals = []
+    for sid in range(len(cams)):
+        t = 0.0
+        while t < duration_s:
+            rate = 90.0 if (t % 5.0) < 1.0 else 30.0
+            t += rng.exponential(1.0 / rate)
+            if t < duration_s:
+                arrivals.append((t, sid))
+    arrivals.sort()
+    outstanding = []
+    lock = threading.Lock()
+    rejected = [0]
+
+    def submitter():
+        t0 = time.perf_counter()
+        for i, (ta, sid) in enumerate(arrivals):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tk = srv.try_submit(sid, pools[sid][i % 3].depth, i)
+            with lock:
+                if tk is None:
+                    rejected[0] += 1
+                else:
+                    outstanding.append((tk, sid))
+
+    th = threading.Thread(target=submitter)
+    base = srv.stats()
+    th.start()
+    lat = {}
+    done = 0
+    t_start = time.perf_counter()
+    while th.is_alive() or outstanding:
+        with lock:
+            cur = list(outstanding)
+        if not cur:
+            time.sleep(0.001)
+            continue
+        for tk, sid in cur:
+            r = srv.poll(tk, sid, timeout_us=200, labels=False)
+            if r is not None:
+                lat.setdefault(cams[sid], []).append(r["latency_us"] / 1e3)
+                done += 1
+                with lock:
+                    outstanding.remove((tk, sid))
+        if time.perf_counter() - t_start > duration_s + 60:
+            break
+    th.join()
+    wall = time.perf_counter() - t_start
+    st = srv.stats()
+    all_lat = np.concatenate([np.array(v) for v in lat.values()]) if lat else np.zeros(1)
+    res = {"cameras": "3x424x240 + 3x640x480 + 2x1280x720 at 30 Hz, Poisson, 3x bursts 1 s in 5 s",
+           "seconds": round(duration_s, 1), "offered_frames": len(arrivals), "completed": done,
+           "rejected": rejected[0], "frames_per_s": round(done / wall, 2),
+           "p50_ms": round(float(np.percentile(all_lat, 50)), 3), "p99_ms": round(float(np.percentile(all_lat, 99)), 3),
+           "mean_batch": round((st["launches"] - base["launches"]) and
+                               (st["completed"] - base["completed"]) / (st["launches"] - base["launches"]), 2),
+           "hbm_peak_mib": st["hbm_peak"] >> 20}
+    for (w, h), v in sorted(lat.items()):
+        res[f"p50_ms_{w}x{h}"] = round(float(np.percentile(v, 50)), 3)
+        res[f"p99_ms_{w}x{h}"] = round(float(np.percentile(v, 99)), 3)
+    # saturation: keep 64 frames in flight on each 640x480 camera for 4 s
+    sids = [3, 4, 5]
+    inflight = {sid: [] for sid in sids}
+    n_done, k = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 4.0:
+        for sid in sids:
+            while len(inflight[sid]) < 64:
+                inflight[sid].append(srv.submit(sid, pools[sid][k % 3].depth, 100000 + k))
+                k += 1
+            keep = []
+            for tk in inflight[sid]:
+                r = srv.poll(tk, sid, timeout_us=0, labels=False)
+                if r is None:
+                    keep.append(tk)
+                else:
+                    n_done += 1
+            inflight[sid] = keep
+        time.sleep(0.0005)
+    res["saturation_frames_per_s_640x480"] = round(n_done / (time.perf_counter() - t0), 2)
+    for sid in sids:
+        for tk in inflight[sid]:
+            while srv.poll(tk, sid, timeout_us=100000, labels=False) is None:
+                pass
+    srv.close()
+    return res
+
+
+def diffusion_bytes_per_px(iters, T):
+    """Algorithmic HBM bytes per pixel of the diffusion passes: uint16 input
+    read every pass, FP32 delta read (all but the first) and written (FP32
+    depth on the last)."""
+    if iters <= 0:
+        return 6
+    P = (iters + T - 1) // T
+    return 2 * P + 4 * (P - 1) + 4 * P
+
+
+def precision_bench(pp, reps=3):
+    """The precision form on two homogeneous batches of 256 frames (1280x720
+    and 848x480 straight-stair frames, 4096 hypotheses): scoring on the vector
+    ALUs, FP32 matrix cores, BF16 and FP16 matrix cores with the 2 mm
+    recheck; outputs must be bitwise identical across forms.  Also the HBM
+    rate of diffusion and normals at a size far above the 256 MB cache.
+    Each batch replicates 8 generated frames 32 times (frame ids differ)."""
+    import torch
+
+    import scenes
+    from paper_2411_01919_amd import autotune
+    ctx = pp.default_context(0)
+    cfg = scenes.CONFIGS[4]
+    out = {}
+    for (W, H) in ((1280, 720), (848, 480)):
+        base = [scenes.make_frame(4, k, size=(W, H)) for k in range(8)]
+        frames = []
+        for i in range(256):
+            f = base[i % 8]
+            d = torch.from_numpy(f.depth.view(np.int16)).to("cuda:0")
+            dc = pp.DiffuseConfig(cfg.diffuse_iters, cfg.lam, cfg.kappa_mm)
+            rc = pp.RansacConfig(cfg.max_planes, cfg.hyps, cfg.min_inliers(W, H), cfg.thresh_m, cfg.ransac_seed, i)
+            frames.append(pp.make_outputs(d, (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc))
+        tun = autotune.tune(frames, ctx=ctx)
+        ctx.set_stage_timing(True)
+        rec = {"tuning": {k: tun[k] for k in ("diffuse_tile", "diffuse_t", "score_hb", "score_chunk")}}
+        ref = None
+        for name, prec, band in (("fp32_valu", pp.PP_SCORE_FP32, 0.0), ("fp32_mfma", pp.PP_SCORE_MFMA_F32, 0.0),
+                                 ("bf16_mfma", pp.PP_SCORE_BF16, 0.002), ("fp16_mfma", pp.PP_SCORE_FP16, 0.002)):
+            for fo in frames:
+                fo.ransac.precision, fo.ransac.recheck_band_m = prec, band
+            best = None
+            for r in range(reps + 1):
+                a = time.perf_counter()
+                pp.batch_run(frames, graph=False, ctx=ctx)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - a
+                br = ctx.stage_breakdown()
+                if r and (best is None or wall < best[0]):
+                    best = (wall, br)
+            snap = [(int(fo.n_planes.cpu().item()), fo.planes.cpu().numpy().tobytes(), fo.labels.cpu().numpy())
+                    for fo in frames[:16]]
+            if ref is None:
+                ref = snap
+            same = all(a[0] == b[0] and a[1] == b[1] and np.array_equal(a[2], b[2]) for a, b in zip(snap, ref))
+            wall, br = best
+            rec[name] = {"frames_per_s": round(256 / wall, 2), "scoring_ms": round(br["scoring"], 3),
+                         "identical_to_fp32": bool(same)}
+            log(f"precision {W}x{H} {name}: {rec[name]}")
+        px = 256 * W * H
+        br = ctx.stage_breakdown()
+        T = ctx.get_tuning()["diffuse_t"]
+        dbytes = diffusion_bytes_per_px(cfg.diffuse_iters, T) * px
+        nbytes = 50 * px  # normals 4 in + 25 out, valid list 1 in + 20 out per pixel (upper bound)
+        rec["diffusion_hbm"] = {"gb_per_s": round(dbytes / (br["diffusion"] * 1e-3) / 1e9, 1),
+                                "frac_of_8tbs": round(dbytes / (br["diffusion"] * 1e-3) / 8e12, 3),
+                                "bytes_per_px": diffusion_bytes_per_px(cfg.diffuse_iters, T), "ms": round(br["diffusion"], 3)}
+        rec["normals_hbm"] = {"gb_per_s": round(nbytes / (br["normals"] * 1e-3) / 1e9, 1),
+                              "frac_of_8tbs": round(nbytes / (br["normals"] * 1e-3) / 8e12, 3), "ms": round(br["normals"], 3)}
+        ctx.set_stage_timing(False)
+        out[f"{W}x{H}x256"] = rec
+        del frames
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +288,9 @@ def main():
     ap.add_argument("--plain-frames", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--served-seconds", type=float, default=20.0, help="0 skips the served leg")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--c4", action="store_true", help="add the precision-form leg (two batches of 256 large frames)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -123,6 +316,11 @@ def main():
         outs.append(pp.make_outputs(d, (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc))
     ctx = pp.default_context(0)
     stream = torch.cuda.current_stream()
+    tuning = None
+    if not args.no_autotune:
+        from paper_2411_01919_amd import autotune
+        tuning = autotune.tune(outs, ctx=ctx, log=log)
+        log(f"tuning: {tuning}")
 
     # ---------------------------------------------------------------- batched (graph) path: the value
     for i in range(args.warmup):
@@ -144,6 +342,7 @@ def main():
     pp.batch_run(outs, graph=False, ctx=ctx)
     torch.cuda.synchronize()
     score_ms, score_launches = 0.0, 0
+    stage_ms = {}
     t2 = time.perf_counter()
     for i in range(args.steps):
         pp.batch_run(outs, graph=False, ctx=ctx)
@@ -151,6 +350,9 @@ def main():
         ms, n = ctx.stage_time()
         score_ms += ms
         score_launches += n
+        br = ctx.stage_breakdown()
+        for kk, vv in br.items():
+            stage_ms[kk] = stage_ms.get(kk, 0.0) + vv
     t3 = time.perf_counter()
     ctx.set_stage_timing(False)
     eager_fps = args.batch * args.steps / (t3 - t2)
@@ -192,6 +394,17 @@ def main():
                  "p99_ms": round(float(np.percentile(lat, 99)), 3), "frames": nf}
         log(f"plain: {plain}")
 
+    served = None
+    if args.served_seconds > 0:
+        log(f"served leg: {args.served_seconds:.0f} s of simulated cameras")
+        served = served_bench(pp, args.served_seconds)
+        log(f"served: {served}")
+
+    precision = None
+    if args.c4:
+        log("precision-form leg")
+        precision = precision_bench(pp)
+
     base = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -216,8 +429,13 @@ def main():
                    "batch_frames": args.batch, "form": "batched, one HIP graph replay per step",
                    "eager_batched_frames_per_s": round(eager_fps, 2),
                    "mpixel_per_s": round(batched_fps * W * H / 1e6, 2),
+                   "tuning": {k: tuning[k] for k in ("diffuse_tile", "diffuse_t", "score_hb", "score_chunk")}
+                   if tuning else "default",
+                   "stage_ms_per_step": {k: round(v / args.steps, 3) for k, v in stage_ms.items()},
                    "planes_per_frame": round(planes_tot / len(outs), 2)},
         "plain": plain,
+        "served": served,
+        "precision_form": precision,
         "roofline": {"bound": "alu", "kernel": "k_score (inlier scoring)",
                      "achieved": round(achieved, 3), "peak": round(VALU_FMA_TFLOPS, 1), "unit": "TFLOP/s",
                      "frac": round(achieved / VALU_FMA_TFLOPS, 4), "traffic": traffic,

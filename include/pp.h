@@ -303,6 +303,10 @@ pp_status pp_server_stats_get(pp_server* s, pp_server_stats* out);
  * their number; the caller must have synchronised the stream first. */
 pp_status pp_set_stage_timing(pp_ctx* ctx, int32_t enable);
 pp_status pp_stage_time(pp_ctx* ctx, float* total_ms, int32_t* launches);
+/* For the most recent instrumented pp_batch_run_eager: ms of [0] diffusion,
+ * [1] back-projection + normals + valid list, [2] inlier scoring (all
+ * rounds), [3] the rest of RANSAC (hypotheses, refit, labelling). */
+pp_status pp_stage_breakdown(pp_ctx* ctx, float out_ms[4]);
 
 #ifdef __cplusplus
 }

@@ -130,6 +130,12 @@ class Context:
         self.check(N.lib().pp_stage_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
 
+    def stage_breakdown(self) -> dict:
+        """ms per stage of the last timed eager batch: diffusion, normals (+ valid list), scoring, rest."""
+        out = (N.c_f32 * 4)()
+        self.check(N.lib().pp_stage_breakdown(self.h, out))
+        return dict(diffusion=out[0], normals=out[1], scoring=out[2], ransac_other=out[3])
+
     def get_tuning(self) -> dict:
         t = N.Tuning()
         self.check(N.lib().pp_get_tuning(self.h, ctypes.byref(t)))

@@ -92,6 +92,7 @@ SIGNATURES = {
     "pp_get_tuning": (c_i32, [c_vp, ctypes.POINTER(Tuning)]),
     "pp_tuning_space": (c_i32, [ctypes.POINTER(c_i32)] * 4),
     "pp_set_stage_timing": (c_i32, [c_vp, c_i32]),
+    "pp_stage_breakdown": (c_i32, [c_vp, ctypes.POINTER(c_f32)]),
     "pp_server_create": (c_i32, [ctypes.POINTER(ServerCfg), ctypes.POINTER(c_vp)]),
     "pp_server_destroy": (c_i32, [c_vp]),
     "pp_server_last_error": (ctypes.c_char_p, [c_vp]),

@@ -58,6 +58,8 @@ struct pp_ctx {
     // stage timing: events around each round's scoring launch
     bool timing = false;
     hipEvent_t score_ev[ppk::kMaxRounds][2] = {};
+    hipEvent_t stage_ev[4] = {};  // batch start, after diffusion, after normals + valid list, end
+    bool stages_valid = false;
     int timed_rounds = 0;
 };
 
@@ -291,6 +293,8 @@ pp_status pp_ctx_destroy(pp_ctx* c) {
     for (int r = 0; r < ppk::kMaxRounds; ++r)
         for (int k = 0; k < 2; ++k)
             if (c->score_ev[r][k]) (void)hipEventDestroy(c->score_ev[r][k]);
+    for (int k = 0; k < 4; ++k)
+        if (c->stage_ev[k]) (void)hipEventDestroy(c->stage_ev[k]);
     delete c;
     return PP_OK;
 }
@@ -346,11 +350,35 @@ pp_status pp_set_stage_timing(pp_ctx* c, int32_t enable) {
     pp_status s = check_ctx(c);
     if (s != PP_OK) return s;
     if ((s = set_device(c)) != PP_OK) return s;
-    if (enable && !c->score_ev[0][0])
+    if (enable && !c->score_ev[0][0]) {
         for (int r = 0; r < ppk::kMaxRounds; ++r)
             for (int k = 0; k < 2; ++k) HIPCHK(c, hipEventCreate(&c->score_ev[r][k]));
+        for (int k = 0; k < 4; ++k) HIPCHK(c, hipEventCreate(&c->stage_ev[k]));
+    }
+    c->stages_valid = false;
     c->timing = enable != 0;
     c->timed_rounds = 0;
+    return PP_OK;
+}
+
+pp_status pp_stage_breakdown(pp_ctx* c, float out_ms[4]) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if (!out_ms) return fail(c, PP_E_INVAL, "pp_stage_breakdown: null output");
+    if (!c->stages_valid) return fail(c, PP_E_INVAL, "pp_stage_breakdown: no timed batch run yet");
+    float d = 0.f, n = 0.f, rr = 0.f, sc = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&d, c->stage_ev[0], c->stage_ev[1]));
+    HIPCHK(c, hipEventElapsedTime(&n, c->stage_ev[1], c->stage_ev[2]));
+    HIPCHK(c, hipEventElapsedTime(&rr, c->stage_ev[2], c->stage_ev[3]));
+    for (int r = 0; r < c->timed_rounds; ++r) {
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->score_ev[r][0], c->score_ev[r][1]));
+        sc += ms;
+    }
+    out_ms[0] = d;
+    out_ms[1] = n;
+    out_ms[2] = sc;
+    out_ms[3] = rr - sc;
     return PP_OK;
 }
 
@@ -563,16 +591,23 @@ BatchPlan plan_batch(const pp_frame_job* jobs, int n, const ppk::Tuning& tu) {
 }
 
 pp_status enqueue_batch(pp_ctx* c, const BatchPlan& b, hipStream_t st, bool capturing) {
+    const bool timed = c->timing && !capturing;
+    if (timed) HIPCHK(c, hipEventRecord(c->stage_ev[0], st));
     for (size_t g = 0; g < b.iter_groups.size(); ++g)
         HIPCHK(c, ppk::launch_diffuse(c->batch_tab + b.iter_groups[g].first, b.iter_groups[g].second, b.maxW, b.maxH,
                                       b.group_iters[g], c->tuning, st));
+    if (timed) HIPCHK(c, hipEventRecord(c->stage_ev[1], st));
     HIPCHK(c, ppk::launch_normals(c->batch_tab, b.nf, b.maxW, b.maxH, st));
     HIPCHK(c, ppk::launch_valid_list(c->batch_tab, b.nf, b.max_px, st));
-    const bool timed = c->timing && !capturing;
+    if (timed) HIPCHK(c, hipEventRecord(c->stage_ev[2], st));
     for (int r = 0; r < b.max_rounds; ++r)
         HIPCHK(c, ppk::launch_round(c->batch_tab, b.nf, r, b.max_px, b.max_hyps, b.precision, c->tuning, st,
                                     timed ? c->score_ev[r][0] : nullptr, timed ? c->score_ev[r][1] : nullptr));
-    if (timed) c->timed_rounds = b.max_rounds;
+    if (timed) {
+        HIPCHK(c, hipEventRecord(c->stage_ev[3], st));
+        c->timed_rounds = b.max_rounds;
+        c->stages_valid = true;
+    }
     return PP_OK;
 }
 

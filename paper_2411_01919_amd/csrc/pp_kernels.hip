@@ -755,17 +755,29 @@ __device__ void jacobi3(double a[3][3], double v[3][3]) {
     }
 }
 
-// Reduce the chunk moments (fixed order), solve for the least-squares plane:
-// centroid c = shift + S/n, scatter C = Q - S S^T / n, normal = eigenvector
-// of the smallest eigenvalue, d = -n.c, flipped so that d >= 0.
-__device__ void solve_refit(const FrameDev& f, int M, double* plane, double* centroid, double* nmom) {
+// Reduce the chunk moments in a fixed order (thread t sums chunks t, t+256,
+// ... in order, then a fixed tree over threads), so every block obtains the
+// same bits.  Then the least-squares plane: centroid c = shift + S/n,
+// scatter C = Q - S S^T / n, normal = eigenvector of the smallest eigenvalue,
+// d = -n.c, flipped so that d >= 0.  All threads call; thread 0 solves.
+__device__ void solve_refit(const FrameDev& f, int M, double* plane, double* centroid, double* nmom, double* sh) {
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
-    double m[10];
-    for (int k = 0; k < 10; ++k) {
-        double s = 0.0;
-        for (int c = 0; c < nch; ++c) s += f.partials[(size_t)c * 10 + k];
-        m[k] = s;
+    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c = threadIdx.x; c < nch; c += kBlock)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) m[k] += f.partials[(size_t)c * 10 + k];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) sh[k * kBlock + threadIdx.x] = m[k];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 10; ++k) sh[k * kBlock + threadIdx.x] += sh[k * kBlock + threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x != 0) return;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) m[k] = sh[k * kBlock];
     const double n = m[0];
     const double mx = m[1] / n, my = m[2] / n, mz = m[3] / n;
     double a[3][3];
@@ -794,13 +806,14 @@ __device__ void solve_refit(const FrameDev& f, int M, double* plane, double* cen
 __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restrict__ tab, int r) {
     __shared__ double s_plane[4], s_cent[3], s_n;
     __shared__ int sh[4];
+    __shared__ double s_red[10 * kBlock];
     const FrameDev& f = tab[blockIdx.z];
     RoundState* st = f.st;
     if (!st->active[r] || st->stop[r]) return;
     const int M = st->M[r];
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
     if ((int)blockIdx.x >= nch) return;
-    if (threadIdx.x == 0) solve_refit(f, M, s_plane, s_cent, &s_n);
+    solve_refit(f, M, s_plane, s_cent, &s_n, s_red);
     __syncthreads();
     const SplitPlane q = split_plane(s_plane);
     const float t = f.thresh;

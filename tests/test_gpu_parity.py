@@ -468,3 +468,18 @@ def test_batched_bf16_form_equals_plain_fp32(pp):
     for fo, r in zip(outs, ref):
         for a, b in zip(_snapshot(fo), r):
             assert np.array_equal(a, b)
+
+
+def test_autotuner_picks_a_valid_tuning_and_caches_it(pp, tmp_path):
+    import torch
+    from paper_2411_01919_amd import autotune
+    frames = [fo for _, fo in _batch_frames(pp, [(1, 0), (1, 1), (3, 0)])]
+    ctx = pp.Context(0)
+    p = str(tmp_path / "tune.json")
+    t = autotune.tune(frames, ctx=ctx, reps=1, path=p)
+    assert not t["cached"] and t["diffuse_tile"] in autotune.TILES and t["diffuse_t"] in autotune.DEPTHS
+    assert t["diffusion_ms"] <= t["diffusion_default_ms"] + 1e-6
+    t2 = autotune.tune(frames, ctx=ctx, reps=1, path=p)
+    assert t2["cached"] and t2["diffuse_t"] == t["diffuse_t"]
+    assert ctx.get_tuning()["diffuse_t"] == t["diffuse_t"]
+    ctx.close()
