@@ -46,6 +46,7 @@ def lib():
         i, d = ctypes.c_int, ctypes.c_double
         L.orc_philox4x64_10.argtypes = [P, P, P]
         L.orc_diffuse.argtypes = [P, i, i, i, d, d, i, P]
+        L.orc_diffuse_variant.argtypes = [P, i, i, i, d, d, i, i, P]
         L.orc_backproject.argtypes = [P, i, i, d, d, d, d, P, P]
         L.orc_normals.argtypes = [P, P, i, i, P, P, P, P]
         L.orc_valid_list.argtypes = [P, i, P]
@@ -113,6 +114,16 @@ def diffuse(depth: np.ndarray, iters: int, lam: float = 0.2, kappa: float = 30.0
     H, W = d.shape
     out = np.zeros((H, W), dtype=np.float64)
     lib().orc_diffuse(_p(d), W, H, int(iters), float(lam), float(kappa), int(edge_stop), _p(out))
+    return out
+
+
+def diffuse_variant(depth: np.ndarray, iters: int, lam: float, kappa: float, scheme: int, edge_stop: int = 0):
+    """Diffusion variants: scheme 1 = Alg. 1 as printed (pixel-centred c_p lap I),
+    scheme 2 = 8-neighbour per-edge flux."""
+    d = np.ascontiguousarray(depth, dtype=np.float64)
+    H, W = d.shape
+    out = np.zeros((H, W), dtype=np.float64)
+    lib().orc_diffuse_variant(_p(d), W, H, int(iters), float(lam), float(kappa), int(edge_stop), int(scheme), _p(out))
     return out
 
 

@@ -121,6 +121,72 @@ void orc_diffuse(const double* depth, int W, int H, int iters, double lambda, do
 }
 
 /* ------------------------------------------------------------------------ */
+/* Diffusion variants beside the hot path's conservative 4-neighbour form.   */
+/*  scheme 1: Alg. 1 as printed, pixel-centred: c_p = g(|grad I_p|) with the */
+/*            gradient from central differences (one-sided next to a hole or */
+/*            the border, 0 with no neighbour on either side), then          */
+/*            I_p += lambda c_p lap(I)_p, lap = sum over valid 4-neighbours    */
+/*            of (I_q - I_p).  Not conservative.                              */
+/*  scheme 2: per-edge flux over the 8-neighbourhood: diagonal neighbours at  */
+/*            distance sqrt(2) with weight 1/2: I_p += lambda sum_q w_q       */
+/*            g(|I_q - I_p| / d_q) (I_q - I_p).  Conservative; stable for     */
+/*            lambda <= 1/6.                                                 */
+/* ------------------------------------------------------------------------ */
+void orc_diffuse_variant(const double* depth, int W, int H, int iters, double lambda, double kappa,
+                         int edge_stop, int scheme, double* out) {
+    size_t n = (size_t)W * H;
+    double* cur = (double*)malloc(n * sizeof(double));
+    double* nxt = (double*)malloc(n * sizeof(double));
+    for (size_t p = 0; p < n; ++p) cur[p] = depth[p];
+#define VALID(u, v) ((u) >= 0 && (u) < W && (v) >= 0 && (v) < H && depth[(size_t)(v) * W + (u)] > 0.0)
+#define VAL(u, v) cur[(size_t)(v) * W + (u)]
+    for (int it = 0; it < iters; ++it) {
+#pragma omp parallel for schedule(static)
+        for (int v = 0; v < H; ++v) {
+            for (int u = 0; u < W; ++u) {
+                size_t p = (size_t)v * W + u;
+                if (!(depth[p] > 0.0)) {
+                    nxt[p] = 0.0;
+                    continue;
+                }
+                double Ip = cur[p];
+                if (scheme == 1) {
+                    int e = VALID(u + 1, v), w = VALID(u - 1, v), s = VALID(u, v + 1), nn = VALID(u, v - 1);
+                    double gx = e && w ? (VAL(u + 1, v) - VAL(u - 1, v)) / 2.0 : e ? VAL(u + 1, v) - Ip : w ? Ip - VAL(u - 1, v) : 0.0;
+                    double gy = s && nn ? (VAL(u, v + 1) - VAL(u, v - 1)) / 2.0 : s ? VAL(u, v + 1) - Ip : nn ? Ip - VAL(u, v - 1) : 0.0;
+                    double lap = 0.0;
+                    if (e) lap += VAL(u + 1, v) - Ip;
+                    if (w) lap += VAL(u - 1, v) - Ip;
+                    if (s) lap += VAL(u, v + 1) - Ip;
+                    if (nn) lap += VAL(u, v - 1) - Ip;
+                    double c = edge_stop_g(sqrt(gx * gx + gy * gy), kappa, edge_stop);
+                    nxt[p] = Ip + lambda * c * lap;
+                } else {
+                    double flux = 0.0;
+                    for (int dv = -1; dv <= 1; ++dv)
+                        for (int du = -1; du <= 1; ++du) {
+                            if (!du && !dv) continue;
+                            if (!VALID(u + du, v + dv)) continue;
+                            int diag = du && dv;
+                            double delta = VAL(u + du, v + dv) - Ip;
+                            double dist = diag ? sqrt(2.0) : 1.0;
+                            double wq = diag ? 0.5 : 1.0;
+                            flux += wq * edge_stop_g(fabs(delta) / dist, kappa, edge_stop) * delta;
+                        }
+                    nxt[p] = Ip + lambda * flux;
+                }
+            }
+        }
+        double* t = cur; cur = nxt; nxt = t;
+    }
+#undef VALID
+#undef VAL
+    memcpy(out, cur, n * sizeof(double));
+    free(cur);
+    free(nxt);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Back-projection (Sec. III-D: polygons projected to 3-D with K; Alg. 2).    */
 /* ------------------------------------------------------------------------ */
 void orc_backproject(const double* depth_mm, int W, int H, double fx, double fy, double cx, double cy,

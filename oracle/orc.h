@@ -32,6 +32,11 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
 void orc_diffuse(const double* depth, int W, int H, int iters, double lambda, double kappa,
                  int edge_stop, double* out);
 
+/* Diffusion variants: scheme 1 = Alg. 1 as printed (pixel-centred c_p lap I),
+ * scheme 2 = 8-neighbour per-edge flux (diagonals weight 1/2, distance sqrt 2). */
+void orc_diffuse_variant(const double* depth, int W, int H, int iters, double lambda, double kappa,
+                         int edge_stop, int scheme, double* out);
+
 /* Back-projection (Sec. III-D, Alg. 2): P [3][H][W] metres, valid [H][W] (1 = depth > 0). */
 void orc_backproject(const double* depth_mm, int W, int H, double fx, double fy, double cx, double cy,
                      double* P, uint8_t* valid);
