@@ -48,6 +48,7 @@ def lib():
         L.orc_diffuse.argtypes = [P, i, i, i, d, d, i, P]
         L.orc_diffuse_variant.argtypes = [P, i, i, i, d, d, i, i, P]
         L.orc_backproject.argtypes = [P, i, i, d, d, d, d, P, P]
+        L.orc_ransac_regions.argtypes = [P, P, P, i, i, i, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_normals.argtypes = [P, P, i, i, P, P, P, P]
         L.orc_valid_list.argtypes = [P, i, P]
         L.orc_valid_list.restype = i
@@ -287,6 +288,48 @@ def ransac(P, valid, prm: RansacParams) -> RansacResult:
     c = prm._c()
     n = lib().orc_ransac(_p(P), _p(v), W, H, ctypes.byref(c), _p(labels), _p(pl), _p(ce), _p(inl), _p(js), _p(res))
     return RansacResult(n, pl[:n].copy(), ce[:n].copy(), inl[:n].copy(), js[:n].copy(), labels, float(res[0]))
+
+
+@dataclass
+class RegionResult:
+    n_stored: int
+    npts: np.ndarray        # [R]
+    triples: np.ndarray     # [R][hyps][3] positions in the region's row-major list
+    planes: np.ndarray      # [R][hyps][4]
+    hvalid: np.ndarray      # [R][hyps]
+    errors: np.ndarray      # [R][hyps] sum |r| (inf without a plane)
+    counts: np.ndarray      # [R][hyps]
+    counts_lo: np.ndarray
+    counts_hi: np.ndarray
+    jstar: np.ndarray       # [R] (-1 none)
+    stored: np.ndarray      # [R] bool
+    centroids: np.ndarray   # [R][3]
+    labels: np.ndarray      # [H][W] int8
+
+
+def ransac_regions(P, valid, region, R: int, prm: RansacParams, eps=None) -> RegionResult:
+    """Region-mode RANSAC (Alg. 2 as printed) for region labels 0..R-1."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    _, H, W = P.shape
+    v = np.ascontiguousarray(valid, dtype=np.uint8)
+    reg = np.ascontiguousarray(region, dtype=np.int16)
+    nh = prm.hyps
+    npts = np.zeros(R, np.int32)
+    tr = np.zeros((R, nh, 3), np.int32)
+    pl = np.zeros((R, nh, 4))
+    hv = np.zeros((R, nh), np.uint8)
+    er = np.zeros((R, nh))
+    cn, lo, hi = (np.zeros((R, nh), np.int32) for _ in range(3))
+    js = np.zeros(R, np.int32)
+    st = np.zeros(R, np.uint8)
+    ce = np.zeros((R, 3))
+    labels = np.zeros((H, W), np.int8)
+    e = None if eps is None else np.ascontiguousarray(np.broadcast_to(eps, (R, nh)), dtype=np.float64)
+    c = prm._c()
+    ns = lib().orc_ransac_regions(_p(P), _p(v), _p(reg), W, H, int(R), ctypes.byref(c), _p(e) if e is not None else None,
+                                  _p(npts), _p(tr), _p(pl), _p(hv), _p(er), _p(cn), _p(lo), _p(hi), _p(js), _p(st),
+                                  _p(ce), _p(labels))
+    return RegionResult(ns, npts, tr, pl, hv.astype(bool), er, cn, lo, hi, js, st.astype(bool), ce, labels)
 
 
 @dataclass

@@ -577,3 +577,135 @@ int orc_ransac(const double* P, const uint8_t* valid, int W, int H, const orc_ra
     free(fmask);
     return np;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Region-mode RANSAC: Alg. 2 as printed, one region at a time.               */
+/* For each region g (pixels with depth and region label g, 0 <= g < R, in    */
+/* row-major order):                                                          */
+/*  - hypothesis j draws three distinct positions of the region's list from  */
+/*    Philox4x64-10 words, key (seed, frame), counter (j, g, b, 1), position */
+/*    floor(w n_g / 2^64); a repeated position is skipped; a degenerate      */
+/*    triple gives no plane;                                                 */
+/*  - error_j = sum over all the region's points of |n.p + d| (Eq. 3),       */
+/*    inliers_j = #{|n.p + d| < t};                                          */
+/*  - the model kept is the first one with the smallest error (strict <, so  */
+/*    ties go to the smaller j); none when no hypothesis has a plane;        */
+/*  - it is stored iff inliers / n_g > 0.9, evaluated as 10 inliers > 9 n_g. */
+/* labels[p] = g for the inliers of a stored model, -1 elsewhere;             */
+/* centroids[g] = mean of those inliers.  Returns the number stored.         */
+/* ------------------------------------------------------------------------ */
+int orc_ransac_regions(const double* P, const uint8_t* valid, const int16_t* region, int W, int H, int R,
+                       const orc_ransac_params* prm, const double* eps, int32_t* npts, int32_t* triples,
+                       double* planes, uint8_t* hvalid, double* errors, int32_t* counts, int32_t* counts_lo,
+                       int32_t* counts_hi, int32_t* jstar, uint8_t* stored, double* centroids, int8_t* labels) {
+    size_t n = (size_t)W * H;
+    const int nh = prm->hyps;
+    int32_t* list = (int32_t*)malloc((n > 0 ? n : 1) * sizeof(int32_t));
+    for (size_t p = 0; p < n; ++p) labels[p] = -1;
+    int n_stored = 0;
+    for (int g = 0; g < R; ++g) {
+        int m = 0;
+        for (size_t p = 0; p < n; ++p)
+            if ((valid[p] & 1) && region[p] == g) list[m++] = (int32_t)p;
+        npts[g] = m;
+        int32_t* tr = triples + (size_t)g * nh * 3;
+        double* pls = planes + (size_t)g * nh * 4;
+        uint8_t* hv = hvalid + (size_t)g * nh;
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < nh; ++j) {
+            int slot[3] = {-1, -1, -1};
+            int got = 0;
+            for (int b = 0; b < 16 && got < 3 && m > 0; ++b) {
+                uint64_t ctr[4] = {(uint64_t)j, (uint64_t)g, (uint64_t)b, 1};
+                uint64_t key[2] = {prm->seed, prm->frame};
+                uint64_t w[4];
+                orc_philox4x64_10(ctr, key, w);
+                for (int q = 0; q < 4 && got < 3; ++q) {
+                    int k = (int)(((unsigned __int128)w[q] * (uint64_t)m) >> 64);
+                    int dup = 0;
+                    for (int s = 0; s < got; ++s)
+                        if (slot[s] == k) dup = 1;
+                    if (!dup) slot[got++] = k;
+                }
+            }
+            double* pl = pls + 4 * (size_t)j;
+            pl[0] = pl[1] = pl[2] = pl[3] = 0.0;
+            hv[j] = 0;
+            for (int s = 0; s < 3; ++s) tr[3 * j + s] = got == 3 ? slot[s] : -1;
+            if (got < 3) continue;
+            double p0[3], p1[3], p2[3];
+            point_at(P, n, list[slot[0]], p0);
+            point_at(P, n, list[slot[1]], p1);
+            point_at(P, n, list[slot[2]], p2);
+            double e1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+            double e2[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+            double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                           e1[0] * e2[1] - e1[1] * e2[0]};
+            double cn = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+            double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+            double l2 = sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+            if (!(cn > 1e-3 * l1 * l2)) continue;
+            double nn[3] = {c[0] / cn, c[1] / cn, c[2] / cn};
+            double d = -(nn[0] * p0[0] + nn[1] * p0[1] + nn[2] * p0[2]);
+            if (d < 0) {
+                nn[0] = -nn[0]; nn[1] = -nn[1]; nn[2] = -nn[2];
+                d = -d;
+            }
+            pl[0] = nn[0]; pl[1] = nn[1]; pl[2] = nn[2]; pl[3] = d;
+            hv[j] = 1;
+        }
+        /* Alg. 2 inner loop over every point of the region */
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int j = 0; j < nh; ++j) {
+            size_t o = (size_t)g * nh + j;
+            double e = 0.0;
+            int32_t c = 0, clo = 0, chi = 0;
+            if (hv[j]) {
+                const double* pl = pls + 4 * (size_t)j;
+                double tlo = eps ? prm->thresh - eps[o] : prm->thresh;
+                double thi = eps ? prm->thresh + eps[o] : prm->thresh;
+                for (int i = 0; i < m; ++i) {
+                    double p[3];
+                    point_at(P, n, list[i], p);
+                    double dist = fabs(pl[0] * p[0] + pl[1] * p[1] + pl[2] * p[2] + pl[3]);
+                    e += dist;
+                    c += dist < prm->thresh;
+                    clo += dist < tlo;
+                    chi += dist < thi;
+                }
+            }
+            errors[o] = hv[j] ? e : INFINITY;
+            counts[o] = c;
+            if (counts_lo) counts_lo[o] = clo;
+            if (counts_hi) counts_hi[o] = chi;
+        }
+        int best = -1;
+        double best_err = INFINITY;
+        for (int j = 0; j < nh; ++j)
+            if (hv[j] && errors[(size_t)g * nh + j] < best_err) {
+                best_err = errors[(size_t)g * nh + j];
+                best = j;
+            }
+        jstar[g] = best;
+        stored[g] = best >= 0 && 10LL * counts[(size_t)g * nh + best] > 9LL * m;
+        double* ce = centroids + 3 * (size_t)g;
+        ce[0] = ce[1] = ce[2] = 0.0;
+        if (!stored[g]) continue;
+        ++n_stored;
+        const double* pl = pls + 4 * (size_t)best;
+        double s[3] = {0.0, 0.0, 0.0};
+        int cnt = 0;
+        for (int i = 0; i < m; ++i) {
+            double p[3];
+            point_at(P, n, list[i], p);
+            if (fabs(pl[0] * p[0] + pl[1] * p[1] + pl[2] * p[2] + pl[3]) < prm->thresh) {
+                labels[list[i]] = (int8_t)g;
+                s[0] += p[0]; s[1] += p[1]; s[2] += p[2];
+                ++cnt;
+            }
+        }
+        ce[0] = s[0] / cnt; ce[1] = s[1] / cnt; ce[2] = s[2] / cnt;
+    }
+    free(list);
+    return n_stored;
+}

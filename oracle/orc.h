@@ -101,6 +101,20 @@ void orc_ransac_round(const double* P, int W, int H, const int32_t* L, int M0, c
                       int32_t* counts, int32_t* counts_lo, int32_t* counts_hi,
                       uint8_t* smask, uint8_t* fmask, orc_round_result* res);
 
+/* Region-mode RANSAC, Alg. 2 as printed: for each region label g in [0, R)
+ * (other labels and depth holes belong to no region), hyps hypotheses drawn
+ * from the region's row-major point list with counter (j, g, b, 1); the model
+ * with the smallest sum of |n.p + d| over the region (ties to the smaller j)
+ * is stored iff 10 inliers > 9 n_g.  Arrays: npts [R]; triples [R][hyps][3]
+ * (list positions, -1 when fewer than 3 were drawn); planes [R][hyps][4];
+ * hvalid, errors (INFINITY without a plane), counts [R][hyps]; with eps
+ * [R][hyps] also counts_lo/hi at t -/+ eps; jstar [R] (-1 none); stored [R];
+ * centroids [R][3]; labels [H][W] int8.  Returns the number stored. */
+int orc_ransac_regions(const double* P, const uint8_t* valid, const int16_t* region, int W, int H, int R,
+                       const orc_ransac_params* prm, const double* eps, int32_t* npts, int32_t* triples,
+                       double* planes, uint8_t* hvalid, double* errors, int32_t* counts, int32_t* counts_lo,
+                       int32_t* counts_hi, int32_t* jstar, uint8_t* stored, double* centroids, int8_t* labels);
+
 /* Whole-frame sequential RANSAC.  labels [H][W] int8 (-1 none), planes_out
  * [max_planes][4], centroids_out [max_planes][3], inliers_out, jstar_out
  * [max_planes] (NULL allowed).  Returns the number of planes emitted;
