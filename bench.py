@@ -291,6 +291,11 @@ def main():
     ap.add_argument("--served-seconds", type=float, default=20.0, help="0 skips the served leg")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--c4", action="store_true", help="add the precision-form leg (two batches of 256 large frames)")
+    ap.add_argument("--tuning", type=str, default="", help="tile,T,hb,chunk (1-based knobs) instead of autotuning")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "mfma_f32", "bf16", "fp16"],
+                    help="scoring form of the batched and plain legs (all give identical results)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 256 MiB device-to-device copy (reference for HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
@@ -302,6 +307,15 @@ def main():
     import scenes
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda:0")
+        a.fill_(1)
+        c = torch.empty_like(a)
+        torch.cuda.synchronize()
+        c.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 256 << 20}), flush=True)
+        return
     dev = torch.device("cuda:0")
     cfg = scenes.CONFIGS[2]
     W, H = cfg.sizes[0]
@@ -311,13 +325,19 @@ def main():
     for f in frames:
         d = torch.from_numpy(f.depth.view(np.int16)).to(dev)
         dc = pp.DiffuseConfig(cfg.diffuse_iters, cfg.lam, cfg.kappa_mm)
+        prec = {"fp32": pp.PP_SCORE_FP32, "mfma_f32": pp.PP_SCORE_MFMA_F32, "bf16": pp.PP_SCORE_BF16,
+                "fp16": pp.PP_SCORE_FP16}[args.precision]
         rc = pp.RansacConfig(cfg.max_planes, cfg.hyps, cfg.min_inliers(W, H), cfg.thresh_m, cfg.ransac_seed,
-                             f.meta["k"])
+                             f.meta["k"], prec, 0.002 if args.precision in ("bf16", "fp16") else 0.0)
         outs.append(pp.make_outputs(d, (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc))
     ctx = pp.default_context(0)
     stream = torch.cuda.current_stream()
     tuning = None
-    if not args.no_autotune:
+    if args.tuning:
+        t = [int(x) for x in args.tuning.split(",")]
+        ctx.set_tuning(*t)
+        tuning = dict(zip(("diffuse_tile", "diffuse_t", "score_hb", "score_chunk"), t))
+    elif not args.no_autotune:
         from paper_2411_01919_amd import autotune
         tuning = autotune.tune(outs, ctx=ctx, log=log)
         log(f"tuning: {tuning}")
@@ -427,6 +447,7 @@ def main():
         "config": {"workload": "640x480 straight staircase, 20 diffusion iterations, sequential RANSAC up to "
                                "12 planes x 1024 hypotheses, t = 10 mm",
                    "batch_frames": args.batch, "form": "batched, one HIP graph replay per step",
+                   "scoring": args.precision,
                    "eager_batched_frames_per_s": round(eager_fps, 2),
                    "mpixel_per_s": round(batched_fps * W * H / 1e6, 2),
                    "tuning": {k: tuning[k] for k in ("diffuse_tile", "diffuse_t", "score_hb", "score_chunk")}

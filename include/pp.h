@@ -67,10 +67,23 @@ typedef struct { float fx, fy, cx, cy; } pp_intrinsics;              /* pixels *
 typedef struct { int32_t width, height, pitch_px; } pp_frame_desc;   /* 3 <= w,h <= 16384; w*h <= 2^27 */
 
 enum { PP_EDGE_EXP = 0, PP_EDGE_RATIONAL = 1 };
+/* Discretisations of Eq. 1:
+ *  PP_DIFFUSE_EDGE4  per-edge flux over the 4-neighbourhood,
+ *                    I_p += lambda sum_q g(|I_q - I_p|) (I_q - I_p): conservative,
+ *                    zero flux into holes and across the border (the default);
+ *  PP_DIFFUSE_PIXEL  Alg. 1 as printed: c_p = g(|grad I_p|), the gradient from
+ *                    central differences (one-sided beside a hole or the border),
+ *                    I_p += lambda c_p sum_q (I_q - I_p) over valid 4-neighbours;
+ *  PP_DIFFUSE_EDGE8  per-edge flux over the 8-neighbourhood, diagonal edges at
+ *                    distance sqrt 2 with weight 1/2: I_p += lambda sum_q w_q
+ *                    g(|I_q - I_p| / d_q) (I_q - I_p). */
+enum { PP_DIFFUSE_EDGE4 = 0, PP_DIFFUSE_PIXEL = 1, PP_DIFFUSE_EDGE8 = 2 };
 /* Alg. 1 parameters: iterations N, step gamma (lambda), edge scale k (kappa, mm).
  * edge_stop PP_EDGE_EXP: g(x) = exp(-(x/kappa)^2) as Alg. 1 prints it;
- * PP_EDGE_RATIONAL: g(x) = 1/(1 + (x/kappa)^2).  0 < lambda <= 0.25, kappa > 0. */
-typedef struct { int32_t iters; float lambda; float kappa_mm; int32_t edge_stop; } pp_diffuse_params;
+ * PP_EDGE_RATIONAL: g(x) = 1/(1 + (x/kappa)^2) (Perona and Malik's second
+ * function).  kappa > 0; 0 < lambda <= 0.25 (EDGE4, PIXEL) or <= 1/6 (EDGE8),
+ * the bounds under which every step is a convex combination of neighbours. */
+typedef struct { int32_t iters; float lambda; float kappa_mm; int32_t edge_stop; int32_t scheme; } pp_diffuse_params;
 
 /* Inlier scoring arithmetic.  Every form decides |n.p + d| < t exactly as the
  * canonical FP32 residual fmaf(nx,x, fmaf(ny,y, fmaf(nz,z,d))) does, so all
@@ -160,8 +173,24 @@ pp_status pp_normals(pp_ctx* ctx, const float* depth_mm_dev, pp_frame_desc desc,
  * min_inliers, planes_dev[r] is written and labels_dev[F] = r, else the
  * frame stops.  Also stops with no valid hypothesis, after max_planes, or
  * with fewer than 3 points left.  labels_dev [h][pitch] int8 (-1 none);
- * n_planes_dev [1].  region_dev_or_null must be NULL (per-region mode is
- * not built: PP_E_UNSUPPORTED). */
+ * n_planes_dev [1].
+ *
+ * With region_dev_or_null [h][pitch] int16 set, region mode (Alg. 2 as
+ * printed; the labels stand for the polygon contours it takes): region g,
+ * 0 <= g < max_planes, is the row-major list of depth-valid pixels labelled g
+ * (other labels belong to no region).  Per region, hyps_per_plane hypotheses
+ * draw three distinct list positions (Philox4x64-10, key (seed, frame_id),
+ * counter (j, g, b, 1), position floor(w n_g / 2^64)); each scores
+ * error_j = sum of |n.p + d| over all the region's points and its inliers
+ * |n.p + d| < thresh_m; the first hypothesis with the smallest error is kept
+ * and stored iff inliers / n_g > 0.9 (10 inliers > 9 n_g).  planes_dev [g]
+ * (max_planes records) holds region g's kept model (the FP32 hypothesis
+ * plane, its inlier count, and the centroid of its inliers when stored);
+ * hyp_index is j when stored, -1 otherwise.  labels_dev = g on the inliers
+ * of stored regions, -1 elsewhere; n_planes_dev = regions stored.
+ * min_inliers and recheck_band_m are unused there; precision must be
+ * PP_SCORE_FP32 (else PP_E_UNSUPPORTED).  Scratch grows on first use per
+ * shape (may allocate and synchronise the device then). */
 pp_status pp_ransac_planes(pp_ctx* ctx, const float* points_dev, const uint8_t* valid_dev,
                            const int16_t* region_dev_or_null, pp_frame_desc desc, const pp_ransac_params* params,
                            pp_plane* planes_dev, int32_t* n_planes_dev, int8_t* labels_dev, void* hip_stream);
@@ -171,6 +200,27 @@ pp_status pp_ransac_planes_dbg(pp_ctx* ctx, const float* points_dev, const uint8
                                pp_frame_desc desc, const pp_ransac_params* params, pp_plane* planes_dev,
                                int32_t* n_planes_dev, int8_t* labels_dev, const pp_ransac_debug* dbg,
                                void* hip_stream);
+
+/* Region-mode introspection (device buffers; any may be NULL), R = max_planes,
+ * Hy = hyps_per_plane: npts [R] points per region; triples [R][Hy][3] list
+ * positions (-1 when fewer than three were drawn); hyps [R][Hy][4] FP32
+ * planes (d = NaN without a plane); errors [R][Hy] FP64 sums of |r|
+ * (+inf without a plane); counts [R][Hy] inliers; jstar [R] kept hypothesis
+ * (-1 none). */
+typedef struct {
+    int32_t* npts;
+    int32_t* triples;
+    float* hyps;
+    double* errors;
+    int32_t* counts;
+    int32_t* jstar;
+} pp_region_debug;
+
+/* Region-mode pp_ransac_planes (region_dev must not be NULL) that also fills *dbg. */
+pp_status pp_ransac_regions_dbg(pp_ctx* ctx, const float* points_dev, const uint8_t* valid_dev,
+                                const int16_t* region_dev, pp_frame_desc desc, const pp_ransac_params* params,
+                                pp_plane* planes_dev, int32_t* n_planes_dev, int8_t* labels_dev,
+                                const pp_region_debug* dbg, void* hip_stream);
 
 /* Score caller-given triples of pixel offsets (y*pitch+x) against every
  * depth-valid point: planes_dev [n][4] receives each triple's FP32 plane

@@ -15,13 +15,15 @@ from dataclasses import dataclass
 from typing import List, Optional, Sequence, Tuple
 
 from . import _native as N
-from ._native import (PP_EDGE_EXP, PP_EDGE_RATIONAL, PP_SCORE_BF16, PP_SCORE_FP16, PP_SCORE_FP32,  # noqa: F401
-                      PP_SCORE_MFMA_F32, LibraryMissing)
+from ._native import (PP_DIFFUSE_EDGE4, PP_DIFFUSE_EDGE8, PP_DIFFUSE_PIXEL, PP_EDGE_EXP,  # noqa: F401
+                      PP_EDGE_RATIONAL, PP_SCORE_BF16, PP_SCORE_FP16, PP_SCORE_FP32, PP_SCORE_MFMA_F32,
+                      LibraryMissing)
 
 __all__ = [
     "PPError", "Server", "Context", "RansacConfig", "DiffuseConfig", "default_context", "diffuse", "normals",
-    "ransac_planes", "ransac_planes_debug", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
-    "planes_to_numpy", "PP_SCORE_FP32", "PP_SCORE_MFMA_F32", "PP_SCORE_BF16", "PP_SCORE_FP16",
+    "ransac_planes", "ransac_planes_debug", "ransac_regions", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
+    "planes_to_numpy", "PP_DIFFUSE_EDGE4", "PP_DIFFUSE_PIXEL", "PP_DIFFUSE_EDGE8", "PP_SCORE_FP32",
+    "PP_SCORE_MFMA_F32", "PP_SCORE_BF16", "PP_SCORE_FP16",
 ]
 
 
@@ -37,9 +39,11 @@ class DiffuseConfig:
     lam: float = 0.2
     kappa_mm: float = 30.0
     edge_stop: int = PP_EDGE_EXP
+    scheme: int = PP_DIFFUSE_EDGE4
 
     def c(self) -> N.DiffuseParams:
-        return N.DiffuseParams(int(self.iters), float(self.lam), float(self.kappa_mm), int(self.edge_stop))
+        return N.DiffuseParams(int(self.iters), float(self.lam), float(self.kappa_mm), int(self.edge_stop),
+                               int(self.scheme))
 
 
 @dataclass
@@ -159,9 +163,10 @@ def _desc(H: int, W: int, pitch: Optional[int] = None) -> N.FrameDesc:
 
 
 def diffuse(depth, iters: int = 20, lam: float = 0.2, kappa_mm: float = 30.0, edge_stop: int = PP_EDGE_EXP,
-            out=None, ctx: Optional[Context] = None, stream=None):
+            out=None, ctx: Optional[Context] = None, stream=None, scheme: int = PP_DIFFUSE_EDGE4):
     """Step 1: Perona-Malik diffusion (Eq. 1, Alg. 1) of a [H][W] uint16/int16
-    depth tensor in mm -> float32 [H][W] mm (holes stay 0)."""
+    depth tensor in mm -> float32 [H][W] mm (holes stay 0).  scheme picks the
+    discretisation: PP_DIFFUSE_EDGE4 (default), PP_DIFFUSE_PIXEL, PP_DIFFUSE_EDGE8."""
     torch = _torch()
     _check_dev(depth, "depth", (torch.uint16, torch.int16))
     H, W = depth.shape
@@ -169,7 +174,7 @@ def diffuse(depth, iters: int = 20, lam: float = 0.2, kappa_mm: float = 30.0, ed
         out = torch.empty((H, W), dtype=torch.float32, device=depth.device)
     _check_dev(out, "out", (torch.float32,), (H, W))
     ctx = ctx or default_context(depth.device.index)
-    p = DiffuseConfig(iters, lam, kappa_mm, edge_stop).c()
+    p = DiffuseConfig(iters, lam, kappa_mm, edge_stop, scheme).c()
     ctx.check(N.lib().pp_diffuse(ctx.h, _ptr(depth), _ptr(out), _desc(H, W), ctypes.byref(p), _stream(stream)))
     return out
 
@@ -263,6 +268,44 @@ def ransac_planes_debug(points, valid, cfg: RansacConfig, ctx: Optional[Context]
     return planes, n_planes, labels, dbg_t
 
 
+def ransac_regions(points, valid, region, cfg: RansacConfig, planes=None, n_planes=None, labels=None,
+                   ctx: Optional[Context] = None, stream=None, debug: bool = False):
+    """Region-mode RANSAC (Alg. 2 as printed) over the regions 0..max_planes-1
+    of an int16 [H][W] label image: per region the hypothesis with the
+    smallest summed distance, stored iff more than 90 % of the region's points
+    are its inliers.  Returns (planes bytes [max_planes*64], n_planes, labels)
+    and, with debug=True, a dict of per-hypothesis tensors as well."""
+    torch = _torch()
+    _check_dev(points, "points", (torch.float32,))
+    _, H, W = points.shape
+    _check_dev(valid, "valid", (torch.uint8,), (H, W))
+    _check_dev(region, "region", (torch.int16,), (H, W))
+    dev = points.device
+    if planes is None:
+        planes, n_planes, labels = _ransac_outputs(H, W, cfg, dev)
+    ctx = ctx or default_context(dev.index)
+    p = cfg.c()
+    if not debug:
+        ctx.check(N.lib().pp_ransac_planes(ctx.h, _ptr(points), _ptr(valid), _ptr(region), _desc(H, W),
+                                           ctypes.byref(p), _ptr(planes), _ptr(n_planes), _ptr(labels),
+                                           _stream(stream)))
+        return planes, n_planes, labels
+    R, Hy = cfg.max_planes, cfg.hyps
+    dbg_t = dict(
+        npts=torch.zeros((R,), dtype=torch.int32, device=dev),
+        triples=torch.full((R, Hy, 3), -2, dtype=torch.int32, device=dev),
+        hyps=torch.zeros((R, Hy, 4), dtype=torch.float32, device=dev),
+        errors=torch.zeros((R, Hy), dtype=torch.float64, device=dev),
+        counts=torch.zeros((R, Hy), dtype=torch.int32, device=dev),
+        jstar=torch.zeros((R,), dtype=torch.int32, device=dev),
+    )
+    dbg = N.RegionDebug(*[_ptr(dbg_t[k]) for k in ("npts", "triples", "hyps", "errors", "counts", "jstar")])
+    ctx.check(N.lib().pp_ransac_regions_dbg(ctx.h, _ptr(points), _ptr(valid), _ptr(region), _desc(H, W),
+                                            ctypes.byref(p), _ptr(planes), _ptr(n_planes), _ptr(labels),
+                                            ctypes.byref(dbg), _stream(stream)))
+    return planes, n_planes, labels, dbg_t
+
+
 def score_triples(points, valid, triples, thresh_m: float, precision: int = PP_SCORE_FP32,
                   recheck_band_m: float = 0.0, ctx: Optional[Context] = None, stream=None):
     """Inlier counts of caller-given triples of pixel offsets over every
@@ -331,7 +374,7 @@ def run_frame(fo: FrameOutputs, ctx: Optional[Context] = None, stream=None):
     """The plain per-frame path: pp_diffuse, pp_normals, pp_ransac_planes on one stream."""
     H, W = fo.depth.shape
     diffuse(fo.depth, fo.diffuse.iters, fo.diffuse.lam, fo.diffuse.kappa_mm, fo.diffuse.edge_stop, out=fo.depth_mm,
-            ctx=ctx, stream=stream)
+            ctx=ctx, stream=stream, scheme=fo.diffuse.scheme)
     normals(fo.depth_mm, fo.K, fo.points, fo.normals, fo.valid, ctx=ctx, stream=stream)
     ransac_planes(fo.points, fo.valid, fo.ransac, fo.planes, fo.n_planes, fo.labels, ctx=ctx, stream=stream)
 

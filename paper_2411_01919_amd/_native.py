@@ -18,6 +18,7 @@ PP_E_INVAL, PP_E_NOMEM, PP_E_BUDGET, PP_E_HIP, PP_E_NODEVICE, PP_E_CLOSED, PP_E_
     -1, -2, -3, -4, -5, -6, -7, -8
 PP_E_AGAIN = -9
 PP_EDGE_EXP, PP_EDGE_RATIONAL = 0, 1
+PP_DIFFUSE_EDGE4, PP_DIFFUSE_PIXEL, PP_DIFFUSE_EDGE8 = 0, 1, 2
 PP_SCORE_FP32, PP_SCORE_MFMA_F32, PP_SCORE_BF16, PP_SCORE_FP16 = 0, 1, 2, 3
 
 
@@ -30,7 +31,7 @@ class FrameDesc(ctypes.Structure):
 
 
 class DiffuseParams(ctypes.Structure):
-    _fields_ = [("iters", c_i32), ("lam", c_f32), ("kappa_mm", c_f32), ("edge_stop", c_i32)]
+    _fields_ = [("iters", c_i32), ("lam", c_f32), ("kappa_mm", c_f32), ("edge_stop", c_i32), ("scheme", c_i32)]
 
 
 class RansacParams(ctypes.Structure):
@@ -45,6 +46,11 @@ class Plane(ctypes.Structure):
 class RansacDebug(ctypes.Structure):
     _fields_ = [("counts", c_vp), ("hyps", c_vp), ("triples", c_vp), ("round_info", c_vp), ("masks", c_vp),
                 ("valid_list", c_vp), ("n_valid", c_vp)]
+
+
+class RegionDebug(ctypes.Structure):
+    _fields_ = [("npts", c_vp), ("triples", c_vp), ("hyps", c_vp), ("errors", c_vp), ("counts", c_vp),
+                ("jstar", c_vp)]
 
 
 class FrameJob(ctypes.Structure):
@@ -84,6 +90,8 @@ SIGNATURES = {
     "pp_ransac_planes": (c_i32, [c_vp, c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp, c_vp, c_vp]),
     "pp_ransac_planes_dbg": (c_i32, [c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp, c_vp,
                                      ctypes.POINTER(RansacDebug), c_vp]),
+    "pp_ransac_regions_dbg": (c_i32, [c_vp, c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp,
+                                      c_vp, ctypes.POINTER(RegionDebug), c_vp]),
     "pp_debug_score_triples": (c_i32, [c_vp, c_vp, c_vp, FrameDesc, c_vp, c_i32, c_f32, c_i32, c_f32, c_vp, c_vp, c_vp]),
     "pp_validate_job": (c_i32, [ctypes.POINTER(FrameJob)]),
     "pp_batch_run": (c_i32, [c_vp, c_i32, ctypes.POINTER(FrameJob), c_vp]),

@@ -55,6 +55,8 @@ struct pp_ctx {
     std::map<std::string, GraphEntry> graphs;
     void* debug_scratch = nullptr;
     size_t debug_scratch_bytes = 0;
+    void* region_scratch = nullptr;
+    size_t region_scratch_bytes = 0;
     // stage timing: events around each round's scoring launch
     bool timing = false;
     hipEvent_t score_ev[ppk::kMaxRounds][2] = {};
@@ -91,7 +93,9 @@ bool desc_ok(const pp_frame_desc& d) {
 }
 
 bool diffuse_params_ok(const pp_diffuse_params* p) {
-    return p && p->iters >= 0 && p->iters <= 1000 && p->lambda > 0.f && p->lambda <= 0.25f && p->kappa_mm > 0.f &&
+    if (!p || p->scheme < PP_DIFFUSE_EDGE4 || p->scheme > PP_DIFFUSE_EDGE8) return false;
+    const float lam_max = p->scheme == PP_DIFFUSE_EDGE8 ? 1.0f / 6.0f : 0.25f;
+    return p->iters >= 0 && p->iters <= 1000 && p->lambda > 0.f && p->lambda <= lam_max && p->kappa_mm > 0.f &&
            isfinite(p->lambda) && (p->edge_stop == PP_EDGE_EXP || p->edge_stop == PP_EDGE_RATIONAL);
 }
 
@@ -109,7 +113,7 @@ bool intrinsics_ok(const pp_intrinsics& K) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t delta, L, list, hyp, triples, counts, partials, chunk_cnt, st, total;
+    size_t delta, L, list, abm, hyp, triples, counts, partials, chunk_cnt, st, total;
 };
 
 Layout slot_layout(size_t px, int hyps) {
@@ -120,6 +124,7 @@ Layout slot_layout(size_t px, int hyps) {
     l.delta = o; o += align256(2 * px * sizeof(float));
     l.L = o; o += align256(px * sizeof(int32_t));
     l.list = o; o += align256(2 * px * sizeof(float4));
+    l.abm = o; o += align256((px + 31) / 32 * sizeof(uint32_t));
     l.hyp = o; o += align256((size_t)hyps * sizeof(float4));
     l.triples = o; o += align256((size_t)hyps * 3 * sizeof(int32_t));
     l.counts = o; o += align256((size_t)hyps * sizeof(int32_t));
@@ -168,6 +173,7 @@ void bind_slot(const pp_ctx* c, int i, FrameDev& f) {
     f.L = reinterpret_cast<int32_t*>(b + l.L);
     f.list[0] = reinterpret_cast<float4*>(b + l.list);
     f.list[1] = f.list[0] + s.px_cap;
+    f.abm = reinterpret_cast<uint32_t*>(b + l.abm);
     f.hyp = reinterpret_cast<float4*>(b + l.hyp);
     f.triples = reinterpret_cast<int32_t*>(b + l.triples);
     f.counts = reinterpret_cast<int32_t*>(b + l.counts);
@@ -186,6 +192,7 @@ void fill_diffuse(FrameDev& f, const pp_diffuse_params& p) {
     f.iters = p.iters;
     f.lambda = p.lambda;
     f.edge_stop = p.edge_stop;
+    f.scheme = p.scheme;
     const double k2 = (double)p.kappa_mm * (double)p.kappa_mm;
     // exp(-(x/k)^2) = 2^(-x^2 log2(e)/k^2); as k -> inf the scale underflows to 0 and g == 1
     f.g_scale = (float)(p.edge_stop == PP_EDGE_RATIONAL ? 1.0 / k2 : 1.4426950408889634 / k2);
@@ -285,6 +292,7 @@ pp_status pp_ctx_destroy(pp_ctx* c) {
     if (c->plain_tab) (void)hipFree(c->plain_tab);
     if (c->batch_tab) (void)hipFree(c->batch_tab);
     if (c->debug_scratch) (void)hipFree(c->debug_scratch);
+    if (c->region_scratch) (void)hipFree(c->region_scratch);
     for (int i = 0; i < pp_ctx::kRing; ++i) {
         if (c->staging[i]) (void)hipHostFree(c->staging[i]);
         if (c->staging_ev[i]) (void)hipEventDestroy(c->staging_ev[i]);
@@ -415,7 +423,7 @@ pp_status pp_diffuse(pp_ctx* c, const uint16_t* depth_dev, float* out_mm_dev, pp
     f.dmm = out_mm_dev;
     hipStream_t st = (hipStream_t)stream;
     if ((s = put_plain(c, f, st)) != PP_OK) return s;
-    HIPCHK(c, ppk::launch_diffuse(c->plain_tab, 1, desc.width, desc.height, p->iters, c->tuning, st));
+    HIPCHK(c, ppk::launch_diffuse(c->plain_tab, 1, desc.width, desc.height, p->iters, p->scheme, c->tuning, st));
     return PP_OK;
 }
 
@@ -469,6 +477,61 @@ static pp_status ransac_common(pp_ctx* c, const float* points_dev, const uint8_t
     return PP_OK;
 }
 
+namespace {
+
+// Region mode: one frame, kernels of pp_regions.hip on library scratch that
+// grows on first use per shape.
+pp_status regions_common(pp_ctx* c, const float* points_dev, const uint8_t* valid_dev, const int16_t* region_dev,
+                         const pp_frame_desc& desc, const pp_ransac_params* p, pp_plane* planes_dev,
+                         int32_t* n_planes_dev, int8_t* labels_dev, const pp_region_debug* dbg, void* stream) {
+    if (p->precision != PP_SCORE_FP32)
+        return fail(c, PP_E_UNSUPPORTED, "region mode scores with the FP32 residual only");
+    pp_status s = set_device(c);
+    if (s != PP_OK) return s;
+    ppk::RegionDev r{};
+    r.pts = points_dev;
+    r.valid = valid_dev;
+    r.region = region_dev;
+    r.W = desc.width;
+    r.H = desc.height;
+    r.pitch = desc.pitch_px;
+    r.R = p->max_planes;
+    r.hyps = p->hyps_per_plane;
+    r.thresh = p->thresh_m;
+    r.seed = p->seed;
+    r.frame_id = p->frame_id;
+    r.planes = planes_dev;
+    r.n_planes = n_planes_dev;
+    r.labels = labels_dev;
+    const size_t need = ppk::region_scratch_bytes(r.W, r.H, r.R, r.hyps);
+    if (c->region_scratch_bytes < need) {
+        if (c->region_scratch) {
+            HIPCHK(c, hipDeviceSynchronize());
+            HIPCHK(c, hipFree(c->region_scratch));
+            c->region_scratch = nullptr;
+            c->region_scratch_bytes = 0;
+        }
+        HIPCHK(c, hipMalloc(&c->region_scratch, need));
+        c->region_scratch_bytes = need;
+    }
+    ppk::region_bind_scratch(r, c->region_scratch);
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, ppk::launch_regions(r, st));
+    if (dbg) {
+        const size_t R = r.R, rh = (size_t)r.R * r.hyps;
+        if (dbg->npts) HIPCHK(c, hipMemcpyAsync(dbg->npts, r.npts, R * 4, hipMemcpyDeviceToDevice, st));
+        if (dbg->triples)
+            HIPCHK(c, hipMemcpyAsync(dbg->triples, r.triples, rh * 12, hipMemcpyDeviceToDevice, st));
+        if (dbg->hyps) HIPCHK(c, hipMemcpyAsync(dbg->hyps, r.hyp, rh * 16, hipMemcpyDeviceToDevice, st));
+        if (dbg->errors) HIPCHK(c, hipMemcpyAsync(dbg->errors, r.errors, rh * 8, hipMemcpyDeviceToDevice, st));
+        if (dbg->counts) HIPCHK(c, hipMemcpyAsync(dbg->counts, r.counts, rh * 4, hipMemcpyDeviceToDevice, st));
+        if (dbg->jstar) HIPCHK(c, hipMemcpyAsync(dbg->jstar, r.jstar, R * 4, hipMemcpyDeviceToDevice, st));
+    }
+    return PP_OK;
+}
+
+}  // namespace
+
 pp_status pp_ransac_planes(pp_ctx* c, const float* points_dev, const uint8_t* valid_dev,
                            const int16_t* region_dev_or_null, pp_frame_desc desc, const pp_ransac_params* p,
                            pp_plane* planes_dev, int32_t* n_planes_dev, int8_t* labels_dev, void* stream) {
@@ -477,8 +540,23 @@ pp_status pp_ransac_planes(pp_ctx* c, const float* points_dev, const uint8_t* va
     if (!points_dev || !valid_dev || !planes_dev || !n_planes_dev || !labels_dev || !desc_ok(desc) ||
         !ransac_params_ok(p))
         return fail(c, PP_E_INVAL, "pp_ransac_planes: bad argument");
-    if (region_dev_or_null) return fail(c, PP_E_UNSUPPORTED, "per-region RANSAC is not built");
+    if (region_dev_or_null)
+        return regions_common(c, points_dev, valid_dev, region_dev_or_null, desc, p, planes_dev, n_planes_dev,
+                              labels_dev, nullptr, stream);
     return ransac_common(c, points_dev, valid_dev, desc, p, planes_dev, n_planes_dev, labels_dev, nullptr, stream);
+}
+
+pp_status pp_ransac_regions_dbg(pp_ctx* c, const float* points_dev, const uint8_t* valid_dev,
+                                const int16_t* region_dev, pp_frame_desc desc, const pp_ransac_params* p,
+                                pp_plane* planes_dev, int32_t* n_planes_dev, int8_t* labels_dev,
+                                const pp_region_debug* dbg, void* stream) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if (!points_dev || !valid_dev || !region_dev || !planes_dev || !n_planes_dev || !labels_dev ||
+        !desc_ok(desc) || !ransac_params_ok(p) || !dbg)
+        return fail(c, PP_E_INVAL, "pp_ransac_regions_dbg: bad argument");
+    return regions_common(c, points_dev, valid_dev, region_dev, desc, p, planes_dev, n_planes_dev, labels_dev, dbg,
+                          stream);
 }
 
 pp_status pp_ransac_planes_dbg(pp_ctx* c, const float* points_dev, const uint8_t* valid_dev, pp_frame_desc desc,
@@ -553,8 +631,8 @@ bool job_ok(const pp_frame_job& j) {
 struct BatchPlan {
     int nf = 0, maxW = 0, maxH = 0, max_px = 0, max_hyps = 0, max_rounds = 0, precision = 0;
     std::vector<int> order;                        // table position -> job index
-    std::vector<std::pair<int, int>> iter_groups;  // (first table position, count) with equal iterations
-    std::vector<int> group_iters;
+    std::vector<std::pair<int, int>> iter_groups;  // (first table position, count): equal iterations and scheme
+    std::vector<int> group_iters, group_scheme;
     std::string key;
 };
 
@@ -564,8 +642,10 @@ BatchPlan plan_batch(const pp_frame_job* jobs, int n, const ppk::Tuning& tu) {
     b.precision = jobs[0].ransac.precision;
     b.order.resize(n);
     for (int i = 0; i < n; ++i) b.order[i] = i;
-    std::stable_sort(b.order.begin(), b.order.end(),
-                     [&](int a, int c) { return jobs[a].diffuse.iters < jobs[c].diffuse.iters; });
+    std::stable_sort(b.order.begin(), b.order.end(), [&](int a, int c) {
+        const pp_diffuse_params &pa = jobs[a].diffuse, &pc = jobs[c].diffuse;
+        return pa.scheme != pc.scheme ? pa.scheme < pc.scheme : pa.iters < pc.iters;
+    });
     for (int i = 0; i < n; ++i) {
         const pp_frame_job& j = jobs[b.order[i]];
         b.maxW = std::max(b.maxW, j.desc.width);
@@ -573,9 +653,11 @@ BatchPlan plan_batch(const pp_frame_job* jobs, int n, const ppk::Tuning& tu) {
         b.max_px = std::max(b.max_px, j.desc.width * j.desc.height);
         b.max_hyps = std::max(b.max_hyps, j.ransac.hyps_per_plane);
         b.max_rounds = std::max(b.max_rounds, j.ransac.max_planes);
-        if (i == 0 || j.diffuse.iters != jobs[b.order[i - 1]].diffuse.iters) {
+        if (i == 0 || j.diffuse.iters != jobs[b.order[i - 1]].diffuse.iters ||
+            j.diffuse.scheme != jobs[b.order[i - 1]].diffuse.scheme) {
             b.iter_groups.push_back({i, 0});
             b.group_iters.push_back(j.diffuse.iters);
+            b.group_scheme.push_back(j.diffuse.scheme);
         }
         b.iter_groups.back().second++;
     }
@@ -584,7 +666,8 @@ BatchPlan plan_batch(const pp_frame_job* jobs, int n, const ppk::Tuning& tu) {
              b.max_rounds, b.precision, tu.diffuse_tile, tu.diffuse_t, tu.score_hb, tu.score_chunk);
     b.key = buf;
     for (size_t g = 0; g < b.iter_groups.size(); ++g) {
-        snprintf(buf, sizeof buf, " g%d:%d:%d", b.iter_groups[g].first, b.iter_groups[g].second, b.group_iters[g]);
+        snprintf(buf, sizeof buf, " g%d:%d:%d:%d", b.iter_groups[g].first, b.iter_groups[g].second, b.group_iters[g],
+                 b.group_scheme[g]);
         b.key += buf;
     }
     return b;
@@ -595,7 +678,7 @@ pp_status enqueue_batch(pp_ctx* c, const BatchPlan& b, hipStream_t st, bool capt
     if (timed) HIPCHK(c, hipEventRecord(c->stage_ev[0], st));
     for (size_t g = 0; g < b.iter_groups.size(); ++g)
         HIPCHK(c, ppk::launch_diffuse(c->batch_tab + b.iter_groups[g].first, b.iter_groups[g].second, b.maxW, b.maxH,
-                                      b.group_iters[g], c->tuning, st));
+                                      b.group_iters[g], b.group_scheme[g], c->tuning, st));
     if (timed) HIPCHK(c, hipEventRecord(c->stage_ev[1], st));
     HIPCHK(c, ppk::launch_normals(c->batch_tab, b.nf, b.maxW, b.maxH, st));
     HIPCHK(c, ppk::launch_valid_list(c->batch_tab, b.nf, b.max_px, st));

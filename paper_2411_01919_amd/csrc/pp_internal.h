@@ -51,6 +51,7 @@ struct FrameDev {
     float lambda;
     float g_scale;           // exp form: log2(e)/kappa^2 ; rational: 1/kappa^2
     int32_t edge_stop;
+    int32_t scheme;  // PP_DIFFUSE_*
     // RANSAC
     int32_t max_planes, hyps, min_inliers, precision;
     float thresh, band;
@@ -58,7 +59,8 @@ struct FrameDev {
     // library scratch
     float* delta[2];         // [H][W] diffusion ping-pong (delta = I - I0)
     int32_t* L;              // [W*H] valid list (pixel offsets y*pitch+x)
-    float4* list[2];         // [W*H] remaining points (x, y, z, offset bits)
+    float4* list[2];         // [W*H] remaining points (x, y, z, valid-list position bits)
+    uint32_t* abm;           // [ceil(W*H/32)] bit k set iff the point at valid-list position k is assigned
     float4* hyp;             // [hyps] (n, d); d = NaN when invalid
     int32_t* triples;        // [hyps][3]
     int32_t* counts;         // [hyps]
@@ -88,7 +90,7 @@ bool t_supported(int t);
 
 // Launchers (all asynchronous on `s`).  `tab` is a device array of nf frames;
 // the *max* arguments bound the per-frame sizes and size the grids.
-hipError_t launch_diffuse(const FrameDev* tab, int nf, int maxW, int maxH, int iters_max,
+hipError_t launch_diffuse(const FrameDev* tab, int nf, int maxW, int maxH, int iters_max, int scheme,
                           const Tuning& tu, hipStream_t s);
 hipError_t launch_normals(const FrameDev* tab, int nf, int maxW, int maxH, hipStream_t s);
 hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, hipStream_t s);
@@ -98,6 +100,43 @@ hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_
 hipError_t launch_hyp_from_triples(const FrameDev* tab, const int32_t* triples, int n, hipStream_t s);
 hipError_t launch_score_only(const FrameDev* tab, int max_px, int n, int precision, const Tuning& tu,
                              hipStream_t s);
+
+// Region mode (Alg. 2 as printed): one frame per call, plain calls only.
+constexpr int kRegionPxChunk = 4096;  // pixels per list-building block
+constexpr int kRegionChunk = 512;     // region points per scoring block
+
+struct RegionDev {
+    const float* pts;        // [3][H][pitch]
+    const uint8_t* valid;    // [H][pitch] bit0: depth
+    const int16_t* region;   // [H][pitch] region labels
+    int32_t W, H, pitch;
+    int32_t R, hyps, nb;     // regions, hypotheses per region, list-building blocks
+    float thresh;
+    int32_t pad;
+    uint64_t seed, frame_id;
+    // scratch (region_bind_scratch)
+    int32_t* bcnt;           // [nb][R] points per (block, region), then list positions
+    int32_t* off;            // [R+1] first list position of each region
+    int32_t* choff;          // [R+1] first scoring chunk of each region
+    int32_t* npts;           // [R]
+    int32_t* list;           // [W*H] pixel offsets grouped by region, row-major within
+    float4* hyp;             // [R][hyps] FP32 planes (n, d); d = NaN without a plane
+    int32_t* triples;        // [R][hyps][3] list positions (-1: fewer than 3 drawn)
+    double* errp;            // [chunks][hyps] per-chunk sums of |r|
+    int32_t* counts;         // [R][hyps]
+    double* errors;          // [R][hyps]
+    int32_t* jstar;          // [R]
+    // caller outputs
+    pp_plane* planes;        // [R]
+    int32_t* n_planes;
+    int8_t* labels;          // [H][pitch]
+};
+
+int region_blocks(int W, int H);
+int region_max_chunks(int W, int H, int R);
+size_t region_bind_scratch(RegionDev& r, void* scratch);  // returns the bytes used
+size_t region_scratch_bytes(int W, int H, int R, int hyps);
+hipError_t launch_regions(const RegionDev& r, hipStream_t s);
 
 // Library scratch one frame needs (the server carves it from its arena), and
 // a batch run whose frame slots use caller-provided scratch (scratch[i] for

@@ -15,144 +15,10 @@
 
 #include <math.h>
 
+#include "pp_device.h"
 #include "pp_internal.h"
 
 namespace ppk {
-
-// ------------------------------------------------------------------ helpers
-__device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long w = __shfl_xor(v, o);
-        v = v > w ? v : w;
-    }
-    return v;
-}
-
-// Sum over the 256 threads of a block; every thread gets the total.
-__device__ __forceinline__ int block_sum(int v, int* sh) {
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    __syncthreads();
-    if (l == 0) sh[w] = v;
-    __syncthreads();
-    return sh[0] + sh[1] + sh[2] + sh[3];
-}
-
-__device__ __forceinline__ unsigned long long lanemask_lt() {
-    const unsigned l = threadIdx.x & 63;
-    return l ? (~0ull >> (64 - l)) : 0ull;
-}
-
-// Stable compaction step for 256 candidates (one per thread): returns this
-// thread's rank among the flagged threads before it; *total gets the count.
-__device__ __forceinline__ int block_rank(bool flag, int* sh, int* total) {
-    const unsigned long long m = __ballot(flag);
-    const int w = threadIdx.x >> 6;
-    const int in_wave = __popcll(m & lanemask_lt());
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[w] = __popcll(m);
-    __syncthreads();
-    int before = 0;
-    for (int i = 0; i < w; ++i) before += sh[i];
-    *total = sh[0] + sh[1] + sh[2] + sh[3];
-    return before + in_wave;
-}
-
-// The canonical FP32 residual n.p + d of a hypothesis plane.  Every scorer
-// and the refit decide |r| < t with exactly this expression.
-__device__ __forceinline__ float canon_res(const float4 h, float x, float y, float z) {
-    return fmaf(h.x, x, fmaf(h.y, y, fmaf(h.z, z, h.w)));
-}
-
-// Refit planes are FP64; their inlier test evaluates n.p + d for FP32 points
-// in compensated FP32 (hi/lo split plane, error-free products, two-sum), which
-// is accurate to ~2^-44 of the largest term.
-struct SplitPlane {
-    float hx, hy, hz, hd, lx, ly, lz, ld;
-};
-
-__device__ __forceinline__ SplitPlane split_plane(const double* p) {
-    SplitPlane s;
-    s.hx = (float)p[0]; s.lx = (float)(p[0] - (double)s.hx);
-    s.hy = (float)p[1]; s.ly = (float)(p[1] - (double)s.hy);
-    s.hz = (float)p[2]; s.lz = (float)(p[2] - (double)s.hz);
-    s.hd = (float)p[3]; s.ld = (float)(p[3] - (double)s.hd);
-    return s;
-}
-
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-    s = a + b;
-    const float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-
-__device__ __forceinline__ float refit_res(const SplitPlane& q, float x, float y, float z) {
-    const float p0 = q.hx * x, e0 = fmaf(q.hx, x, -p0);
-    const float p1 = q.hy * y, e1 = fmaf(q.hy, y, -p1);
-    const float p2 = q.hz * z, e2 = fmaf(q.hz, z, -p2);
-    float s, t0, t1, t2;
-    two_sum(q.hd, p0, s, t0);
-    two_sum(s, p1, s, t1);
-    two_sum(s, p2, s, t2);
-    const float small = ((q.ld + (e0 + e1 + e2)) + (t0 + t1 + t2)) + (q.lx * x + q.ly * y + q.lz * z);
-    return s + small;
-}
-
-// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
-// 64x64->128 multiplies with the published constants, key bumped by the
-// published Weyl increments between rounds.
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += W0;
-            k1 += W1;
-        }
-        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-        const uint64_t a = hi1 ^ c[1] ^ k0, b = hi0 ^ c[3] ^ k1;
-        c[0] = a;
-        c[1] = lo1;
-        c[2] = b;
-        c[3] = lo0;
-    }
-}
-
-// FP32 plane through three points (Alg. 2 "fit plane model"): n = e1 x e2
-// normalised, d = -n.p0, camera-facing (d >= 0); degenerate when
-// |e1 x e2| <= 1e-3 |e1||e2|, returned as d = NaN (never an inlier).
-__device__ __forceinline__ float4 plane_from_points(float3 p0, float3 p1, float3 p2) {
-    const float e1x = p1.x - p0.x, e1y = p1.y - p0.y, e1z = p1.z - p0.z;
-    const float e2x = p2.x - p0.x, e2y = p2.y - p0.y, e2z = p2.z - p0.z;
-    const float mx = e1y * e2z - e1z * e2y;
-    const float my = e1z * e2x - e1x * e2z;
-    const float mz = e1x * e2y - e1y * e2x;
-    const float mn = sqrtf(mx * mx + my * my + mz * mz);
-    const float l1 = sqrtf(e1x * e1x + e1y * e1y + e1z * e1z);
-    const float l2 = sqrtf(e2x * e2x + e2y * e2y + e2z * e2z);
-    if (!(mn > 1e-3f * l1 * l2)) return make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
-    float nx = mx / mn, ny = my / mn, nz = mz / mn;
-    float d = -(nx * p0.x + ny * p0.y + nz * p0.z);
-    if (d < 0.f) {
-        nx = -nx; ny = -ny; nz = -nz; d = -d;
-    }
-    return make_float4(nx, ny, nz, d);
-}
 
 __device__ __forceinline__ float3 load_point(const FrameDev& f, int off) {
     const size_t plane = (size_t)f.H * f.pitch;
@@ -163,10 +29,14 @@ __device__ __forceinline__ bool hyp_valid(const float4 h) { return h.w == h.w; }
 
 // ------------------------------------------------------------------ diffusion
 // One pass = `it` (<= T) explicit iterations on a TX x TY tile whose LDS copy
-// carries a T-pixel halo; iteration k updates the tile grown by T - it + k
-// ... T - k pixels, so the last one is exact on the tile.  The iterate is kept
-// as delta = I - I0 with I0 the integer input: edge differences are
-// (I0_q - I0_p) + (delta_q - delta_p), the first term exact in FP32.
+// carries a T-pixel halo.  Iteration k updates the tile grown by T - k (for
+// it == T) pixels, so the last one is exact on the tile.  The iterate is kept
+// as delta = I - I0 with I0 the integer input, so the integer part of every
+// edge difference, (I0_q - I0_p), is exact and loop-invariant (precomputed).
+// Each iteration first computes every edge's flux once, g(D) D with
+// D = I_q - I_p, for the east and south edge of each pixel (zero across the
+// border and into holes), then every pixel adds lam times the fluxes of its
+// four edges: the flux leaves one pixel exactly as it enters the other.
 template <int TX, int TY, int T>
 __global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__ tab, int it, int first, int last,
                                                      int src, int dst) {
@@ -175,8 +45,11 @@ __global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
     if (x0 >= W || y0 >= H) return;
     constexpr int EW = TX + 2 * T, EH = TY + 2 * T, EN = EW * EH;
+    constexpr int NPT = (EN + kBlock - 1) / kBlock;  // extended pixels per thread
     __shared__ float s_i0[EN];
-    __shared__ float s_d[2][EN];
+    __shared__ float s_d[EN];
+    __shared__ float s_fe[EN];  // flux over the east edge of each pixel
+    __shared__ float s_fs[EN];  // flux over the south edge
     const float* __restrict__ din = f.delta[src];
     for (int e = threadIdx.x; e < EN; e += kBlock) {
         const int ex = e % EW, ey = e / EW;
@@ -187,36 +60,64 @@ __global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__
             if (!first && i0 > 0.f) d = din[(size_t)y * W + x];
         }
         s_i0[e] = i0;
-        s_d[0][e] = d;
-        s_d[1][e] = d;
+        s_d[e] = d;
+        s_fe[e] = 0.f;
+        s_fs[e] = 0.f;
     }
     __syncthreads();
+    // loop-invariant edge data of this thread's pixels
+    float dIe[NPT], dIs[NPT];
+    bool ve[NPT], vs[NPT], vp[NPT];
+    int exy[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        const int e = threadIdx.x + q * kBlock;
+        const int ex = e % EW, ey = e / EW;
+        exy[q] = (ex << 16) | ey;
+        vp[q] = false; ve[q] = false; vs[q] = false; dIe[q] = 0.f; dIs[q] = 0.f;
+        if (e < EN) {
+            const float i0 = s_i0[e];
+            vp[q] = i0 > 0.f;
+            if (ex + 1 < EW) { const float q0 = s_i0[e + 1]; ve[q] = vp[q] && q0 > 0.f; dIe[q] = q0 - i0; }
+            if (ey + 1 < EH) { const float q0 = s_i0[e + EW]; vs[q] = vp[q] && q0 > 0.f; dIs[q] = q0 - i0; }
+        }
+    }
     const float lam = f.lambda, gs = f.g_scale;
     const bool rational = f.edge_stop == PP_EDGE_RATIONAL;
-    int cur = 0;
     for (int k = 1; k <= it; ++k) {
-        const int s = T - it + k;
-        for (int e = threadIdx.x; e < EN; e += kBlock) {
-            const int ex = e % EW, ey = e / EW;
-            if (ex < s || ex >= EW - s || ey < s || ey >= EH - s) continue;
-            const float i0 = s_i0[e];
-            if (!(i0 > 0.f)) continue;
-            const float dc = s_d[cur][e];
-            float flux = 0.f;
-            const int nb[4] = {e - 1, e + 1, e - EW, e + EW};
+        const int s = T - it + k;  // pixels updated this iteration: [s, EW - s) x [s, EH - s)
+        // fluxes of the edges those pixels touch
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float iq = s_i0[nb[q]];
-                if (!(iq > 0.f)) continue;  // no flux into holes or across the border
-                const float delta = (iq - i0) + (s_d[cur][nb[q]] - dc);
-                const float a = delta * delta * gs;
-                const float g = rational ? 1.0f / (1.0f + a) : exp2f(-a);
-                flux += g * delta;
+        for (int q = 0; q < NPT; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            const int ex = exy[q] >> 16, ey = exy[q] & 0xFFFF;
+            if (e >= EN || ex < s - 1 || ex >= EW - s || ey < s - 1 || ey >= EH - s) continue;
+            const float dp = s_d[e];
+            if (ve[q] && ey >= s) {
+                const float D = dIe[q] + (s_d[e + 1] - dp);
+                const float a = D * D * gs;
+                s_fe[e] = (rational ? 1.0f / (1.0f + a) : exp2f(-a)) * D;
             }
-            s_d[cur ^ 1][e] = dc + lam * flux;
+            if (vs[q] && ex >= s) {
+                const float D = dIs[q] + (s_d[e + EW] - dp);
+                const float a = D * D * gs;
+                s_fs[e] = (rational ? 1.0f / (1.0f + a) : exp2f(-a)) * D;
+            }
         }
         __syncthreads();
-        cur ^= 1;
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            const int e = threadIdx.x + q * kBlock;
+            const int ex = exy[q] >> 16, ey = exy[q] & 0xFFFF;
+            if (e >= EN || !vp[q] || ex < s || ex >= EW - s || ey < s || ey >= EH - s) continue;
+            // fluxes into holes or across the border are zero: their slots were never written
+            const float fe = ve[q] ? s_fe[e] : 0.f;
+            const float fw = s_i0[e - 1] > 0.f ? s_fe[e - 1] : 0.f;
+            const float fs = vs[q] ? s_fs[e] : 0.f;
+            const float fn = s_i0[e - EW] > 0.f ? s_fs[e - EW] : 0.f;
+            s_d[e] = s_d[e] + lam * ((fe - fw) + (fs - fn));
+        }
+        __syncthreads();
     }
     float* __restrict__ dout = f.delta[dst];
     for (int e = threadIdx.x; e < TX * TY; e += kBlock) {
@@ -225,7 +126,132 @@ __global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__
         if (x >= W || y >= H) continue;
         const int ee = (ty + T) * EW + (tx + T);
         const float i0 = s_i0[ee];
-        const float d = i0 > 0.f ? s_d[cur][ee] : 0.f;
+        const float d = i0 > 0.f ? s_d[ee] : 0.f;
+        if (last)
+            f.dmm[(size_t)y * f.pitch + x] = i0 > 0.f ? i0 + d : 0.f;
+        else
+            dout[(size_t)y * W + x] = d;
+    }
+}
+
+// Other discretisations of Eq. 1, on the same tiling, temporal blocking and
+// delta form as k_diffuse (fixed 64 x 16 tiles, up to kVarT iterations a pass):
+//  PP_DIFFUSE_PIXEL  Alg. 1 as printed.  Each pixel takes c_p = g(|grad I_p|),
+//                    the gradient from central differences, or a one-sided
+//                    difference when only one neighbour along that axis is
+//                    valid (0 with none), and adds lam c_p times the sum of
+//                    (I_q - I_p) over its valid 4-neighbours.  A pixel's update
+//                    is computed from the old image first (s_u), then applied.
+//  PP_DIFFUSE_EDGE8  per-edge fluxes over the 8-neighbourhood.  Each pixel owns
+//                    its E, S, SE and SW edge; a diagonal flux is
+//                    1/2 g(|D| / sqrt 2) D.  Every flux is computed once and
+//                    enters both of its pixels with opposite signs.
+constexpr int kVarTX = 64, kVarTY = 16, kVarT = 5;
+
+__device__ __forceinline__ float edge_g(float a, bool rational) { return rational ? 1.0f / (1.0f + a) : exp2f(-a); }
+
+template <int SCHEME>
+__global__ __launch_bounds__(kBlock) void k_diffuse_var(const FrameDev* __restrict__ tab, int it, int first, int last,
+                                                        int src, int dst) {
+    constexpr int TX = kVarTX, TY = kVarTY, T = kVarT;
+    constexpr int EW = TX + 2 * T, EH = TY + 2 * T, EN = EW * EH;
+    constexpr int NA = SCHEME == PP_DIFFUSE_EDGE8 ? 4 : 1;  // per-pixel work arrays
+    const FrameDev& f = tab[blockIdx.z];
+    const int W = f.W, H = f.H;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    if (x0 >= W || y0 >= H) return;
+    __shared__ float s_i0[EN];
+    __shared__ float s_d[EN];
+    __shared__ float s_a[NA][EN];  // PIXEL: the update; EDGE8: E, S, SE, SW fluxes
+    const float* __restrict__ din = f.delta[src];
+    for (int e = threadIdx.x; e < EN; e += kBlock) {
+        const int x = x0 - T + e % EW, y = y0 - T + e / EW;
+        float i0 = 0.f, d = 0.f;
+        if (x >= 0 && x < W && y >= 0 && y < H) {
+            i0 = (float)f.depth[(size_t)y * f.pitch + x];
+            if (!first && i0 > 0.f) d = din[(size_t)y * W + x];
+        }
+        s_i0[e] = i0;
+        s_d[e] = d;
+    }
+    __syncthreads();
+    const float lam = f.lambda, gs = f.g_scale;
+    const bool rational = f.edge_stop == PP_EDGE_RATIONAL;
+    for (int k = 1; k <= it; ++k) {
+        const int s = T - it + k;  // pixels updated this iteration: [s, EW - s) x [s, EH - s)
+        for (int e = threadIdx.x; e < EN; e += kBlock) {
+            const int ex = e % EW, ey = e / EW;
+            if (SCHEME == PP_DIFFUSE_PIXEL) {
+                if (ex < s || ex >= EW - s || ey < s || ey >= EH - s) continue;
+                const float i0 = s_i0[e];
+                if (!(i0 > 0.f)) continue;
+                const float dp = s_d[e];
+                // differences I_q - I_p of the four neighbours (integer part exact)
+                const bool ve = s_i0[e + 1] > 0.f, vw = s_i0[e - 1] > 0.f;
+                const bool vs = s_i0[e + EW] > 0.f, vn = s_i0[e - EW] > 0.f;
+                const float De = ve ? (s_i0[e + 1] - i0) + (s_d[e + 1] - dp) : 0.f;
+                const float Dw = vw ? (s_i0[e - 1] - i0) + (s_d[e - 1] - dp) : 0.f;
+                const float Ds = vs ? (s_i0[e + EW] - i0) + (s_d[e + EW] - dp) : 0.f;
+                const float Dn = vn ? (s_i0[e - EW] - i0) + (s_d[e - EW] - dp) : 0.f;
+                const float gx = ve && vw ? 0.5f * ((s_i0[e + 1] - s_i0[e - 1]) + (s_d[e + 1] - s_d[e - 1]))
+                                          : (De - Dw);
+                const float gy = vs && vn ? 0.5f * ((s_i0[e + EW] - s_i0[e - EW]) + (s_d[e + EW] - s_d[e - EW]))
+                                          : (Ds - Dn);
+                const float c = edge_g((gx * gx + gy * gy) * gs, rational);
+                s_a[0][e] = lam * c * ((De + Dw) + (Ds + Dn));
+            } else {
+                // fluxes of edges whose both pixels hold this iteration's input: [s-1, EW-s+1)^2
+                if (ex < s - 1 || ex >= EW - s + 1 || ey < s - 1 || ey >= EH - s + 1) continue;
+                const float i0 = s_i0[e], dp = s_d[e];
+                const bool vp = i0 > 0.f;
+                float fE = 0.f, fS = 0.f, fSE = 0.f, fSW = 0.f;
+                if (vp && ex < EW - s && s_i0[e + 1] > 0.f) {
+                    const float D = (s_i0[e + 1] - i0) + (s_d[e + 1] - dp);
+                    fE = edge_g(D * D * gs, rational) * D;
+                }
+                if (vp && ey < EH - s) {
+                    if (s_i0[e + EW] > 0.f) {
+                        const float D = (s_i0[e + EW] - i0) + (s_d[e + EW] - dp);
+                        fS = edge_g(D * D * gs, rational) * D;
+                    }
+                    if (ex < EW - s && s_i0[e + EW + 1] > 0.f) {
+                        const float D = (s_i0[e + EW + 1] - i0) + (s_d[e + EW + 1] - dp);
+                        fSE = 0.5f * edge_g(0.5f * D * D * gs, rational) * D;
+                    }
+                    if (ex >= s && s_i0[e + EW - 1] > 0.f) {
+                        const float D = (s_i0[e + EW - 1] - i0) + (s_d[e + EW - 1] - dp);
+                        fSW = 0.5f * edge_g(0.5f * D * D * gs, rational) * D;
+                    }
+                }
+                s_a[0][e] = fE;
+                s_a[NA > 1 ? 1 : 0][e] = fS;
+                s_a[NA > 2 ? 2 : 0][e] = fSE;
+                s_a[NA > 3 ? 3 : 0][e] = fSW;
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < EN; e += kBlock) {
+            const int ex = e % EW, ey = e / EW;
+            if (ex < s || ex >= EW - s || ey < s || ey >= EH - s || !(s_i0[e] > 0.f)) continue;
+            if (SCHEME == PP_DIFFUSE_PIXEL) {
+                s_d[e] += s_a[0][e];
+            } else {
+                const float sum = (s_a[0][e] - s_a[0][e - 1]) + (s_a[NA > 1 ? 1 : 0][e] - s_a[NA > 1 ? 1 : 0][e - EW]) +
+                                  ((s_a[NA > 2 ? 2 : 0][e] - s_a[NA > 2 ? 2 : 0][e - EW - 1]) +
+                                   (s_a[NA > 3 ? 3 : 0][e] - s_a[NA > 3 ? 3 : 0][e - EW + 1]));
+                s_d[e] += lam * sum;
+            }
+        }
+        __syncthreads();
+    }
+    float* __restrict__ dout = f.delta[dst];
+    for (int e = threadIdx.x; e < TX * TY; e += kBlock) {
+        const int tx = e % TX, ty = e / TX;
+        const int x = x0 + tx, y = y0 + ty;
+        if (x >= W || y >= H) continue;
+        const int ee = (ty + T) * EW + (tx + T);
+        const float i0 = s_i0[ee];
+        const float d = i0 > 0.f ? s_d[ee] : 0.f;
         if (last)
             f.dmm[(size_t)y * f.pitch + x] = i0 > 0.f ? i0 + d : 0.f;
         else
@@ -325,6 +351,8 @@ __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restri
     const int npx = f.W * f.H;
     const int nch = (npx + kValidChunk - 1) / kValidChunk;
     if (blockIdx.x == 0 && threadIdx.x == 0) f.st->p1max_bits = 0u;
+    const int nwords = (npx + 31) >> 5;
+    for (int w = blockIdx.x * kBlock + threadIdx.x; w < nwords; w += gridDim.x * kBlock) f.abm[w] = 0u;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         int cnt = 0;
         for (int i = threadIdx.x; i < kValidChunk; i += kBlock) {
@@ -341,6 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restri
 
 __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __restrict__ tab) {
     __shared__ int sh[4];
+    __shared__ float shf[4];
     const FrameDev& f = tab[blockIdx.z];
     const int npx = f.W * f.H;
     const int nch = (npx + kValidChunk - 1) / kValidChunk;
@@ -350,6 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
         for (int i = threadIdx.x; i < c; i += kBlock) before += f.chunk_cnt[i];
         before = block_sum(before, sh);
         int run = before;
+        float p1 = 0.f;
         for (int s = 0; s < kValidChunk; s += kBlock) {
             const int p = c * kValidChunk + s + threadIdx.x;
             bool v = false;
@@ -362,20 +392,26 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
             }
             int tot;
             const int rank = block_rank(v, sh, &tot);
-            float p1 = 0.f;
             if (v) {
                 const int k = run + rank;
-                const float4 q = make_float4(f.pts[off], f.pts[plane + off], f.pts[2 * plane + off], __int_as_float(off));
+                const float4 q = make_float4(f.pts[off], f.pts[plane + off], f.pts[2 * plane + off], __int_as_float(k));
                 f.L[k] = off;
                 f.list[0][k] = q;
                 if (f.dbg.valid_list) f.dbg.valid_list[k] = off;
-                p1 = fabsf(q.x) + fabsf(q.y) + fabsf(q.z);
+                p1 = fmaxf(p1, fabsf(q.x) + fabsf(q.y) + fabsf(q.z));
             }
-            // frame-wide bound on |p|_1 for the recheck bands of the matrix-core scorers
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) p1 = fmaxf(p1, __shfl_xor(p1, o));
-            if ((threadIdx.x & 63) == 0 && p1 > 0.f) atomicMax(&f.st->p1max_bits, __float_as_uint(p1));
             run += tot;
+        }
+        // frame-wide bound on |p|_1 for the recheck bands of the matrix-core scorers
+        float pm = p1;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) pm = fmaxf(pm, __shfl_xor(pm, o));
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) shf[threadIdx.x >> 6] = pm;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            pm = fmaxf(fmaxf(shf[0], shf[1]), fmaxf(shf[2], shf[3]));
+            if (pm > 0.f) atomicMax(&f.st->p1max_bits, __float_as_uint(pm));
         }
         if (c == nch - 1 && threadIdx.x == 0) {
             RoundState* st = f.st;
@@ -395,24 +431,48 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
 // it is skipped if that pixel is already assigned or already chosen; 16
 // blocks at most.  The list L is fixed per frame, so the draws of round r do
 // not depend on how many points earlier rounds removed.
+// 4 lanes per hypothesis compute Philox blocks 0..3 and look up their 16
+// candidates in the assignment bitmap; one lane then walks them in order and,
+// only if fewer than 3 were usable, continues with blocks 4..15 itself.  The
+// triple is exactly the sequential draw's.
+constexpr int kHypLanes = 4;
+constexpr int kHypPerBlock = kBlock / kHypLanes;
+
+__device__ __forceinline__ bool point_taken(const FrameDev& f, int k) { return (f.abm[k >> 5] >> (k & 31)) & 1u; }
+
 __global__ __launch_bounds__(kBlock) void k_hypgen(const FrameDev* __restrict__ tab, int r) {
+    __shared__ int cand[kHypPerBlock][4 * kHypLanes];
     const FrameDev& f = tab[blockIdx.z];
     const RoundState* st = f.st;
     if (!st->active[r]) return;
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= f.hyps) return;
+    const int hl = threadIdx.x / kHypLanes, b = threadIdx.x % kHypLanes;
+    const int j = blockIdx.x * kHypPerBlock + hl;
+    if (blockIdx.x * kHypPerBlock >= f.hyps) return;
     const uint64_t M0 = (uint64_t)st->M0;
-    int slot[3] = {-1, -1, -1};
-    int got = 0;
-    for (int b = 0; b < 16 && got < 3; ++b) {
+    if (j < f.hyps) {
         uint64_t c[4] = {(uint64_t)j, (uint64_t)r, (uint64_t)b, 0ull};
         philox4x64_10(c, f.seed, f.frame_id);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (got >= 3) break;
             const int k = (int)__umul64hi(c[q], M0);
-            if (f.labels[f.L[k]] >= 0) continue;
-            if (k == slot[0] || k == slot[1]) continue;
+            cand[hl][4 * b + q] = point_taken(f, k) ? -1 : k;
+        }
+    }
+    __syncthreads();
+    if (b != 0 || j >= f.hyps) return;
+    int slot[3] = {-1, -1, -1};
+    int got = 0;
+    for (int i = 0; i < 4 * kHypLanes && got < 3; ++i) {
+        const int k = cand[hl][i];
+        if (k < 0 || k == slot[0] || k == slot[1]) continue;
+        slot[got++] = k;
+    }
+    for (int bb = kHypLanes; bb < 16 && got < 3; ++bb) {
+        uint64_t c[4] = {(uint64_t)j, (uint64_t)r, (uint64_t)bb, 0ull};
+        philox4x64_10(c, f.seed, f.frame_id);
+        for (int q = 0; q < 4 && got < 3; ++q) {
+            const int k = (int)__umul64hi(c[q], M0);
+            if (point_taken(f, k) || k == slot[0] || k == slot[1]) continue;
             slot[got++] = k;
         }
     }
@@ -446,9 +506,11 @@ __global__ __launch_bounds__(kBlock) void k_hyp_from_triples(const FrameDev* __r
 // ------------------------------------------------------------------ scoring
 // count_j = #{i in R_r : |n_j . p_i + d_j| < t}.  A block owns HB hypotheses
 // (uniform: scalar loads into SGPRs) and a strided share of the points, one
-// point per lane; each (point, hypothesis) costs 3 FMA + compare + add.
-// Per-lane counters are wave-reduced once per block and added to the global
-// count with one integer atomic per wave and hypothesis (order-free).
+// point per lane in wave-uniform tiles of 64.  Each (point, hypothesis) costs
+// 3 FMA and one compare on the vector ALU; the compare's lane mask is counted
+// on the scalar unit (popcount + add), so the counters live in SGPRs and each
+// wave adds its totals to the global counts with one integer atomic per
+// hypothesis (order-free).
 template <int HB>
 __global__ __launch_bounds__(kBlock) void k_score(const FrameDev* __restrict__ tab, int r) {
     const FrameDev& f = tab[blockIdx.z];
@@ -457,29 +519,34 @@ __global__ __launch_bounds__(kBlock) void k_score(const FrameDev* __restrict__ t
     const int M = st->M[r];
     const int h0 = blockIdx.y * HB;
     if (h0 >= f.hyps) return;
-    const int start = blockIdx.x * kBlock;
-    if (start >= M) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float4* __restrict__ pts = f.list[r & 1];
     float4 h[HB];
 #pragma unroll
     for (int i = 0; i < HB; ++i) h[i] = (h0 + i < f.hyps) ? f.hyp[h0 + i] : make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
     const float t = f.thresh;
-    int cnt[HB];
+    uint32_t cnt[HB];
 #pragma unroll
-    for (int i = 0; i < HB; ++i) cnt[i] = 0;
+    for (int i = 0; i < HB; ++i) cnt[i] = 0u;
+    const float qnan = __int_as_float(0x7fc00000);
     const int stride = gridDim.x * kBlock;
-    for (int i = start + threadIdx.x; i < M; i += stride) {
-        const float4 p = pts[i];
+    int base = blockIdx.x * kBlock + wave * 64;
+    float4 pn = make_float4(qnan, qnan, qnan, 0.f);  // the next tile's point, loaded one iteration ahead
+    if (base + lane < M) pn = pts[base + lane];
+    for (; base < M; base += stride) {
+        const float4 p = pn;
+        pn = make_float4(qnan, qnan, qnan, 0.f);
+        if (base + stride + lane < M) pn = pts[base + stride + lane];
 #pragma unroll
-        for (int k = 0; k < HB; ++k) cnt[k] += fabsf(canon_res(h[k], p.x, p.y, p.z)) < t ? 1 : 0;
+        for (int k = 0; k < HB; ++k)
+            cnt[k] += (uint32_t)__popcll(__ballot(fabsf(canon_res(h[k], p.x, p.y, p.z)) < t));
     }
+    if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < HB; ++k) {
-        const int c = wave_sum(cnt[k]);
-        if ((threadIdx.x & 63) == 0 && c != 0 && h0 + k < f.hyps) atomicAdd(&f.counts[h0 + k], c);
+        for (int k = 0; k < HB; ++k)
+            if (cnt[k] != 0u && h0 + k < f.hyps) atomicAdd(&f.counts[h0 + k], (int)cnt[k]);
     }
 }
-
 
 // ------------------------------------------------------------------ matrix-core scoring
 // The same counts as k_score, with the contraction n.p + d on the matrix
@@ -506,9 +573,8 @@ __device__ __forceinline__ short f32_to_bf16_rne(float x) {
     return (short)(b >> 16);
 }
 
-template <int PREC>
+template <int PREC, int G>  // G: hypothesis groups of 16 per wave
 __global__ __launch_bounds__(kBlock) void k_score_mfma(const FrameDev* __restrict__ tab, int r) {
-    constexpr int G = 4;  // hypothesis groups of 16 per wave
     const FrameDev& f = tab[blockIdx.z];
     const RoundState* st = f.st;
     if (!st->active[r]) return;
@@ -556,21 +622,36 @@ __global__ __launch_bounds__(kBlock) void k_score_mfma(const FrameDev* __restric
 
     const int ntiles = (M + 15) >> 4;
     const int wstride = gridDim.x * 4;
-    for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += wstride) {
+    // operands of the next tile are loaded one iteration ahead (software pipelining)
+    int tile = blockIdx.x * 4 + wave;
+    float v_next = 0.f;
+    float4 p_next = make_float4(0.f, 0.f, 0.f, 0.f), c_next = p_next;
+    if (tile < ntiles) {
+        const int i = (tile << 4) + col;
+        const int ic = i < M ? i : M - 1;  // loads stay in range; rows past M become NaN
+        if (PREC == PP_SCORE_MFMA_F32) v_next = ptsf[4 * ic + grp];
+        else { p_next = pts[ic]; c_next = pts[tile << 4]; }
+    }
+    for (; tile < ntiles; tile += wstride) {
         const int base = tile << 4;
         const int i = base + col;
-        const int ic = i < M ? i : M - 1;  // loads stay in range; rows past M become NaN
+        const float v = v_next;
+        const float4 p = p_next, c = c_next;
+        if (tile + wstride < ntiles) {
+            const int i2 = ((tile + wstride) << 4) + col;
+            const int ic2 = i2 < M ? i2 : M - 1;
+            if (PREC == PP_SCORE_MFMA_F32) v_next = ptsf[4 * ic2 + grp];
+            else { p_next = pts[ic2]; c_next = pts[(tile + wstride) << 4]; }
+        }
         f32x4_t D[G];
         uint32_t unsafe = 0;  // rows whose low-precision error bound exceeds the band
         if (PREC == PP_SCORE_MFMA_F32) {
-            const float v = ptsf[4 * ic + grp];
             const float a = i < M ? (grp == 3 ? 1.0f : v) : qnan;
             const f32x4_t z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int g = 0; g < G; ++g) D[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bop[g], z, 0, 0, 0);
         } else {
-            const float4 c = pts[base];  // tile anchor
-            const float4 p = pts[ic];
+            // c: the tile's first point (anchor); p: this lane's point
             const float qx = i < M ? p.x - c.x : qnan, qy = p.y - c.y, qz = p.z - c.z;
             const bool row_unsafe = i < M && !(row_coef * (fabsf(qx) + fabsf(qy) + fabsf(qz)) + row_fixed < f.band);
             unsafe = (uint32_t)(__ballot(grp == 0 && row_unsafe) & 0xFFFFull);
@@ -698,7 +779,7 @@ __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __rest
             m[4] += qx * qx; m[5] += qx * qy; m[6] += qx * qz;
             m[7] += qy * qy; m[8] += qy * qz; m[9] += qz * qz;
             if (f.dbg.masks) {
-                const int off = __float_as_int(p.w);
+                const int off = f.L[__float_as_int(p.w)];
                 const int y = off / f.pitch, x = off - y * f.pitch;
                 f.dbg.masks[(size_t)r * f.W * f.H + (size_t)y * f.W + x] |= 1;
             }
@@ -889,8 +970,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
                 const bool inF = fabsf(refit_res(q, p.x, p.y, p.z)) < t;
                 keep = !inF;
                 if (inF) {
-                    const int off = __float_as_int(p.w);
+                    const int pos = __float_as_int(p.w);
+                    const int off = f.L[pos];
                     f.labels[off] = (int8_t)r;
+                    atomicOr(&f.abm[pos >> 5], 1u << (pos & 31));
                     if (f.dbg.masks) {
                         const int y = off / f.pitch, x = off - y * f.pitch;
                         f.dbg.masks[(size_t)r * f.W * f.H + (size_t)y * f.W + x] |= 2;
@@ -938,13 +1021,28 @@ static void diffuse_pass_t(int T, const FrameDev* tab, int nf, int maxW, int max
     }
 }
 
-// All frames of a table run max(iters) iterations in passes of T; a frame
-// with fewer iterations must not be mixed with others (the batch path groups
-// frames by iteration count).
-hipError_t launch_diffuse(const FrameDev* tab, int nf, int maxW, int maxH, int iters, const Tuning& tu,
+// All frames of a table run max(iters) iterations in passes of T, with one
+// discretisation; frames with other iteration counts or schemes must not be
+// mixed with them (the batch path groups frames by both).
+hipError_t launch_diffuse(const FrameDev* tab, int nf, int maxW, int maxH, int iters, int scheme, const Tuning& tu,
                           hipStream_t s) {
     if (iters <= 0) {
         hipLaunchKernelGGL(k_diffuse_copy, dim3((maxW + 63) / 64, (maxH + 3) / 4, nf), dim3(kBlock), 0, s, tab);
+        return hipGetLastError();
+    }
+    if (scheme != PP_DIFFUSE_EDGE4) {
+        const dim3 grid((maxW + kVarTX - 1) / kVarTX, (maxH + kVarTY - 1) / kVarTY, nf);
+        for (int done = 0, src = 0; done < iters; src ^= 1) {
+            const int it = iters - done < kVarT ? iters - done : kVarT;
+            const int first = done == 0, last = done + it == iters;
+            if (scheme == PP_DIFFUSE_PIXEL)
+                hipLaunchKernelGGL(k_diffuse_var<PP_DIFFUSE_PIXEL>, grid, dim3(kBlock), 0, s, tab, it, first, last, src,
+                                   src ^ 1);
+            else
+                hipLaunchKernelGGL(k_diffuse_var<PP_DIFFUSE_EDGE8>, grid, dim3(kBlock), 0, s, tab, it, first, last, src,
+                                   src ^ 1);
+            done += it;
+        }
         return hipGetLastError();
     }
     const int T = tu.diffuse_t;
@@ -992,10 +1090,11 @@ static void score_launch(const FrameDev* tab, int nf, int r, int max_pts, int ma
 template <int PREC>
 static void score_mfma_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target,
                               hipStream_t s) {
-    const int groups = (max_hyps + 63) / 64;
+    constexpr int G = PREC == PP_SCORE_MFMA_F32 ? 8 : 4;
+    const int groups = (max_hyps + 16 * G - 1) / (16 * G);
     const int per_frame_cap = clampi(16384 / (nf > 0 ? nf : 1), 8, 4096);
     const int bx = clampi((max_pts + target - 1) / target, 1, clampi(per_frame_cap / groups, 1, 1024));
-    hipLaunchKernelGGL((k_score_mfma<PREC>), dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
+    hipLaunchKernelGGL((k_score_mfma<PREC, G>), dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
 }
 
 static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int precision,
@@ -1013,7 +1112,7 @@ static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int 
 
 hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_hyps, int precision,
                         const Tuning& tu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    hipLaunchKernelGGL(k_hypgen, dim3((max_hyps + kBlock - 1) / kBlock, 1, nf), dim3(kBlock), 0, s, tab, r);
+    hipLaunchKernelGGL(k_hypgen, dim3((max_hyps + kHypPerBlock - 1) / kHypPerBlock, 1, nf), dim3(kBlock), 0, s, tab, r);
     if (ev0) (void)hipEventRecord(ev0, s);
     score_dispatch(tab, nf, r, max_px, max_hyps, precision, tu, s);
     if (ev1) (void)hipEventRecord(ev1, s);

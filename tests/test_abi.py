@@ -33,7 +33,7 @@ def test_ctypes_structures_match_the_c_layout(tmp_path):
     structs = {"pp_intrinsics": N.Intrinsics, "pp_frame_desc": N.FrameDesc, "pp_diffuse_params": N.DiffuseParams,
                "pp_ransac_params": N.RansacParams, "pp_plane": N.Plane, "pp_ransac_debug": N.RansacDebug,
                "pp_frame_job": N.FrameJob, "pp_tuning": N.Tuning, "pp_server_cfg": N.ServerCfg,
-               "pp_result": N.Result, "pp_server_stats": N.ServerStats}
+               "pp_result": N.Result, "pp_server_stats": N.ServerStats, "pp_region_debug": N.RegionDebug}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pp.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -99,7 +99,8 @@ def _job(**kw):
 @pytest.mark.parametrize("change", [
     {}, {"desc.width": 2}, {"desc.height": 0}, {"desc.pitch_px": 10}, {"desc.width": 20000},
     {"diffuse.lam": 0.3}, {"diffuse.lam": 0.0}, {"diffuse.kappa_mm": 0.0}, {"diffuse.iters": -1},
-    {"diffuse.edge_stop": 5}, {"ransac.hyps_per_plane": 0}, {"ransac.thresh_m": 0.0}, {"ransac.max_planes": 0},
+    {"diffuse.edge_stop": 5}, {"diffuse.scheme": 3}, {"diffuse.scheme": -1}, {"diffuse.scheme": 2, "diffuse.lam": 0.2},
+    {"ransac.hyps_per_plane": 0}, {"ransac.thresh_m": 0.0}, {"ransac.max_planes": 0},
     {"ransac.max_planes": 128}, {"ransac.min_inliers": 0}, {"K.fx": 0.0}, {"depth": None}, {"labels": None},
 ])
 def test_job_validation_is_host_only(change):
