@@ -266,8 +266,12 @@ pp_status pp_batch_run_eager(pp_ctx* ctx, int32_t n_frames, const pp_frame_job* 
 /* ---------------------------------------------------------------- tuning */
 /* Launch-shape knobs the autotuner searches (0 = library default).
  * diffuse_tile: index of the diffusion tile shape, diffuse_t: iterations
- * fused per pass (temporal blocking depth), score_hb: hypotheses per
- * scoring block, score_chunk: points per scoring work item. */
+ * fused per pass (temporal blocking depth), score_hb: the FP32 scorer's
+ * hypotheses per block (1: 8, 2: 16, 3: 32 on the vector ALUs; 4: 64 with
+ * tile culling, each 64-point tile's bounding box first decides for every
+ * hypothesis whether all, none or only some of its points can be inliers),
+ * score_chunk: points per scoring work item.  Every choice gives identical
+ * results. */
 typedef struct {
     int32_t diffuse_tile;
     int32_t diffuse_t;

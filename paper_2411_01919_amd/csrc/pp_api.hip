@@ -34,11 +34,14 @@ struct GraphEntry {
 
 }  // namespace
 
+// 64x16 diffusion tiles, 3 iterations a pass, the culled scorer, 2048 points a scoring block
+constexpr ppk::Tuning kDefaultTuning{0, 3, 3, 1};
+
 struct pp_ctx {
     int device = 0;
     bool poisoned = false;
     std::string last_error;
-    ppk::Tuning tuning{0, 5, 1, 2};
+    ppk::Tuning tuning = kDefaultTuning;
     std::vector<Slot> slots;
     // device frame tables: [0] single-frame calls, [1] batches
     FrameDev* plain_tab = nullptr;
@@ -113,7 +116,7 @@ bool intrinsics_ok(const pp_intrinsics& K) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t delta, L, list, abm, hyp, triples, counts, partials, chunk_cnt, st, total;
+    size_t delta, L, list, abm, hyp, triples, counts, partials, chunk_cnt, chunk_cnt_q, tbox, st, total;
 };
 
 Layout slot_layout(size_t px, int hyps) {
@@ -130,6 +133,9 @@ Layout slot_layout(size_t px, int hyps) {
     l.counts = o; o += align256((size_t)hyps * sizeof(int32_t));
     l.partials = o; o += align256(nch_refit * 10 * sizeof(double));
     l.chunk_cnt = o; o += align256(std::max(nch_refit, nch_valid) * sizeof(int32_t));
+    // the padded 8x8-block scan of a frame of px pixels (each side >= 3) covers at most 3.4 px + 70 positions
+    l.chunk_cnt_q = o; o += align256(((4 * px + 4096) / ppk::kValidChunk + 1) * sizeof(int32_t));
+    l.tbox = o; o += align256((px + 63) / 64 * 2 * sizeof(float4));
     l.st = o; o += align256(sizeof(RoundState));
     l.total = o;
     return l;
@@ -179,6 +185,8 @@ void bind_slot(const pp_ctx* c, int i, FrameDev& f) {
     f.counts = reinterpret_cast<int32_t*>(b + l.counts);
     f.partials = reinterpret_cast<double*>(b + l.partials);
     f.chunk_cnt = reinterpret_cast<int32_t*>(b + l.chunk_cnt);
+    f.chunk_cnt_q = reinterpret_cast<int32_t*>(b + l.chunk_cnt_q);
+    f.tbox = reinterpret_cast<float4*>(b + l.tbox);
     f.st = reinterpret_cast<RoundState*>(b + l.st);
 }
 
@@ -320,7 +328,7 @@ pp_status pp_set_tuning(pp_ctx* c, const pp_tuning* t) {
     pp_status s = check_ctx(c);
     if (s != PP_OK) return s;
     if (!t) {
-        c->tuning = ppk::Tuning{0, 5, 1, 2};
+        c->tuning = kDefaultTuning;
         return PP_OK;
     }
     ppk::Tuning n = c->tuning;

@@ -14,6 +14,7 @@ constexpr int kMaxHyps = 8192;
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64s)
 constexpr int kValidChunk = 1024; // pixels per valid-list chunk
 constexpr int kRefitChunk = 2048; // points per refit / apply chunk
+constexpr int kScanBlock = 8;     // the scoring list walks the image in 8x8-pixel blocks
 
 // Per-frame RANSAC state in device memory.  Fields indexed by the round r are
 // written only by an earlier kernel than the ones that read them, so no
@@ -66,6 +67,9 @@ struct FrameDev {
     int32_t* counts;         // [hyps]
     double* partials;        // [refit chunks][10]
     int32_t* chunk_cnt;      // [max(valid chunks, refit chunks)]
+    int32_t* chunk_cnt_q;    // [block-order chunks] depth-valid pixels per 1024 positions of the 8x8-block scan
+    float4* tbox;            // [ceil(W*H/64)][2] per 64-point tile of the current list: centre (w: point
+                             // count bits) and half extents of its bounding box
     RoundState* st;
     // introspection (may be null)
     pp_ransac_debug dbg;
@@ -74,13 +78,13 @@ struct FrameDev {
 struct Tuning {
     int diffuse_tile;  // index into the tile table
     int diffuse_t;     // iterations per pass
-    int score_hb;      // index into {8, 16, 32}
+    int score_hb;      // index into {8, 16, 32, 64 with tile culling}
     int score_chunk;   // index into {1024, 2048, 4096, 8192}
 };
 
 constexpr int kNumTiles = 4;
 constexpr int kMaxT = 10;
-constexpr int kNumHB = 3;
+constexpr int kNumHB = 4;
 constexpr int kNumChunk = 4;
 int tile_w(int tile);
 int tile_h(int tile);

@@ -345,6 +345,24 @@ __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__
 // ------------------------------------------------------------------ valid list
 // Row-major list L of depth-valid pixels (the fixed per-frame point set the
 // sampler indexes) plus the round-0 point list; labels start at -1.
+// The scoring list walks the image in 8x8-pixel blocks (blocks in row-major
+// order, pixels row-major inside a block) so that 64 consecutive points are
+// close in space; the sampling list L stays row-major.  Scan position q of the
+// padded block grid maps to pixel (x, y), outside the image past the edges.
+__device__ __forceinline__ int scan_positions(const FrameDev& f) {
+    return ((f.W + kScanBlock - 1) / kScanBlock) * ((f.H + kScanBlock - 1) / kScanBlock) * kScanBlock * kScanBlock;
+}
+
+__device__ __forceinline__ bool scan_pixel(const FrameDev& f, int q, int& x, int& y) {
+    constexpr int B2 = kScanBlock * kScanBlock;
+    const int bw = (f.W + kScanBlock - 1) / kScanBlock;
+    const int b = q / B2, w = q - b * B2;
+    const int by = b / bw, bx = b - by * bw;
+    x = bx * kScanBlock + w % kScanBlock;
+    y = by * kScanBlock + w / kScanBlock;
+    return x < f.W && y < f.H && q < scan_positions(f);
+}
+
 __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restrict__ tab) {
     __shared__ int sh[4];
     const FrameDev& f = tab[blockIdx.z];
@@ -365,6 +383,18 @@ __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restri
         cnt = block_sum(cnt, sh);
         if (threadIdx.x == 0) f.chunk_cnt[c] = cnt;
     }
+    // the same counts over the 8x8-block scan that orders the scoring list
+    const int nq = scan_positions(f);
+    const int nchq = (nq + kValidChunk - 1) / kValidChunk;
+    for (int c = blockIdx.x; c < nchq; c += gridDim.x) {
+        int cnt = 0;
+        for (int i = threadIdx.x; i < kValidChunk; i += kBlock) {
+            int x, y;
+            if (scan_pixel(f, c * kValidChunk + i, x, y)) cnt += f.valid[(size_t)y * f.pitch + x] & 1;
+        }
+        cnt = block_sum(cnt, sh);
+        if (threadIdx.x == 0) f.chunk_cnt_q[c] = cnt;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __restrict__ tab) {
@@ -374,6 +404,9 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
     const int npx = f.W * f.H;
     const int nch = (npx + kValidChunk - 1) / kValidChunk;
     const size_t plane = (size_t)f.H * f.pitch;
+    // valid-list position of every depth-valid pixel, [H][W]; the diffusion
+    // ping-pong buffer is free by now
+    int32_t* __restrict__ lpos = reinterpret_cast<int32_t*>(f.delta[0]);
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         int before = 0;
         for (int i = threadIdx.x; i < c; i += kBlock) before += f.chunk_cnt[i];
@@ -394,11 +427,10 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
             const int rank = block_rank(v, sh, &tot);
             if (v) {
                 const int k = run + rank;
-                const float4 q = make_float4(f.pts[off], f.pts[plane + off], f.pts[2 * plane + off], __int_as_float(k));
                 f.L[k] = off;
-                f.list[0][k] = q;
+                lpos[p] = k;
                 if (f.dbg.valid_list) f.dbg.valid_list[k] = off;
-                p1 = fmaxf(p1, fabsf(q.x) + fabsf(q.y) + fabsf(q.z));
+                p1 = fmaxf(p1, fabsf(f.pts[off]) + fabsf(f.pts[plane + off]) + fabsf(f.pts[2 * plane + off]));
             }
             run += tot;
         }
@@ -439,6 +471,35 @@ constexpr int kHypLanes = 4;
 constexpr int kHypPerBlock = kBlock / kHypLanes;
 
 __device__ __forceinline__ bool point_taken(const FrameDev& f, int k) { return (f.abm[k >> 5] >> (k & 31)) & 1u; }
+
+// Round 0's scoring list: the depth-valid points in 8x8-block scan order,
+// each tagged with its valid-list position (w), by ordered compaction over
+// chunks of 1024 scan positions.
+__global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restrict__ tab) {
+    __shared__ int sh[4];
+    const FrameDev& f = tab[blockIdx.z];
+    const int nq = scan_positions(f);
+    const int nchq = (nq + kValidChunk - 1) / kValidChunk;
+    const size_t plane = (size_t)f.H * f.pitch;
+    const int32_t* __restrict__ lpos = reinterpret_cast<const int32_t*>(f.delta[0]);
+    for (int c = blockIdx.x; c < nchq; c += gridDim.x) {
+        int before = 0;
+        for (int i = threadIdx.x; i < c; i += kBlock) before += f.chunk_cnt_q[i];
+        int run = block_sum(before, sh);
+        for (int s = 0; s < kValidChunk; s += kBlock) {
+            int x = 0, y = 0;
+            bool v = scan_pixel(f, c * kValidChunk + s + threadIdx.x, x, y);
+            const int off = y * f.pitch + x;
+            v = v && (f.valid[off] & 1);
+            int tot;
+            const int rank = block_rank(v, sh, &tot);
+            if (v)
+                f.list[0][run + rank] = make_float4(f.pts[off], f.pts[plane + off], f.pts[2 * plane + off],
+                                                    __int_as_float(lpos[y * f.W + x]));
+            run += tot;
+        }
+    }
+}
 
 __global__ __launch_bounds__(kBlock) void k_hypgen(const FrameDev* __restrict__ tab, int r) {
     __shared__ int cand[kHypPerBlock][4 * kHypLanes];
@@ -546,6 +607,103 @@ __global__ __launch_bounds__(kBlock) void k_score(const FrameDev* __restrict__ t
         for (int k = 0; k < HB; ++k)
             if (cnt[k] != 0u && h0 + k < f.hyps) atomicAdd(&f.counts[h0 + k], (int)cnt[k]);
     }
+}
+
+// ------------------------------------------------------------------ culled scoring
+// Bounding boxes of the 64-point tiles of round r's list (one wave per tile):
+// centre c (w: the tile's point count as integer bits) and half extents e,
+// widened so that [c - e, c + e] holds every point of the tile.
+__global__ __launch_bounds__(kBlock) void k_tile_box(const FrameDev* __restrict__ tab, int r) {
+    const FrameDev& f = tab[blockIdx.z];
+    const RoundState* st = f.st;
+    if (!st->active[r]) return;
+    const int M = st->M[r];
+    const int ntiles = (M + 63) >> 6;
+    const int lane = threadIdx.x & 63;
+    const float4* __restrict__ pts = f.list[r & 1];
+    for (int tile = blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += gridDim.x * 4) {
+        const int i = tile * 64 + lane;
+        float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+        if (i < M) {
+            const float4 p = pts[i];
+            lx = hx = p.x;
+            ly = hy = p.y;
+            lz = hz = p.z;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lx = fminf(lx, __shfl_xor(lx, o));
+            ly = fminf(ly, __shfl_xor(ly, o));
+            lz = fminf(lz, __shfl_xor(lz, o));
+            hx = fmaxf(hx, __shfl_xor(hx, o));
+            hy = fmaxf(hy, __shfl_xor(hy, o));
+            hz = fmaxf(hz, __shfl_xor(hz, o));
+        }
+        if (lane == 0) {
+            const float cx = 0.5f * (lx + hx), cy = 0.5f * (ly + hy), cz = 0.5f * (lz + hz);
+            // the rounded differences may fall short of the true ones by an ulp: widen by 2^-20
+            const float w = 1.0f + 9.5367432e-7f;
+            const float ex = fmaxf(hx - cx, cx - lx) * w, ey = fmaxf(hy - cy, cy - ly) * w, ez = fmaxf(hz - cz, cz - lz) * w;
+            const int n = min(64, M - tile * 64);
+            f.tbox[2 * tile] = make_float4(cx, cy, cz, __int_as_float(n));
+            f.tbox[2 * tile + 1] = make_float4(ex, ey, ez, 0.f);
+        }
+    }
+}
+
+// Inlier counts with tile culling.  A block holds 64 hypotheses, one per lane.
+// For each 64-point tile, every lane bounds its hypothesis' residual over the
+// tile's box: |n.c + d| -/+ (|nx| ex + |ny| ey + |nz| ez).  With a margin of
+// 16 u (P1 + |d|) (u = 2^-24, P1 = max |p|_1 of the frame), which exceeds
+// the FP32 rounding of the bound and of the canonical residual, a tile lies
+// wholly outside (no inliers) or wholly inside (all its points are inliers)
+// exactly as the canonical formula decides; only the hypotheses left
+// straddling are evaluated point by point (one point per lane), and their
+// counts are the canonical ones.
+__global__ __launch_bounds__(kBlock) void k_score_cull(const FrameDev* __restrict__ tab, int r) {
+    __shared__ float4 s_h[64];
+    const FrameDev& f = tab[blockIdx.z];
+    const RoundState* st = f.st;
+    if (!st->active[r]) return;
+    const int M = st->M[r];
+    const int h0 = blockIdx.y * 64;
+    if (h0 >= f.hyps) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float qnan = __int_as_float(0x7fc00000);
+    if (threadIdx.x < 64)
+        s_h[threadIdx.x] = h0 + threadIdx.x < f.hyps ? f.hyp[h0 + threadIdx.x] : make_float4(0.f, 0.f, 0.f, qnan);
+    __syncthreads();
+    const float4 hl = s_h[lane];
+    const bool hv = hl.w == hl.w;
+    const float t = f.thresh;
+    const float band = 16.f * 5.9604645e-8f * (__uint_as_float(st->p1max_bits) + fabsf(hl.w));
+    const float thi = t + band, tlo = t - band;
+    const float ax = fabsf(hl.x), ay = fabsf(hl.y), az = fabsf(hl.z);
+    const float4* __restrict__ pts = f.list[r & 1];
+    const float4* __restrict__ box = f.tbox;
+    const int ntiles = (M + 63) >> 6;
+    uint32_t cnt = 0u;
+    for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
+        const float4 c = box[2 * tile], e = box[2 * tile + 1];
+        const float a = fabsf(fmaf(hl.x, c.x, fmaf(hl.y, c.y, fmaf(hl.z, c.z, hl.w))));
+        const float ext = fmaf(ax, e.x, fmaf(ay, e.y, az * e.z));
+        const bool in = hv && a + ext < tlo;
+        const bool out = !hv || a - ext >= thi;
+        if (in) cnt += (uint32_t)__float_as_int(c.w);
+        unsigned long long S = __ballot(!in && !out);
+        if (S) {
+            const int i = tile * 64 + lane;
+            const float4 p = i < M ? pts[i] : make_float4(qnan, qnan, qnan, 0.f);
+            while (S) {
+                const int k = __ffsll(S) - 1;
+                S &= S - 1;
+                const float4 h = s_h[k];
+                const uint32_t m = (uint32_t)__popcll(__ballot(fabsf(canon_res(h, p.x, p.y, p.z)) < t));
+                cnt += lane == k ? m : 0u;
+            }
+        }
+    }
+    if (hv && cnt) atomicAdd(&f.counts[h0 + lane], (int)cnt);
 }
 
 // ------------------------------------------------------------------ matrix-core scoring
@@ -991,7 +1149,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
 // ------------------------------------------------------------------ launchers
 static const int kTileW[kNumTiles] = {64, 128, 64, 128};
 static const int kTileH[kNumTiles] = {16, 16, 32, 32};
-static const int kHB[kNumHB] = {8, 16, 32};
+static const int kHB[kNumHB] = {8, 16, 32, 64};  // 64: the culled scorer
 static const int kChunk[kNumChunk] = {1024, 2048, 4096, 8192};
 
 int tile_w(int t) { return kTileW[t]; }
@@ -1076,6 +1234,9 @@ hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, hipStream_
     const int gx = clampi(nch, 1, 1024);
     hipLaunchKernelGGL(k_valid_count, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab);
     hipLaunchKernelGGL(k_valid_scatter, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab);
+    // block-order chunks: the padded scan covers at most 3.4 max_px + 70 positions
+    const int gq = clampi((int)(((int64_t)4 * max_px + 4096) / kValidChunk + 1), 1, 1024);
+    hipLaunchKernelGGL(k_list_scatter, dim3(gq, 1, nf), dim3(kBlock), 0, s, tab);
     return hipGetLastError();
 }
 
@@ -1085,6 +1246,17 @@ static void score_launch(const FrameDev* tab, int nf, int r, int max_pts, int ma
     const int per_frame_cap = clampi(16384 / (nf > 0 ? nf : 1), 8, 4096);
     const int bx = clampi((max_pts + target - 1) / target, 1, clampi(per_frame_cap / groups, 1, 1024));
     hipLaunchKernelGGL((k_score<HB>), dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
+}
+
+// Culled scoring: the tile boxes of round r's list, then 64 hypotheses per block.
+static void score_cull_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target,
+                              hipStream_t s) {
+    const int tiles = (max_pts + 63) / 64;
+    hipLaunchKernelGGL(k_tile_box, dim3(clampi((tiles + 3) / 4, 1, 2048), 1, nf), dim3(kBlock), 0, s, tab, r);
+    const int groups = (max_hyps + 63) / 64;
+    const int per_frame_cap = clampi(16384 / (nf > 0 ? nf : 1), 8, 4096);
+    const int bx = clampi((max_pts + target - 1) / target, 1, clampi(per_frame_cap / groups, 1, 1024));
+    hipLaunchKernelGGL(k_score_cull, dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
 }
 
 template <int PREC>
@@ -1106,7 +1278,8 @@ static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int 
     switch (tu.score_hb) {
         case 0: score_launch<8>(tab, nf, r, max_pts, max_hyps, target, s); break;
         case 1: score_launch<16>(tab, nf, r, max_pts, max_hyps, target, s); break;
-        default: score_launch<32>(tab, nf, r, max_pts, max_hyps, target, s); break;
+        case 2: score_launch<32>(tab, nf, r, max_pts, max_hyps, target, s); break;
+        default: score_cull_launch(tab, nf, r, max_pts, max_hyps, target, s); break;
     }
 }
 

@@ -354,7 +354,7 @@ def test_scoring_tunings_give_identical_planes(pp):
     dc, rc = cfg_params(2, W, H, 2)
     ref = None
     ctx = pp.Context(0)
-    for hb in (1, 2, 3):
+    for hb in (1, 2, 3, 4):
         for ch in (1, 4):
             ctx.set_tuning(score_hb=hb, score_chunk=ch)
             fo = pp.make_outputs(to_dev(f.depth), (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc)
@@ -366,6 +366,31 @@ def test_scoring_tunings_give_identical_planes(pp):
             for a, b in zip(snap, ref):
                 assert np.array_equal(a, b)
     ctx.close()
+
+
+@pytest.mark.parametrize("cid,k,size,hyps", [(1, 0, None, 256), (2, 1, None, 1024), (3, 2, (301, 97), 5),
+                                              (3, 0, (848, 480), 100), (4, 1, (1280, 720), 1024)])
+def test_culled_scorer_counts_equal_the_plain_scorer(pp, cid, k, size, hyps):
+    """Tile culling decides whole tiles only where the canonical residual
+    cannot change side: every count of every round is bitwise the plain one."""
+    f = scenes.make_frame(cid, k, size=size)
+    H, W = f.depth.shape
+    dc, rc = cfg_params(cid, W, H, k, hyps=hyps)
+    log(f"culled scorer cfg={cid} k={k} {W}x{H} hyps={hyps}")
+    runs = []
+    for hb in (1, 4):
+        ctx = pp.Context(0)
+        ctx.set_tuning(score_hb=hb)
+        runs.append(run_plain(f, dc, rc, ctx=ctx))
+        ctx.close()
+    a, b = runs
+    assert a["n_planes"] == b["n_planes"] and np.array_equal(a["labels"], b["labels"])
+    for key in ("counts", "triples", "round_info"):
+        assert np.array_equal(a["dbg"][key], b["dbg"][key]), key
+    assert np.array_equal(a["dbg"]["hyps"], b["dbg"]["hyps"], equal_nan=True)
+    for pa, pb in zip(a["planes"], b["planes"]):
+        assert np.array_equal(pa["n"], pb["n"]) and pa["d"] == pb["d"] and pa["inliers"] == pb["inliers"]
+    log(f"  {a['n_planes']} planes, counts of {int((a['dbg']['round_info'][:, 0] > 0).sum())} rounds equal")
 
 
 # ------------------------------------------------------------------ edge cases

@@ -72,7 +72,11 @@ def _check(orc, P32, valid, region, R, hyps, seed, frame_id, got, t=0.01):
         n = int(ref.npts[g])
         v = ref.hvalid[g]
         if v.any():
-            dpl = np.abs(got["hyps"][g][v].astype(np.float64) - ref.planes[g][v]).max(axis=1)
+            q, o = got["hyps"][g][v].astype(np.float64), ref.planes[g][v]
+            dpl = np.abs(q - o).max(axis=1)
+            # a plane through the camera centre (|d| inside the band) is camera-facing either way round
+            flip = np.abs(o[:, 3]) <= eps[g][v]
+            dpl[flip] = np.minimum(dpl[flip], np.abs(q + o).max(axis=1)[flip])
             assert (dpl <= eps[g][v]).all(), g
             c = got["counts"][g][v]
             assert (ref.counts_lo[g][v] <= c).all() and (c <= ref.counts_hi[g][v]).all(), g
