@@ -660,18 +660,68 @@ __global__ __launch_bounds__(kBlock) void k_tile_box(const FrameDev* __restrict_
 // exactly as the canonical formula decides; only the hypotheses left
 // straddling are evaluated point by point (one point per lane), and their
 // counts are the canonical ones.
+// Loads through the global address space (global_load rather than the
+// generic flat path).  Only for data no kernel of the same launch writes.
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) v4f_t* gv4_ptr;
+
+__device__ __forceinline__ float4 ld_global4(const float4* p, int i) {
+    const v4f_t v = ((gv4_ptr)p)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// x, y, z of a float4 record (a 12-byte load: w is never read)
+typedef float v3f_t __attribute__((ext_vector_type(3)));
+__device__ __forceinline__ float3 ld_global_xyz(const float4* p, int i) {
+    const v3f_t v = *reinterpret_cast<const __attribute__((address_space(1))) v3f_t*>(
+        reinterpret_cast<const __attribute__((address_space(1))) char*>((gv4_ptr)p) + (size_t)i * 16);
+    return make_float3(v.x, v.y, v.z);
+}
+
+// One tile of k_score_cull for this lane's hypothesis: the box test, then,
+// only if some hypothesis of the block straddles, the tile's points (one per
+// lane; the index is clamped and lanes past the end are masked out of every
+// ballot) against each straddling hypothesis, lowest first; returns this
+// lane's count.
+__device__ __forceinline__ uint32_t cull_tile(const float4* box, const float4* hyp_lds, int tile, int M,
+                                              const float4* pts, float4 hl, bool hv, float ax, float ay, float az,
+                                              float tlo, float thi, float t) {
+    const float4 c = ld_global4(box, 2 * tile), e = ld_global4(box, 2 * tile + 1);
+    const float a = fabsf(fmaf(hl.x, c.x, fmaf(hl.y, c.y, fmaf(hl.z, c.z, hl.w))));
+    const float ext = fmaf(ax, e.x, fmaf(ay, e.y, az * e.z));
+    const bool in = hv && a + ext < tlo;
+    const bool out = !hv || a - ext >= thi;
+    uint32_t cnt = in ? (uint32_t)__float_as_int(c.w) : 0u;
+    unsigned long long S = __ballot(!in && !out);
+    if (!S) return cnt;
+    const unsigned long long live = __ballot(tile * 64 + (int)(threadIdx.x & 63) < M);
+    const float3 p = ld_global_xyz(pts, min(tile * 64 + (int)(threadIdx.x & 63), M - 1));
+    int tmp = 0;
+    while (S) {
+        const int k = __ffsll(S) - 1;
+        S &= S - 1;
+        const float4 h = hyp_lds[k];
+        const int m = __popcll(__ballot(fabsf(canon_res(h, p.x, p.y, p.z)) < t) & live);
+        tmp += (int)(threadIdx.x & 63) == k ? m : 0;
+    }
+    return cnt + (uint32_t)tmp;
+}
+
 __global__ __launch_bounds__(kBlock) void k_score_cull(const FrameDev* __restrict__ tab, int r) {
-    __shared__ float4 s_h[64];
     const FrameDev& f = tab[blockIdx.z];
     const RoundState* st = f.st;
     if (!st->active[r]) return;
-    const int M = st->M[r];
+    const int M = __builtin_amdgcn_readfirstlane(st->M[r]);
     const int h0 = blockIdx.y * 64;
-    if (h0 >= f.hyps) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int hyps = __builtin_amdgcn_readfirstlane(f.hyps);
+    if (h0 >= hyps) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const float qnan = __int_as_float(0x7fc00000);
-    if (threadIdx.x < 64)
-        s_h[threadIdx.x] = h0 + threadIdx.x < f.hyps ? f.hyp[h0 + threadIdx.x] : make_float4(0.f, 0.f, 0.f, qnan);
+    const int nh = min(64, hyps - h0);
+    const float4* hyp = f.hyp + h0;
+    __shared__ float4 s_h[64];
+    if (threadIdx.x < 64) s_h[threadIdx.x] = lane < nh ? ld_global4(hyp, lane) : make_float4(0.f, 0.f, 0.f, qnan);
     __syncthreads();
     const float4 hl = s_h[lane];
     const bool hv = hl.w == hl.w;
@@ -679,30 +729,13 @@ __global__ __launch_bounds__(kBlock) void k_score_cull(const FrameDev* __restric
     const float band = 16.f * 5.9604645e-8f * (__uint_as_float(st->p1max_bits) + fabsf(hl.w));
     const float thi = t + band, tlo = t - band;
     const float ax = fabsf(hl.x), ay = fabsf(hl.y), az = fabsf(hl.z);
-    const float4* __restrict__ pts = f.list[r & 1];
-    const float4* __restrict__ box = f.tbox;
+    const float4* pts = f.list[r & 1];
+    const float4* box = f.tbox;
     const int ntiles = (M + 63) >> 6;
+    const int tstride = gridDim.x * 4;
     uint32_t cnt = 0u;
-    for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
-        const float4 c = box[2 * tile], e = box[2 * tile + 1];
-        const float a = fabsf(fmaf(hl.x, c.x, fmaf(hl.y, c.y, fmaf(hl.z, c.z, hl.w))));
-        const float ext = fmaf(ax, e.x, fmaf(ay, e.y, az * e.z));
-        const bool in = hv && a + ext < tlo;
-        const bool out = !hv || a - ext >= thi;
-        if (in) cnt += (uint32_t)__float_as_int(c.w);
-        unsigned long long S = __ballot(!in && !out);
-        if (S) {
-            const int i = tile * 64 + lane;
-            const float4 p = i < M ? pts[i] : make_float4(qnan, qnan, qnan, 0.f);
-            while (S) {
-                const int k = __ffsll(S) - 1;
-                S &= S - 1;
-                const float4 h = s_h[k];
-                const uint32_t m = (uint32_t)__popcll(__ballot(fabsf(canon_res(h, p.x, p.y, p.z)) < t));
-                cnt += lane == k ? m : 0u;
-            }
-        }
-    }
+    for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += tstride)
+        cnt += cull_tile(box, s_h, tile, M, pts, hl, hv, ax, ay, az, tlo, thi, t);
     if (hv && cnt) atomicAdd(&f.counts[h0 + lane], (int)cnt);
 }
 
@@ -1074,6 +1107,8 @@ __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restri
     }
 }
 
+constexpr int kApplySteps = kRefitChunk / kBlock;
+
 // F = the refit plane's inliers among R_r.  If |F| >= min_inliers: label F
 // with r, write the plane record, and compact the survivors (in order) into
 // the next round's list; otherwise the frame stops without emitting.
@@ -1109,40 +1144,56 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
         }
     }
     if (!emit) return;
+    __shared__ int s_cnt[kApplySteps][kBlock / 64];
     const SplitPlane q = split_plane(st->plane);
     const float t = f.thresh;
     const float4* __restrict__ pts = f.list[r & 1];
     float4* __restrict__ out = f.list[(r + 1) & 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         int before = 0;
         for (int i = threadIdx.x; i < c; i += kBlock) before += kRefitChunk - f.chunk_cnt[i];
         before = block_sum(before, sh);
-        int run = before;
         const int e = min(M, (c + 1) * kRefitChunk);
-        for (int s = c * kRefitChunk; s < e; s += kBlock) {
-            const int i = s + threadIdx.x;
-            bool keep = false;
-            float4 p = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (i < e) {
-                p = pts[i];
-                const bool inF = fabsf(refit_res(q, p.x, p.y, p.z)) < t;
-                keep = !inF;
-                if (inF) {
-                    const int pos = __float_as_int(p.w);
-                    const int off = f.L[pos];
-                    f.labels[off] = (int8_t)r;
-                    atomicOr(&f.abm[pos >> 5], 1u << (pos & 31));
-                    if (f.dbg.masks) {
-                        const int y = off / f.pitch, x = off - y * f.pitch;
-                        f.dbg.masks[(size_t)r * f.W * f.H + (size_t)y * f.W + x] |= 2;
-                    }
+        // every point of this thread in flight at once: point c*chunk + s*256 + tid of step s
+        float4 p[kApplySteps];
+#pragma unroll
+        for (int s = 0; s < kApplySteps; ++s) {
+            const int i = c * kRefitChunk + s * kBlock + threadIdx.x;
+            p[s] = pts[min(i, e - 1)];
+        }
+        unsigned long long keepm[kApplySteps];
+#pragma unroll
+        for (int s = 0; s < kApplySteps; ++s) {
+            const int i = c * kRefitChunk + s * kBlock + threadIdx.x;
+            const bool inF = i < e && fabsf(refit_res(q, p[s].x, p[s].y, p[s].z)) < t;
+            if (inF) {
+                const int pos = __float_as_int(p[s].w);
+                const int off = f.L[pos];
+                f.labels[off] = (int8_t)r;
+                atomicOr(&f.abm[pos >> 5], 1u << (pos & 31));
+                if (f.dbg.masks) {
+                    const int y = off / f.pitch, x = off - y * f.pitch;
+                    f.dbg.masks[(size_t)r * f.W * f.H + (size_t)y * f.W + x] |= 2;
                 }
             }
-            int tot;
-            const int rank = block_rank(keep, sh, &tot);
-            if (keep) out[run + rank] = p;
-            run += tot;
+            keepm[s] = __ballot(i < e && !inF);
+            if (lane == 0) s_cnt[s][wave] = __popcll(keepm[s]);
         }
+        __syncthreads();
+        // survivors keep their order: step-major, then wave, then lane
+        int base = before;
+#pragma unroll
+        for (int s = 0; s < kApplySteps; ++s) {
+            int mine = base;
+            for (int w = 0; w < kBlock / 64; ++w) {
+                const int n = s_cnt[s][w];
+                mine += w < wave ? n : 0;
+                base += n;
+            }
+            if ((keepm[s] >> lane) & 1ull) out[mine + __popcll(keepm[s] & lanemask_lt())] = p[s];
+        }
+        __syncthreads();  // s_cnt is reused by the next chunk
     }
 }
 
