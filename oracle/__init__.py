@@ -48,6 +48,11 @@ def lib():
         L.orc_diffuse.argtypes = [P, i, i, i, d, d, i, P]
         L.orc_diffuse_variant.argtypes = [P, i, i, i, d, d, i, i, P]
         L.orc_backproject.argtypes = [P, i, i, d, d, d, d, P, P]
+        f = ctypes.c_float
+        L.orc_seg_grad.argtypes = [P, P, i, i, P, P, P]
+        L.orc_seg_edges.argtypes = [P, P, P, i, i, f, f, P, P]
+        L.orc_seg_regions.argtypes = [P, i, i, i, i, P]
+        L.orc_segment.argtypes = [P, P, i, i, f, f, i, i, P, P]
         L.orc_ransac_regions.argtypes = [P, P, P, i, i, i, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_normals.argtypes = [P, P, i, i, P, P, P, P]
         L.orc_valid_list.argtypes = [P, i, P]
@@ -330,6 +335,51 @@ def ransac_regions(P, valid, region, R: int, prm: RansacParams, eps=None) -> Reg
                                   _p(npts), _p(tr), _p(pl), _p(hv), _p(er), _p(cn), _p(lo), _p(hi), _p(js), _p(st),
                                   _p(ce), _p(labels))
     return RegionResult(ns, npts, tr, pl, hv.astype(bool), er, cn, lo, hi, js, st.astype(bool), ce, labels)
+
+
+def seg_grad(N, nvalid):
+    """-> (m2 float32 [H][W], sector u8, barrier u8) of the FP32 normal image N [3][H][W]."""
+    N = np.ascontiguousarray(N, dtype=np.float32)
+    _, H, W = N.shape
+    nv = np.ascontiguousarray(nvalid != 0, dtype=np.uint8)
+    m2 = np.zeros((H, W), np.float32)
+    sec = np.zeros((H, W), np.uint8)
+    bar = np.zeros((H, W), np.uint8)
+    lib().orc_seg_grad(_p(N), _p(nv), W, H, _p(m2), _p(sec), _p(bar))
+    return m2, sec, bar
+
+
+def seg_edges(m2, sector, barrier, low: float, high: float):
+    """-> (cls u8 0/1/2 after non-maximum suppression, edge u8 after hysteresis)."""
+    m2 = np.ascontiguousarray(m2, dtype=np.float32)
+    H, W = m2.shape
+    sec = np.ascontiguousarray(sector, dtype=np.uint8)
+    bar = np.ascontiguousarray(barrier, dtype=np.uint8)
+    cls = np.zeros((H, W), np.uint8)
+    edge = np.zeros((H, W), np.uint8)
+    lib().orc_seg_edges(_p(m2), _p(sec), _p(bar), W, H, float(low), float(high), _p(cls), _p(edge))
+    return cls, edge
+
+
+def seg_regions(mask, min_area: int, max_regions: int):
+    """Ranked 4-connected components of mask -> (int16 [H][W] labels, count)."""
+    m = np.ascontiguousarray(mask != 0, dtype=np.uint8)
+    H, W = m.shape
+    reg = np.zeros((H, W), np.int16)
+    n = lib().orc_seg_regions(_p(m), W, H, int(min_area), int(max_regions), _p(reg))
+    return reg, n
+
+
+def segment(N, nvalid, low: float, high: float, min_area: int, max_regions: int):
+    """Canny on the normal image, then its regions -> (int16 labels, count, edge u8)."""
+    N = np.ascontiguousarray(N, dtype=np.float32)
+    _, H, W = N.shape
+    nv = np.ascontiguousarray(nvalid != 0, dtype=np.uint8)
+    reg = np.zeros((H, W), np.int16)
+    edge = np.zeros((H, W), np.uint8)
+    n = lib().orc_segment(_p(N), _p(nv), W, H, float(low), float(high), int(min_area), int(max_regions), _p(reg),
+                          _p(edge))
+    return reg, n, edge
 
 
 @dataclass

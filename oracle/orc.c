@@ -33,6 +33,7 @@
 #include "orc.h"
 
 #include <math.h>
+#include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -708,4 +709,195 @@ int orc_ransac_regions(const double* P, const uint8_t* valid, const int16_t* reg
     }
     free(list);
     return n_stored;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Segmentation of the normal image (Sec. III-D: Canny edges on the normal   */
+/* image; the regions between edges are the candidate planes).              */
+/* The paper names the steps only; the readings:                            */
+/*  - gradient of the vector image: 3x3 Sobel sums of each normal channel   */
+/*    (the kernels of Eq. 2), structure tensor Exx = sum gx^2, Eyy = sum     */
+/*    gy^2, Exy = sum gx gy; magnitude^2 m2 = Exx + Eyy; edge direction      */
+/*    from the doubled angle (A, B) = (Exx - Eyy, 2 Exy) of the principal    */
+/*    eigenvector, in four sectors;                                          */
+/*  - a pixel whose 3x3 window holds an invalid normal is a barrier (no     */
+/*    gradient, no edge, no region);                                         */
+/*  - non-maximum suppression along the sector: keep m2 > m2(behind) and     */
+/*    m2 >= m2(ahead); thresholds m2 > low^2 (weak), m2 > high^2 (strong);    */
+/*    hysteresis keeps weak pixels 8-connected to a strong one;              */
+/*  - regions: 4-connected components of valid, non-barrier pixels with no   */
+/*    edge pixel in their 3x3 window (edges closed by one dilation), with at */
+/*    least min_area pixels, numbered by size (ties: smallest pixel index    */
+/*    first), at most max_regions.                                           */
+/* All floating-point decisions are taken in FP32 (float, no contraction),  */
+/* in the order written here.                                               */
+/* ------------------------------------------------------------------------ */
+void orc_seg_grad(const float* N, const uint8_t* nvalid, int W, int H, float* m2, uint8_t* sector, uint8_t* barrier) {
+    const size_t n = (size_t)W * H;
+#pragma omp parallel for schedule(static)
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            size_t p = (size_t)v * W + u;
+            int ok = u >= 1 && u < W - 1 && v >= 1 && v < H - 1;
+            for (int dv = -1; dv <= 1 && ok; ++dv)
+                for (int du = -1; du <= 1; ++du)
+                    if (!nvalid[p + (ptrdiff_t)dv * W + du]) ok = 0;
+            barrier[p] = !ok;
+            m2[p] = 0.0f;
+            sector[p] = 0;
+            if (!ok) continue;
+            float exx = 0.0f, eyy = 0.0f, exy = 0.0f;
+            for (int c = 0; c < 3; ++c) {
+                const float* ch = N + (size_t)c * n;
+#define NV(du, dv) ch[p + (ptrdiff_t)(dv) * W + (du)]
+                /* Sobel sums: right minus left column (1,2,1 rows); bottom minus top row */
+                float gx = ((NV(1, -1) - NV(-1, -1)) + 2.0f * (NV(1, 0) - NV(-1, 0))) + (NV(1, 1) - NV(-1, 1));
+                float gy = ((NV(-1, 1) - NV(-1, -1)) + 2.0f * (NV(0, 1) - NV(0, -1))) + (NV(1, 1) - NV(1, -1));
+#undef NV
+                exx = exx + gx * gx;
+                eyy = eyy + gy * gy;
+                exy = exy + gx * gy;
+            }
+            m2[p] = exx + eyy;
+            float A = exx - eyy, B = 2.0f * exy;
+            /* sector of theta = atan2(B, A) / 2: 0 across columns, 1 along (+1,+1), 2 across rows, 3 along (+1,-1) */
+            float aA = fabsf(A), aB = fabsf(B);
+            uint8_t s;
+            if (aB <= aA) s = A >= 0.0f ? 0 : 2;
+            else s = B > 0.0f ? 1 : 3;
+            sector[p] = s;
+        }
+}
+
+static const int SEC_DU[4] = {1, 1, 0, 1};
+static const int SEC_DV[4] = {0, 1, 1, -1};
+
+void orc_seg_edges(const float* m2, const uint8_t* sector, const uint8_t* barrier, int W, int H, float low, float high,
+                   uint8_t* cls, uint8_t* edge) {
+    const size_t n = (size_t)W * H;
+    const float lo2 = low * low, hi2 = high * high;
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            size_t p = (size_t)v * W + u;
+            cls[p] = 0;
+            if (barrier[p]) continue;
+            int s = sector[p];
+            int ua = u + SEC_DU[s], va = v + SEC_DV[s], ub = u - SEC_DU[s], vb = v - SEC_DV[s];
+            float ahead = (ua >= 0 && ua < W && va >= 0 && va < H) ? m2[(size_t)va * W + ua] : 0.0f;
+            float behind = (ub >= 0 && ub < W && vb >= 0 && vb < H) ? m2[(size_t)vb * W + ub] : 0.0f;
+            if (!(m2[p] > behind && m2[p] >= ahead)) continue;
+            cls[p] = m2[p] > hi2 ? 2 : (m2[p] > lo2 ? 1 : 0);
+        }
+    /* hysteresis: breadth-first from every strong pixel through weak ones (8-connectivity) */
+    int32_t* q = (int32_t*)malloc((n > 0 ? n : 1) * sizeof(int32_t));
+    for (size_t p = 0; p < n; ++p) edge[p] = 0;
+    size_t head = 0, tail = 0;
+    for (size_t p = 0; p < n; ++p)
+        if (cls[p] == 2) {
+            edge[p] = 1;
+            q[tail++] = (int32_t)p;
+        }
+    while (head < tail) {
+        int p = q[head++];
+        int u = p % W, v = p / W;
+        for (int dv = -1; dv <= 1; ++dv)
+            for (int du = -1; du <= 1; ++du) {
+                int uu = u + du, vv = v + dv;
+                if (uu < 0 || uu >= W || vv < 0 || vv >= H) continue;
+                size_t qq = (size_t)vv * W + uu;
+                if (cls[qq] >= 1 && !edge[qq]) {
+                    edge[qq] = 1;
+                    q[tail++] = (int32_t)qq;
+                }
+            }
+    }
+    free(q);
+}
+
+typedef struct {
+    int32_t size, root;
+} seg_comp;
+
+static int seg_comp_cmp(const void* a, const void* b) {
+    const seg_comp* x = (const seg_comp*)a;
+    const seg_comp* y = (const seg_comp*)b;
+    if (x->size != y->size) return x->size > y->size ? -1 : 1;
+    return x->root < y->root ? -1 : (x->root > y->root);
+}
+
+/* region pixels: mask != 0; 4-connected components (breadth-first), ranked. Returns the number of regions. */
+int orc_seg_regions(const uint8_t* mask, int W, int H, int min_area, int max_regions, int16_t* region) {
+    const size_t n = (size_t)W * H;
+    int32_t* comp = (int32_t*)malloc((n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t* q = (int32_t*)malloc((n > 0 ? n : 1) * sizeof(int32_t));
+    seg_comp* cs = (seg_comp*)malloc((n > 0 ? n : 1) * sizeof(seg_comp));
+    int nc = 0;
+    for (size_t p = 0; p < n; ++p) comp[p] = -1;
+    for (size_t p0 = 0; p0 < n; ++p0) {
+        if (!mask[p0] || comp[p0] >= 0) continue;
+        size_t head = 0, tail = 0;
+        q[tail++] = (int32_t)p0;
+        comp[p0] = nc;
+        while (head < tail) {
+            int p = q[head++];
+            int u = p % W, v = p / W;
+            const int du[4] = {1, -1, 0, 0}, dv[4] = {0, 0, 1, -1};
+            for (int k = 0; k < 4; ++k) {
+                int uu = u + du[k], vv = v + dv[k];
+                if (uu < 0 || uu >= W || vv < 0 || vv >= H) continue;
+                size_t qq = (size_t)vv * W + uu;
+                if (mask[qq] && comp[qq] < 0) {
+                    comp[qq] = nc;
+                    q[tail++] = (int32_t)qq;
+                }
+            }
+        }
+        cs[nc].size = (int32_t)tail;
+        cs[nc].root = (int32_t)p0; /* the first pixel met in row-major order is the smallest index */
+        ++nc;
+    }
+    int32_t* rank = (int32_t*)malloc((nc > 0 ? nc : 1) * sizeof(int32_t));
+    seg_comp* sorted = (seg_comp*)malloc((nc > 0 ? nc : 1) * sizeof(seg_comp));
+    memcpy(sorted, cs, (size_t)nc * sizeof(seg_comp));
+    qsort(sorted, (size_t)nc, sizeof(seg_comp), seg_comp_cmp);
+    for (int i = 0; i < nc; ++i) rank[i] = -1;
+    int nr = 0;
+    for (int i = 0; i < nc && nr < max_regions; ++i) {
+        if (sorted[i].size < min_area) break;
+        rank[comp[sorted[i].root]] = nr++;
+    }
+    for (size_t p = 0; p < n; ++p) region[p] = (int16_t)(comp[p] >= 0 ? rank[comp[p]] : -1);
+    free(comp); free(q); free(cs); free(rank); free(sorted);
+    return nr;
+}
+
+/* The whole segmentation: gradient, edges, regions of valid-normal, non-barrier, non-edge pixels. */
+int orc_segment(const float* N, const uint8_t* nvalid, int W, int H, float low, float high, int min_area,
+                int max_regions, int16_t* region, uint8_t* edge_out) {
+    const size_t n = (size_t)W * H;
+    float* m2 = (float*)malloc((n > 0 ? n : 1) * sizeof(float));
+    uint8_t* sec = (uint8_t*)malloc(n > 0 ? n : 1);
+    uint8_t* bar = (uint8_t*)malloc(n > 0 ? n : 1);
+    uint8_t* cls = (uint8_t*)malloc(n > 0 ? n : 1);
+    uint8_t* edge = (uint8_t*)malloc(n > 0 ? n : 1);
+    orc_seg_grad(N, nvalid, W, H, m2, sec, bar);
+    orc_seg_edges(m2, sec, bar, W, H, low, high, cls, edge);
+    /* region pixels: valid, no barrier, no edge pixel in the 3x3 window (the
+       edges closed by one dilation, which seals the gaps suppression leaves
+       where three planes meet) */
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            size_t p = (size_t)v * W + u;
+            int near_edge = 0;
+            for (int dv = -1; dv <= 1; ++dv)
+                for (int du = -1; du <= 1; ++du) {
+                    int uu = u + du, vv = v + dv;
+                    if (uu >= 0 && uu < W && vv >= 0 && vv < H && edge[(size_t)vv * W + uu]) near_edge = 1;
+                }
+            cls[p] = nvalid[p] && !bar[p] && !near_edge;
+        }
+    int nr = orc_seg_regions(cls, W, H, min_area, max_regions, region);
+    if (edge_out) memcpy(edge_out, edge, n);
+    free(m2); free(sec); free(bar); free(cls); free(edge);
+    return nr;
 }

@@ -115,6 +115,20 @@ int orc_ransac_regions(const double* P, const uint8_t* valid, const int16_t* reg
                        double* planes, uint8_t* hvalid, double* errors, int32_t* counts, int32_t* counts_lo,
                        int32_t* counts_hi, int32_t* jstar, uint8_t* stored, double* centroids, int8_t* labels);
 
+/* Segmentation of the normal image (Canny edges, then regions).  N [3][H][W]
+ * FP32 normals, nvalid [H][W].  Every floating-point decision is in FP32.
+ * orc_seg_grad: m2 = Exx + Eyy of the channels' Sobel sums, sector 0..3 of
+ * the edge normal, barrier = an invalid normal in the 3x3 window.
+ * orc_seg_edges: cls 0/1 weak/2 strong after non-maximum suppression, edge =
+ * hysteresis result.  orc_seg_regions: ranked 4-connected components of
+ * mask.  orc_segment: all of it; returns the number of regions. */
+void orc_seg_grad(const float* N, const uint8_t* nvalid, int W, int H, float* m2, uint8_t* sector, uint8_t* barrier);
+void orc_seg_edges(const float* m2, const uint8_t* sector, const uint8_t* barrier, int W, int H, float low, float high,
+                   uint8_t* cls, uint8_t* edge);
+int orc_seg_regions(const uint8_t* mask, int W, int H, int min_area, int max_regions, int16_t* region);
+int orc_segment(const float* N, const uint8_t* nvalid, int W, int H, float low, float high, int min_area,
+                int max_regions, int16_t* region, uint8_t* edge_out);
+
 /* Whole-frame sequential RANSAC.  labels [H][W] int8 (-1 none), planes_out
  * [max_planes][4], centroids_out [max_planes][3], inliers_out, jstar_out
  * [max_planes] (NULL allowed).  Returns the number of planes emitted;
