@@ -195,6 +195,31 @@ pp_status pp_ransac_planes(pp_ctx* ctx, const float* points_dev, const uint8_t* 
                            const int16_t* region_dev_or_null, pp_frame_desc desc, const pp_ransac_params* params,
                            pp_plane* planes_dev, int32_t* n_planes_dev, int8_t* labels_dev, void* hip_stream);
 
+/* Segmentation of the normal image (Sec. III-D: Canny edges on the normal
+ * image; the regions between them are the planes region-mode RANSAC fits).
+ * From normals_dev [3][h][pitch] and valid_dev bit1 (normal valid):
+ *  - the 3x3 Sobel sums of each normal channel give the structure tensor
+ *    Exx, Eyy, Exy; m2 = Exx + Eyy is the squared gradient magnitude and the
+ *    sector of (Exx - Eyy, 2 Exy) the gradient direction (4 sectors); a pixel
+ *    whose 3x3 window holds an invalid normal (or that lies on the border) is
+ *    a barrier: no gradient, no edge, no region;
+ *  - non-maximum suppression keeps m2 > m2(behind) and m2 >= m2(ahead) along
+ *    the sector; weak m2 > low^2, strong m2 > high^2; hysteresis keeps weak
+ *    pixels 8-connected to a strong one (edges_dev_or_null [h][pitch] u8);
+ *  - regions are the 4-connected components of valid, non-barrier pixels
+ *    with no edge pixel in their 3x3 window; those of at least min_area
+ *    pixels are numbered 0, 1, ... by size (ties: smallest row-major pixel
+ *    index first), at most max_regions; region_dev [h][pitch] int16 (-1
+ *    elsewhere), n_regions_dev [1].
+ * Every floating-point decision is taken in FP32, so the result is exact
+ * and deterministic.  0 <= low <= high; 1 <= max_regions <= 32767;
+ * min_area >= 1 with width*height <= 4096 min_area.  Scratch grows on first
+ * use per shape (may allocate and synchronise the device then). */
+typedef struct { float low; float high; int32_t min_area; int32_t max_regions; } pp_segment_params;
+pp_status pp_segment(pp_ctx* ctx, const float* normals_dev, const uint8_t* valid_dev, pp_frame_desc desc,
+                     const pp_segment_params* params, int16_t* region_dev, int32_t* n_regions_dev,
+                     uint8_t* edges_dev_or_null, void* hip_stream);
+
 /* pp_ransac_planes that also fills the introspection buffers of *dbg. */
 pp_status pp_ransac_planes_dbg(pp_ctx* ctx, const float* points_dev, const uint8_t* valid_dev,
                                pp_frame_desc desc, const pp_ransac_params* params, pp_plane* planes_dev,

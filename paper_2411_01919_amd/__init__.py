@@ -21,7 +21,7 @@ from ._native import (PP_DIFFUSE_EDGE4, PP_DIFFUSE_EDGE8, PP_DIFFUSE_PIXEL, PP_E
 
 __all__ = [
     "PPError", "Server", "Context", "RansacConfig", "DiffuseConfig", "default_context", "diffuse", "normals",
-    "ransac_planes", "ransac_planes_debug", "ransac_regions", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
+    "ransac_planes", "ransac_planes_debug", "ransac_regions", "segment", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
     "planes_to_numpy", "PP_DIFFUSE_EDGE4", "PP_DIFFUSE_PIXEL", "PP_DIFFUSE_EDGE8", "PP_SCORE_FP32",
     "PP_SCORE_MFMA_F32", "PP_SCORE_BF16", "PP_SCORE_FP16",
 ]
@@ -266,6 +266,33 @@ def ransac_planes_debug(points, valid, cfg: RansacConfig, ctx: Optional[Context]
                                            _ptr(planes), _ptr(n_planes), _ptr(labels), ctypes.byref(dbg),
                                            _stream(stream)))
     return planes, n_planes, labels, dbg_t
+
+
+def segment(normals, valid, low: float = 0.35, high: float = 0.7, min_area: Optional[int] = None,
+            max_regions: int = 127, region=None, n_regions=None, edges: bool = False,
+            ctx: Optional[Context] = None, stream=None):
+    """Canny edges on the normal image and the regions between them (Sec.
+    III-D).  normals float32 [3][H][W], valid uint8 [H][W] (bit1: normal
+    valid).  Returns (region int16 [H][W], n_regions int32 [1]) and the edge
+    map uint8 [H][W] when edges=True.  min_area defaults to max(50,
+    ceil(0.002 W H))."""
+    torch = _torch()
+    _check_dev(normals, "normals", (torch.float32,))
+    _, H, W = normals.shape
+    _check_dev(valid, "valid", (torch.uint8,), (H, W))
+    dev = normals.device
+    if min_area is None:
+        min_area = max(50, -(-2 * W * H // 1000))
+    if region is None:
+        region = torch.empty((H, W), dtype=torch.int16, device=dev)
+    if n_regions is None:
+        n_regions = torch.zeros((1,), dtype=torch.int32, device=dev)
+    e = torch.empty((H, W), dtype=torch.uint8, device=dev) if edges else None
+    ctx = ctx or default_context(dev.index)
+    prm = N.SegmentParams(float(low), float(high), int(min_area), int(max_regions))
+    ctx.check(N.lib().pp_segment(ctx.h, _ptr(normals), _ptr(valid), _desc(H, W), ctypes.byref(prm), _ptr(region),
+                                 _ptr(n_regions), _ptr(e), _stream(stream)))
+    return (region, n_regions, e) if edges else (region, n_regions)
 
 
 def ransac_regions(points, valid, region, cfg: RansacConfig, planes=None, n_planes=None, labels=None,

@@ -53,6 +53,10 @@ class RegionDebug(ctypes.Structure):
                 ("jstar", c_vp)]
 
 
+class SegmentParams(ctypes.Structure):
+    _fields_ = [("low", c_f32), ("high", c_f32), ("min_area", c_i32), ("max_regions", c_i32)]
+
+
 class FrameJob(ctypes.Structure):
     _fields_ = [("depth", c_vp), ("desc", FrameDesc), ("K", Intrinsics), ("diffuse", DiffuseParams),
                 ("ransac", RansacParams), ("depth_mm", c_vp), ("points", c_vp), ("normals", c_vp),
@@ -90,6 +94,7 @@ SIGNATURES = {
     "pp_ransac_planes": (c_i32, [c_vp, c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp, c_vp, c_vp]),
     "pp_ransac_planes_dbg": (c_i32, [c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp, c_vp,
                                      ctypes.POINTER(RansacDebug), c_vp]),
+    "pp_segment": (c_i32, [c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(SegmentParams), c_vp, c_vp, c_vp, c_vp]),
     "pp_ransac_regions_dbg": (c_i32, [c_vp, c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp,
                                       c_vp, ctypes.POINTER(RegionDebug), c_vp]),
     "pp_debug_score_triples": (c_i32, [c_vp, c_vp, c_vp, FrameDesc, c_vp, c_i32, c_f32, c_i32, c_f32, c_vp, c_vp, c_vp]),

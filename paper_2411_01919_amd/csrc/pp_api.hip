@@ -60,6 +60,8 @@ struct pp_ctx {
     size_t debug_scratch_bytes = 0;
     void* region_scratch = nullptr;
     size_t region_scratch_bytes = 0;
+    void* seg_scratch = nullptr;
+    size_t seg_scratch_bytes = 0;
     // stage timing: events around each round's scoring launch
     bool timing = false;
     hipEvent_t score_ev[ppk::kMaxRounds][2] = {};
@@ -301,6 +303,7 @@ pp_status pp_ctx_destroy(pp_ctx* c) {
     if (c->batch_tab) (void)hipFree(c->batch_tab);
     if (c->debug_scratch) (void)hipFree(c->debug_scratch);
     if (c->region_scratch) (void)hipFree(c->region_scratch);
+    if (c->seg_scratch) (void)hipFree(c->seg_scratch);
     for (int i = 0; i < pp_ctx::kRing; ++i) {
         if (c->staging[i]) (void)hipHostFree(c->staging[i]);
         if (c->staging_ev[i]) (void)hipEventDestroy(c->staging_ev[i]);
@@ -552,6 +555,47 @@ pp_status pp_ransac_planes(pp_ctx* c, const float* points_dev, const uint8_t* va
         return regions_common(c, points_dev, valid_dev, region_dev_or_null, desc, p, planes_dev, n_planes_dev,
                               labels_dev, nullptr, stream);
     return ransac_common(c, points_dev, valid_dev, desc, p, planes_dev, n_planes_dev, labels_dev, nullptr, stream);
+}
+
+pp_status pp_segment(pp_ctx* c, const float* normals_dev, const uint8_t* valid_dev, pp_frame_desc desc,
+                     const pp_segment_params* p, int16_t* region_dev, int32_t* n_regions_dev, uint8_t* edges_dev,
+                     void* stream) {
+    pp_status s = check_ctx(c);
+    if (s != PP_OK) return s;
+    if (!normals_dev || !valid_dev || !region_dev || !n_regions_dev || !desc_ok(desc) || !p)
+        return fail(c, PP_E_INVAL, "pp_segment: bad argument");
+    if (!(p->low >= 0.f) || !(p->high >= p->low) || !isfinite(p->high) || p->max_regions < 1 ||
+        p->max_regions > 32767 || p->min_area < 1 ||
+        (int64_t)desc.width * desc.height > (int64_t)p->min_area * ppk::kSegMaxCand)
+        return fail(c, PP_E_INVAL, "pp_segment: bad parameters");
+    if ((s = set_device(c)) != PP_OK) return s;
+    ppk::SegDev g{};
+    g.nrm = normals_dev;
+    g.valid = valid_dev;
+    g.W = desc.width;
+    g.H = desc.height;
+    g.pitch = desc.pitch_px;
+    g.min_area = p->min_area;
+    g.max_regions = p->max_regions;
+    g.low = p->low;
+    g.high = p->high;
+    g.region = region_dev;
+    g.n_regions = n_regions_dev;
+    g.edges = edges_dev;
+    const size_t need = ppk::seg_scratch_bytes(g.W, g.H);
+    if (c->seg_scratch_bytes < need) {
+        if (c->seg_scratch) {
+            HIPCHK(c, hipDeviceSynchronize());
+            HIPCHK(c, hipFree(c->seg_scratch));
+            c->seg_scratch = nullptr;
+            c->seg_scratch_bytes = 0;
+        }
+        HIPCHK(c, hipMalloc(&c->seg_scratch, need));
+        c->seg_scratch_bytes = need;
+    }
+    ppk::seg_bind_scratch(g, c->seg_scratch);
+    HIPCHK(c, ppk::launch_segment(g, (hipStream_t)stream));
+    return PP_OK;
 }
 
 pp_status pp_ransac_regions_dbg(pp_ctx* c, const float* points_dev, const uint8_t* valid_dev,

@@ -142,6 +142,34 @@ size_t region_bind_scratch(RegionDev& r, void* scratch);  // returns the bytes u
 size_t region_scratch_bytes(int W, int H, int R, int hyps);
 hipError_t launch_regions(const RegionDev& r, hipStream_t s);
 
+// Segmentation of the normal image (one frame per call).
+constexpr int kSegMaxCand = 4096;  // components of at least min_area pixels (W*H / min_area bounds them)
+
+struct SegDev {
+    const float* nrm;        // [3][H][pitch] normals
+    const uint8_t* valid;    // [H][pitch] bit1: normal valid
+    int32_t W, H, pitch, min_area, max_regions;
+    float low, high;         // thresholds on the gradient magnitude
+    int16_t* region;         // [H][pitch] out: -1 or rank
+    int32_t* n_regions;      // [1] out
+    uint8_t* edges;          // [H][pitch] out, may be null
+    // scratch (seg_bind_scratch), [H][W] unless noted
+    float* m2;
+    int32_t* root;           // aliases m2 (dead after suppression)
+    uint8_t* meta;           // sector | barrier | weak | strong | edge bits
+    uint8_t* strong;         // by union-find root: the edge component holds a strong pixel
+    int32_t* parent;         // union-find of edge pixels
+    int32_t* parent2;        // union-find of region pixels
+    int32_t* cnt;            // component size by root
+    int32_t* rank;           // region label by root
+    unsigned long long* cand;  // [kSegMaxCand]
+    int32_t* ncand;          // [1]
+};
+
+size_t seg_bind_scratch(SegDev& s, void* scratch);  // returns the bytes used
+size_t seg_scratch_bytes(int W, int H);
+hipError_t launch_segment(const SegDev& s, hipStream_t st);
+
 // Library scratch one frame needs (the server carves it from its arena), and
 // a batch run whose frame slots use caller-provided scratch (scratch[i] for
 // jobs[i], each frame_scratch_bytes() long).

@@ -33,7 +33,8 @@ def test_ctypes_structures_match_the_c_layout(tmp_path):
     structs = {"pp_intrinsics": N.Intrinsics, "pp_frame_desc": N.FrameDesc, "pp_diffuse_params": N.DiffuseParams,
                "pp_ransac_params": N.RansacParams, "pp_plane": N.Plane, "pp_ransac_debug": N.RansacDebug,
                "pp_frame_job": N.FrameJob, "pp_tuning": N.Tuning, "pp_server_cfg": N.ServerCfg,
-               "pp_result": N.Result, "pp_server_stats": N.ServerStats, "pp_region_debug": N.RegionDebug}
+               "pp_result": N.Result, "pp_server_stats": N.ServerStats, "pp_region_debug": N.RegionDebug,
+               "pp_segment_params": N.SegmentParams}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pp.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
