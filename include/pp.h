@@ -220,6 +220,22 @@ pp_status pp_segment(pp_ctx* ctx, const float* normals_dev, const uint8_t* valid
                      const pp_segment_params* params, int16_t* region_dev, int32_t* n_regions_dev,
                      uint8_t* edges_dev_or_null, void* hip_stream);
 
+/* The contours of regions 0..n_regions-1 of a host label image region_host
+ * [height][pitch] int16 (pp_segment's output, copied to the host),
+ * simplified into polygons (Sec. III-D).  Contour: the outer boundary,
+ * traced with the Moore neighbourhood clockwise on screen from the region's
+ * first pixel in row-major order (entered from the west) until the trace is
+ * back on the start and its next move would repeat the first move.  Simplification: Douglas-Peucker on the
+ * closed contour split at the point farthest from the start; a point stays
+ * iff its distance to the chord exceeds eps_px.  Output: xy_host
+ * [max_vertices][2] int32 (x = column, y = row), offsets_host [n_regions+1]
+ * (region g's vertices are offsets[g] .. offsets[g+1]-1; none for an empty
+ * region).  Host memory only, no device work.  PP_E_NOMEM when max_vertices
+ * is too small: offsets_host[n_regions] then holds the number needed and
+ * nothing past max_vertices is written. */
+pp_status pp_region_polygons(const int16_t* region_host, pp_frame_desc desc, int32_t n_regions, double eps_px,
+                             int32_t* xy_host, int32_t max_vertices, int32_t* offsets_host);
+
 /* pp_ransac_planes that also fills the introspection buffers of *dbg. */
 pp_status pp_ransac_planes_dbg(pp_ctx* ctx, const float* points_dev, const uint8_t* valid_dev,
                                pp_frame_desc desc, const pp_ransac_params* params, pp_plane* planes_dev,

@@ -53,6 +53,7 @@ def lib():
         L.orc_seg_edges.argtypes = [P, P, P, i, i, f, f, P, P]
         L.orc_seg_regions.argtypes = [P, i, i, i, i, P]
         L.orc_segment.argtypes = [P, P, i, i, f, f, i, i, P, P]
+        L.orc_region_polygons.argtypes = [P, i, i, i, d, P, i, P]
         L.orc_ransac_regions.argtypes = [P, P, P, i, i, i, P, P, P, P, P, P, P, P, P, P, P, P, P, P]
         L.orc_normals.argtypes = [P, P, i, i, P, P, P, P]
         L.orc_valid_list.argtypes = [P, i, P]
@@ -380,6 +381,17 @@ def segment(N, nvalid, low: float, high: float, min_area: int, max_regions: int)
     n = lib().orc_segment(_p(N), _p(nv), W, H, float(low), float(high), int(min_area), int(max_regions), _p(reg),
                           _p(edge))
     return reg, n, edge
+
+
+def region_polygons(region, n_regions: int, eps: float):
+    """Simplified contour polygons of regions 0..n_regions-1 -> list of int32 [k][2] (x, y) arrays."""
+    reg = np.ascontiguousarray(region, dtype=np.int16)
+    H, W = reg.shape
+    off = np.zeros(n_regions + 1, np.int32)
+    need = lib().orc_region_polygons(_p(reg), W, H, int(n_regions), float(eps), None, 0, _p(off))
+    xy = np.zeros((max(need, 1), 2), np.int32)
+    lib().orc_region_polygons(_p(reg), W, H, int(n_regions), float(eps), _p(xy), need, _p(off))
+    return [xy[off[g]:off[g + 1]].copy() for g in range(n_regions)]
 
 
 @dataclass

@@ -901,3 +901,141 @@ int orc_segment(const float* N, const uint8_t* nvalid, int W, int H, float low, 
     free(m2); free(sec); free(bar); free(cls); free(edge);
     return nr;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Region contours simplified into polygons (Sec. III-D: contours of the     */
+/* segmented normal image, simplified into polygons).  Readings:            */
+/*  - the contour of region g is its outer boundary, traced with the Moore  */
+/*    neighbourhood clockwise (on screen, y down) from the region's first   */
+/*    pixel in row-major order, entered from the west; the trace stops when */
+/*    it is back on the first pixel and would repeat its first move;        */
+/*  - simplification: Douglas-Peucker on the closed contour, split at the   */
+/*    contour point farthest from the first (the first such in order); a    */
+/*    point is kept iff its distance to the current chord exceeds eps px;   */
+/*  - vertices are pixel coordinates (x = column, y = row), clockwise from  */
+/*    the first pixel.                                                      */
+/* ------------------------------------------------------------------------ */
+static const int MOORE_DX[8] = {-1, -1, 0, 1, 1, 1, 0, -1}; /* W NW N NE E SE S SW */
+static const int MOORE_DY[8] = {0, -1, -1, -1, 0, 1, 1, 1};
+
+static int in_region(const int16_t* reg, int W, int H, int x, int y, int g) {
+    return x >= 0 && x < W && y >= 0 && y < H && reg[(size_t)y * W + x] == g;
+}
+
+/* Boundary pixels of region g from its first pixel (sx, sy), into bx/by
+ * (capacity cap, at least 4 n_g + 8); returns their number.  b is the
+ * direction from the current pixel to the last outside pixel checked.  The
+ * trace ends when it stands on the start pixel again and its next move
+ * would repeat the first move out of it. */
+static int trace_boundary(const int16_t* reg, int W, int H, int g, int sx, int sy, int* bx, int* by, int cap) {
+    int n = 0, cx = sx, cy = sy, b = 0; /* entered from the west */
+    int fx = -1, fy = -1;               /* the first move's target */
+    bx[n] = sx; by[n] = sy; ++n;
+    for (int guard = 0; guard < cap; ++guard) {
+        int found = -1;
+        for (int k = 1; k <= 8; ++k) {
+            int d = (b + k) & 7;
+            if (in_region(reg, W, H, cx + MOORE_DX[d], cy + MOORE_DY[d], g)) { found = d; break; }
+        }
+        if (found < 0) break; /* a single pixel */
+        int ox = cx + MOORE_DX[(found + 7) & 7], oy = cy + MOORE_DY[(found + 7) & 7];
+        int nx = cx + MOORE_DX[found], ny = cy + MOORE_DY[found];
+        if (guard == 0) { fx = nx; fy = ny; }
+        else if (cx == sx && cy == sy && nx == fx && ny == fy) { --n; break; } /* drop the repeated start */
+        int nb = 0;
+        for (int d = 0; d < 8; ++d)
+            if (nx + MOORE_DX[d] == ox && ny + MOORE_DY[d] == oy) nb = d;
+        if (n >= cap) break;
+        bx[n] = nx; by[n] = ny; ++n;
+        cx = nx; cy = ny; b = nb;
+    }
+    return n;
+}
+
+/* distance of p to the line through a and c (to a when a == c) */
+static double chord_dist(double px, double py, double ax, double ay, double cx, double cy) {
+    double dx = cx - ax, dy = cy - ay;
+    double len = sqrt(dx * dx + dy * dy);
+    if (len == 0.0) return sqrt((px - ax) * (px - ax) + (py - ay) * (py - ay));
+    return fabs(dx * (py - ay) - dy * (px - ax)) / len;
+}
+
+/* Douglas-Peucker on the open chain idx[0..m-1] of points (bx, by): keep[] marks kept ones */
+static void dp_chain(const int* bx, const int* by, const int* idx, int m, double eps, uint8_t* keep, int* stack) {
+    keep[0] = keep[m - 1] = 1;
+    int top = 0;
+    stack[top++] = 0; stack[top++] = m - 1;
+    while (top > 0) {
+        int hi = stack[--top], lo = stack[--top];
+        if (hi - lo < 2) continue;
+        double best = -1.0;
+        int bi = -1;
+        for (int i = lo + 1; i < hi; ++i) {
+            double d = chord_dist(bx[idx[i]], by[idx[i]], bx[idx[lo]], by[idx[lo]], bx[idx[hi]], by[idx[hi]]);
+            if (d > best) { best = d; bi = i; }
+        }
+        if (best > eps) {
+            keep[bi] = 1;
+            stack[top++] = lo; stack[top++] = bi;
+            stack[top++] = bi; stack[top++] = hi;
+        }
+    }
+}
+
+int orc_region_polygons(const int16_t* region, int W, int H, int n_regions, double eps, int32_t* xy,
+                        int max_vertices, int32_t* offsets) {
+    const size_t n = (size_t)W * H;
+    int cap = 4 * (int)n + 8;
+    int* bx = (int*)malloc((size_t)cap * sizeof(int));
+    int* by = (int*)malloc((size_t)cap * sizeof(int));
+    int* idx = (int*)malloc((size_t)(cap + 1) * sizeof(int));
+    int* stack = (int*)malloc((size_t)(2 * cap + 8) * sizeof(int));
+    uint8_t* keep = (uint8_t*)malloc((size_t)cap + 1);
+    int total = 0;
+    for (int g = 0; g < n_regions; ++g) {
+        offsets[g] = total;
+        size_t first = n;
+        for (size_t p = 0; p < n; ++p)
+            if (region[p] == g) { first = p; break; }
+        if (first == n) continue;
+        int sx = (int)(first % W), sy = (int)(first / W);
+        int m = trace_boundary(region, W, H, g, sx, sy, bx, by, cap);
+        int kept_n = 0;
+        int* out_i = idx; /* reuse: indices of the kept points, in contour order */
+        if (m <= 2) {
+            for (int i = 0; i < m; ++i) out_i[kept_n++] = i;
+        } else {
+            int far = 0;
+            double fd = -1.0;
+            for (int i = 1; i < m; ++i) {
+                double d = sqrt((double)(bx[i] - sx) * (bx[i] - sx) + (double)(by[i] - sy) * (by[i] - sy));
+                if (d > fd) { fd = d; far = i; }
+            }
+            /* chain A = 0..far, chain B = far..m-1, 0 */
+            int* ca = (int*)malloc((size_t)(m + 1) * sizeof(int));
+            uint8_t* ka = (uint8_t*)calloc((size_t)m + 1, 1);
+            for (int i = 0; i <= far; ++i) ca[i] = i;
+            dp_chain(bx, by, ca, far + 1, eps, ka, stack);
+            for (int i = 0; i < far; ++i)
+                if (ka[i]) out_i[kept_n++] = ca[i];
+            int mb = m - far + 1;
+            for (int i = 0; i < mb; ++i) ca[i] = i < m - far ? far + i : 0;
+            memset(ka, 0, (size_t)m + 1);
+            dp_chain(bx, by, ca, mb, eps, ka, stack);
+            for (int i = 0; i < mb - 1; ++i)
+                if (ka[i]) out_i[kept_n++] = ca[i];
+            free(ca);
+            free(ka);
+        }
+        for (int i = 0; i < kept_n; ++i) {
+            if (total < max_vertices) {
+                xy[2 * total] = bx[out_i[i]];
+                xy[2 * total + 1] = by[out_i[i]];
+            }
+            ++total;
+        }
+    }
+    offsets[n_regions] = total;
+    free(bx); free(by); free(idx); free(stack); free(keep);
+    return total;
+}

@@ -129,6 +129,15 @@ int orc_seg_regions(const uint8_t* mask, int W, int H, int min_area, int max_reg
 int orc_segment(const float* N, const uint8_t* nvalid, int W, int H, float low, float high, int min_area,
                 int max_regions, int16_t* region, uint8_t* edge_out);
 
+/* Contours of the regions 0..n_regions-1 of a label image, simplified into
+ * polygons (Moore tracing clockwise from each region's first pixel, Jacob's
+ * stop; Douglas-Peucker with tolerance eps px on the closed contour).
+ * xy [max_vertices][2] (x, y) pixel vertices; offsets [n_regions+1].
+ * Returns the total vertex count (may exceed max_vertices: nothing past it
+ * is written). */
+int orc_region_polygons(const int16_t* region, int W, int H, int n_regions, double eps, int32_t* xy,
+                        int max_vertices, int32_t* offsets);
+
 /* Whole-frame sequential RANSAC.  labels [H][W] int8 (-1 none), planes_out
  * [max_planes][4], centroids_out [max_planes][3], inliers_out, jstar_out
  * [max_planes] (NULL allowed).  Returns the number of planes emitted;

@@ -21,7 +21,7 @@ from ._native import (PP_DIFFUSE_EDGE4, PP_DIFFUSE_EDGE8, PP_DIFFUSE_PIXEL, PP_E
 
 __all__ = [
     "PPError", "Server", "Context", "RansacConfig", "DiffuseConfig", "default_context", "diffuse", "normals",
-    "ransac_planes", "ransac_planes_debug", "ransac_regions", "segment", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
+    "ransac_planes", "ransac_planes_debug", "ransac_regions", "segment", "region_polygons", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
     "planes_to_numpy", "PP_DIFFUSE_EDGE4", "PP_DIFFUSE_PIXEL", "PP_DIFFUSE_EDGE8", "PP_SCORE_FP32",
     "PP_SCORE_MFMA_F32", "PP_SCORE_BF16", "PP_SCORE_FP16",
 ]
@@ -293,6 +293,29 @@ def segment(normals, valid, low: float = 0.35, high: float = 0.7, min_area: Opti
     ctx.check(N.lib().pp_segment(ctx.h, _ptr(normals), _ptr(valid), _desc(H, W), ctypes.byref(prm), _ptr(region),
                                  _ptr(n_regions), _ptr(e), _stream(stream)))
     return (region, n_regions, e) if edges else (region, n_regions)
+
+
+def region_polygons(region, n_regions: int, eps_px: float = 1.5):
+    """Contours of regions 0..n_regions-1 of a label image (host numpy int16
+    [H][W] or a device tensor, copied to the host) simplified into polygons:
+    a list of int32 [k][2] (x, y) vertex arrays, clockwise from each region's
+    first pixel."""
+    import numpy as np
+    if hasattr(region, "detach"):
+        region = region.detach().cpu().numpy()
+    reg = np.ascontiguousarray(region, dtype=np.int16)
+    H, W = reg.shape
+    off = np.zeros(n_regions + 1, np.int32)
+    L = N.lib()
+    st = L.pp_region_polygons(reg.ctypes.data, _desc(H, W), int(n_regions), float(eps_px), None, 0, off.ctypes.data)
+    if st not in (N.PP_OK, N.PP_E_NOMEM):
+        raise PPError(st, "pp_region_polygons")
+    xy = np.zeros((max(int(off[-1]), 1), 2), np.int32)
+    st = L.pp_region_polygons(reg.ctypes.data, _desc(H, W), int(n_regions), float(eps_px), xy.ctypes.data,
+                              int(off[-1]), off.ctypes.data)
+    if st != N.PP_OK:
+        raise PPError(st, "pp_region_polygons")
+    return [xy[off[g]:off[g + 1]].copy() for g in range(n_regions)]
 
 
 def ransac_regions(points, valid, region, cfg: RansacConfig, planes=None, n_planes=None, labels=None,

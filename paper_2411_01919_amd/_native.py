@@ -94,6 +94,7 @@ SIGNATURES = {
     "pp_ransac_planes": (c_i32, [c_vp, c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp, c_vp, c_vp]),
     "pp_ransac_planes_dbg": (c_i32, [c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp, c_vp,
                                      ctypes.POINTER(RansacDebug), c_vp]),
+    "pp_region_polygons": (c_i32, [c_vp, FrameDesc, c_i32, ctypes.c_double, c_vp, c_i32, c_vp]),
     "pp_segment": (c_i32, [c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(SegmentParams), c_vp, c_vp, c_vp, c_vp]),
     "pp_ransac_regions_dbg": (c_i32, [c_vp, c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp,
                                       c_vp, ctypes.POINTER(RegionDebug), c_vp]),
