@@ -236,6 +236,54 @@ pp_status pp_segment(pp_ctx* ctx, const float* normals_dev, const uint8_t* valid
 pp_status pp_region_polygons(const int16_t* region_host, pp_frame_desc desc, int32_t n_regions, double eps_px,
                              int32_t* xy_host, int32_t max_vertices, int32_t* offsets_host);
 
+/* ---------------------------------------------------------------- map */
+/* Polygon map with vertical drift compensation (Sec. III-E, Eqs. 4-10), host
+ * code in float64.  The map keeps near-horizontal polygons (normal within
+ * max_tilt_deg of world +Z; the others are skipped).  pp_map_integrate takes
+ * one frame: the camera pose from odometry (R world<-camera row-major, C the
+ * camera centre; its height may drift) and the frame's polygons in the camera
+ * frame (plane n.p + d = 0, centroid, support, and the pixel polygon of
+ * pp_region_polygons, lifted onto the plane through K).  A polygon's raw
+ * height is its centroid's world z.  It matches the map polygon whose
+ * footprint (convex hull in world x, y) overlaps its own with positive area
+ * and whose height is within drift_tolerance_m (Eq. 5; the paper's 5 cm) of
+ * the raw height minus the drift estimate; the smallest difference wins,
+ * ties to the older map polygon.  The measurement z_k is the mean of raw
+ * minus map height over the matches; the drift filter predicts (Eqs. 6-7:
+ * P += sigma_p) and, with a measurement, updates (Eqs. 8-10).  The polygons,
+ * corrected by the updated estimate, merge into their match (hull of both,
+ * support-weighted height, supports add) or are appended, in input order.
+ * match_of_out [n] (may be NULL): map index, -1 appended, -2 skipped. */
+typedef struct pp_map pp_map;
+typedef struct { double drift_tolerance_m; double sigma_p; double sigma_m; double max_tilt_deg; } pp_map_params;
+typedef struct {
+    double n[3];
+    double d;
+    double centroid[3];
+    int32_t support;
+    int32_t n_vertices;
+    const int32_t* xy_px; /* [n_vertices][2] (x = column, y = row) */
+} pp_map_observation;
+typedef struct {
+    int32_t matched, added, skipped, pad;
+    double measurement; /* z_k, NaN without a match */
+    double drift;       /* x_k */
+    double variance;    /* P_k */
+} pp_map_frame_result;
+typedef struct { double height; int64_t support; int32_t n_vertices; int32_t pad; } pp_map_polygon_info;
+/* 0 < drift_tolerance_m, 0 <= sigma_p, 0 < sigma_m, 0 <= max_tilt_deg < 90. */
+pp_status pp_map_create(const pp_map_params* params, pp_map** out);
+pp_status pp_map_destroy(pp_map* map);
+pp_status pp_map_integrate(pp_map* map, pp_intrinsics K, const double* R_world_cam, const double* C_world,
+                           const pp_map_observation* polygons, int32_t n, int32_t* match_of_out,
+                           pp_map_frame_result* out);
+pp_status pp_map_size(const pp_map* map, int32_t* n);
+/* Map polygon i: height, support, and its footprint's vertices (counter-
+ * clockwise, world x, y) into xy_out [max_vertices][2]; PP_E_NOMEM (with
+ * info->n_vertices set) when max_vertices is too small. */
+pp_status pp_map_polygon(const pp_map* map, int32_t i, pp_map_polygon_info* info, double* xy_out,
+                         int32_t max_vertices);
+
 /* pp_ransac_planes that also fills the introspection buffers of *dbg. */
 pp_status pp_ransac_planes_dbg(pp_ctx* ctx, const float* points_dev, const uint8_t* valid_dev,
                                pp_frame_desc desc, const pp_ransac_params* params, pp_plane* planes_dev,

@@ -21,7 +21,7 @@ from ._native import (PP_DIFFUSE_EDGE4, PP_DIFFUSE_EDGE8, PP_DIFFUSE_PIXEL, PP_E
 
 __all__ = [
     "PPError", "Server", "Context", "RansacConfig", "DiffuseConfig", "default_context", "diffuse", "normals",
-    "ransac_planes", "ransac_planes_debug", "ransac_regions", "segment", "region_polygons", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
+    "ransac_planes", "ransac_planes_debug", "ransac_regions", "segment", "region_polygons", "DriftMap", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
     "planes_to_numpy", "PP_DIFFUSE_EDGE4", "PP_DIFFUSE_PIXEL", "PP_DIFFUSE_EDGE8", "PP_SCORE_FP32",
     "PP_SCORE_MFMA_F32", "PP_SCORE_BF16", "PP_SCORE_FP16",
 ]
@@ -316,6 +316,70 @@ def region_polygons(region, n_regions: int, eps_px: float = 1.5):
     if st != N.PP_OK:
         raise PPError(st, "pp_region_polygons")
     return [xy[off[g]:off[g + 1]].copy() for g in range(n_regions)]
+
+
+class DriftMap:
+    """The polygon map with vertical drift compensation (Sec. III-E, Eqs.
+    4-10), host code behind the C ABI.  integrate() takes the intrinsics, the
+    odometry pose (R world<-camera, camera centre) and the frame's polygons
+    as (n[3], d, centroid[3], support, xy_px int32 [k][2]) in the camera frame."""
+
+    def __init__(self, drift_tolerance_m: float = 0.05, sigma_p: float = 1e-5, sigma_m: float = 1e-4,
+                 max_tilt_deg: float = 15.0):
+        self._lib = N.lib()
+        h = ctypes.c_void_p()
+        st = self._lib.pp_map_create(ctypes.byref(N.MapParams(drift_tolerance_m, sigma_p, sigma_m, max_tilt_deg)),
+                                     ctypes.byref(h))
+        if st != N.PP_OK:
+            raise PPError(st, "pp_map_create")
+        self.h = h.value
+
+    def integrate(self, K, R, C, polygons):
+        import numpy as np
+        keep = []
+        obs = (N.MapObservation * max(1, len(polygons)))()
+        for i, (n, d, cen, sup, xy) in enumerate(polygons):
+            xy = np.ascontiguousarray(xy, dtype=np.int32).reshape(-1, 2)
+            keep.append(xy)
+            obs[i].n[:] = [float(v) for v in n]
+            obs[i].d = float(d)
+            obs[i].centroid[:] = [float(v) for v in cen]
+            obs[i].support = int(sup)
+            obs[i].n_vertices = len(xy)
+            obs[i].xy_px = xy.ctypes.data
+        Rm = np.ascontiguousarray(R, dtype=np.float64).reshape(9)
+        Cm = np.ascontiguousarray(C, dtype=np.float64).reshape(3)
+        match = np.zeros(max(1, len(polygons)), np.int32)
+        res = N.MapFrameResult()
+        st = self._lib.pp_map_integrate(self.h, N.Intrinsics(*[float(v) for v in K]), Rm.ctypes.data, Cm.ctypes.data,
+                                        obs, len(polygons), match.ctypes.data, ctypes.byref(res))
+        if st != N.PP_OK:
+            raise PPError(st, "pp_map_integrate")
+        return dict(matched=res.matched, added=res.added, skipped=res.skipped, measurement=res.measurement,
+                    drift=res.drift, variance=res.variance, match_of=match[:len(polygons)].tolist())
+
+    def polygons(self):
+        import numpy as np
+        n = ctypes.c_int32()
+        self._lib.pp_map_size(self.h, ctypes.byref(n))
+        out = []
+        for i in range(n.value):
+            info = N.MapPolygonInfo()
+            self._lib.pp_map_polygon(self.h, i, ctypes.byref(info), None, 0)
+            xy = np.zeros((max(1, info.n_vertices), 2))
+            st = self._lib.pp_map_polygon(self.h, i, ctypes.byref(info), xy.ctypes.data, info.n_vertices)
+            if st != N.PP_OK:
+                raise PPError(st, "pp_map_polygon")
+            out.append(dict(height=info.height, support=info.support, hull=xy[:info.n_vertices].copy()))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.pp_map_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def ransac_regions(points, valid, region, cfg: RansacConfig, planes=None, n_planes=None, labels=None,

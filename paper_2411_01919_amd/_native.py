@@ -57,6 +57,25 @@ class SegmentParams(ctypes.Structure):
     _fields_ = [("low", c_f32), ("high", c_f32), ("min_area", c_i32), ("max_regions", c_i32)]
 
 
+class MapParams(ctypes.Structure):
+    _fields_ = [("drift_tolerance_m", ctypes.c_double), ("sigma_p", ctypes.c_double), ("sigma_m", ctypes.c_double),
+                ("max_tilt_deg", ctypes.c_double)]
+
+
+class MapObservation(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_double * 3), ("d", ctypes.c_double), ("centroid", ctypes.c_double * 3),
+                ("support", c_i32), ("n_vertices", c_i32), ("xy_px", c_vp)]
+
+
+class MapFrameResult(ctypes.Structure):
+    _fields_ = [("matched", c_i32), ("added", c_i32), ("skipped", c_i32), ("pad", c_i32),
+                ("measurement", ctypes.c_double), ("drift", ctypes.c_double), ("variance", ctypes.c_double)]
+
+
+class MapPolygonInfo(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_double), ("support", ctypes.c_int64), ("n_vertices", c_i32), ("pad", c_i32)]
+
+
 class FrameJob(ctypes.Structure):
     _fields_ = [("depth", c_vp), ("desc", FrameDesc), ("K", Intrinsics), ("diffuse", DiffuseParams),
                 ("ransac", RansacParams), ("depth_mm", c_vp), ("points", c_vp), ("normals", c_vp),
@@ -94,6 +113,11 @@ SIGNATURES = {
     "pp_ransac_planes": (c_i32, [c_vp, c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp, c_vp, c_vp]),
     "pp_ransac_planes_dbg": (c_i32, [c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp, c_vp,
                                      ctypes.POINTER(RansacDebug), c_vp]),
+    "pp_map_create": (c_i32, [ctypes.POINTER(MapParams), ctypes.POINTER(c_vp)]),
+    "pp_map_destroy": (c_i32, [c_vp]),
+    "pp_map_integrate": (c_i32, [c_vp, Intrinsics, c_vp, c_vp, c_vp, c_i32, c_vp, ctypes.POINTER(MapFrameResult)]),
+    "pp_map_size": (c_i32, [c_vp, ctypes.POINTER(c_i32)]),
+    "pp_map_polygon": (c_i32, [c_vp, c_i32, ctypes.POINTER(MapPolygonInfo), c_vp, c_i32]),
     "pp_region_polygons": (c_i32, [c_vp, FrameDesc, c_i32, ctypes.c_double, c_vp, c_i32, c_vp]),
     "pp_segment": (c_i32, [c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(SegmentParams), c_vp, c_vp, c_vp, c_vp]),
     "pp_ransac_regions_dbg": (c_i32, [c_vp, c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp,

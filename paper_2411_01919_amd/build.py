@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpp.so")
-SOURCES = ["csrc/pp_kernels.hip", "csrc/pp_regions.hip", "csrc/pp_segment.hip", "csrc/pp_polygons.cpp", "csrc/pp_api.hip", "csrc/pp_server.hip"]
+SOURCES = ["csrc/pp_kernels.hip", "csrc/pp_regions.hip", "csrc/pp_segment.hip", "csrc/pp_polygons.cpp", "csrc/pp_map.cpp", "csrc/pp_api.hip", "csrc/pp_server.hip"]
 ARCH = os.environ.get("PP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -34,7 +34,9 @@ def test_ctypes_structures_match_the_c_layout(tmp_path):
                "pp_ransac_params": N.RansacParams, "pp_plane": N.Plane, "pp_ransac_debug": N.RansacDebug,
                "pp_frame_job": N.FrameJob, "pp_tuning": N.Tuning, "pp_server_cfg": N.ServerCfg,
                "pp_result": N.Result, "pp_server_stats": N.ServerStats, "pp_region_debug": N.RegionDebug,
-               "pp_segment_params": N.SegmentParams}
+               "pp_segment_params": N.SegmentParams, "pp_map_params": N.MapParams,
+               "pp_map_observation": N.MapObservation, "pp_map_frame_result": N.MapFrameResult,
+               "pp_map_polygon_info": N.MapPolygonInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pp.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
