@@ -293,6 +293,48 @@ def precision_bench(pp, reps=3):
     return out
 
 
+def paper_chain_bench(pp, n_frames=24):
+    """The paper's own per-frame chain at 640x480, one frame at a time with the
+    depth resident on the device: diffusion, normals, segmentation of the
+    normal image and region-mode RANSAC (10 hypotheses per region, the
+    paper's setting) on the GPU; the region polygons and the drift-compensated
+    map on the host.  Also the three diffusion discretisations alone."""
+    import torch
+
+    import scenes
+    cfg = scenes.CONFIGS[2]
+    frames = [scenes.make_frame(2, k) for k in range(n_frames)]
+    deps = [torch.from_numpy(f.depth.view(np.int16)).cuda() for f in frames]
+    m = pp.DriftMap()
+    times, planes = {}, 0
+    pp.paper_chain(deps[0], (frames[0].K.fx, frames[0].K.fy, frames[0].K.cx, frames[0].K.cy))  # warm-up
+    t0 = time.perf_counter()
+    for k, (f, d) in enumerate(zip(frames, deps)):
+        out = pp.paper_chain(d, (f.K.fx, f.K.fy, f.K.cx, f.K.cy), m, f.pose, seed=cfg.ransac_seed, frame_id=k,
+                             times=times)
+        planes += len(out["planes"])
+    wall = (time.perf_counter() - t0) / n_frames
+    rec = {"frames": n_frames, "ms_per_frame": round(wall * 1e3, 3), "frames_per_s": round(1.0 / wall, 1),
+           "planes_per_frame": round(planes / n_frames, 2),
+           "stage_ms": {k: round(v / n_frames, 3) for k, v in times.items()}}
+    # the diffusion variants, 20 iterations on one frame
+    d = deps[0]
+    var = {}
+    for name, scheme, lam in (("edge4", pp.PP_DIFFUSE_EDGE4, 0.2), ("pixel_centred", pp.PP_DIFFUSE_PIXEL, 0.2),
+                              ("edge8", pp.PP_DIFFUSE_EDGE8, 1 / 6)):
+        out = pp.diffuse(d, 20, lam, 30.0, scheme=scheme)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            pp.diffuse(d, 20, lam, 30.0, out=out, scheme=scheme)
+        e1.record()
+        torch.cuda.synchronize()
+        var[name] = round(e0.elapsed_time(e1) / 20, 4)
+    rec["diffusion_variant_ms_per_frame"] = var
+    m.close()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +350,7 @@ def main():
     ap.add_argument("--tuning", type=str, default="", help="tile,T,hb,chunk (1-based knobs) instead of autotuning")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mfma_f32", "bf16", "fp16"],
                     help="scoring form of the batched and plain legs (all give identical results)")
+    ap.add_argument("--no-chain", action="store_true", help="skip the paper-chain leg (segmentation, region RANSAC, map)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -441,6 +484,12 @@ def main():
         log("precision-form leg")
         precision = precision_bench(pp)
 
+    chain = None
+    if not args.no_chain:
+        log("paper-chain leg")
+        chain = paper_chain_bench(pp)
+        log(f"paper chain: {chain}")
+
     base = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -473,6 +522,7 @@ def main():
         "plain": plain,
         "served": served,
         "precision_form": precision,
+        "paper_chain": chain,
         "roofline": {"bound": "alu", "kernel": score_kernel_name(args.precision, tuning),
                      "achieved": round(achieved, 3), "peak": round(FP32_VECTOR_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,

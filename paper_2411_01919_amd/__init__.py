@@ -21,7 +21,7 @@ from ._native import (PP_DIFFUSE_EDGE4, PP_DIFFUSE_EDGE8, PP_DIFFUSE_PIXEL, PP_E
 
 __all__ = [
     "PPError", "Server", "Context", "RansacConfig", "DiffuseConfig", "default_context", "diffuse", "normals",
-    "ransac_planes", "ransac_planes_debug", "ransac_regions", "segment", "region_polygons", "DriftMap", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
+    "ransac_planes", "ransac_planes_debug", "ransac_regions", "segment", "region_polygons", "DriftMap", "paper_chain", "score_triples", "FrameOutputs", "make_outputs", "batch_run",
     "planes_to_numpy", "PP_DIFFUSE_EDGE4", "PP_DIFFUSE_PIXEL", "PP_DIFFUSE_EDGE8", "PP_SCORE_FP32",
     "PP_SCORE_MFMA_F32", "PP_SCORE_BF16", "PP_SCORE_FP16",
 ]
@@ -380,6 +380,59 @@ class DriftMap:
 
     def __del__(self):
         self.close()
+
+
+def paper_chain(depth, K, drift_map: Optional["DriftMap"] = None, pose=None, diffuse_cfg: Optional[DiffuseConfig] = None,
+                low: float = 0.35, high: float = 0.7, min_area: Optional[int] = None, hyps: int = 10,
+                thresh_m: float = 0.01, seed: int = 0, frame_id: int = 0, eps_px: float = 1.5,
+                ctx: Optional[Context] = None, stream=None, times: Optional[dict] = None):
+    """The paper's per-frame chain through the library: diffusion, normals,
+    segmentation and region-mode RANSAC on the GPU, then (on the host) the
+    region polygons and, with a map and a pose (R world<-camera, camera
+    centre), the drift-compensated map update.  Returns a dict with the
+    device outputs, the stored planes and polygons, and the map result.  With
+    `times`, per-stage milliseconds are accumulated into it (device stages by
+    events on the stream, host stages by the host clock)."""
+    import time
+    torch = _torch()
+    dc = diffuse_cfg or DiffuseConfig()
+    H, W = depth.shape
+    st = torch.cuda.current_stream() if stream is None else stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if times is not None else None
+    if ev:
+        ev[0].record(st)
+    dmm = diffuse(depth, dc.iters, dc.lam, dc.kappa_mm, dc.edge_stop, ctx=ctx, stream=stream, scheme=dc.scheme)
+    if ev:
+        ev[1].record(st)
+    pts, nrm, valid = normals(dmm, K, ctx=ctx, stream=stream)
+    if ev:
+        ev[2].record(st)
+    region, n_reg = segment(nrm, valid, low, high, min_area, 127, ctx=ctx, stream=stream)
+    if ev:
+        ev[3].record(st)
+    cfg = RansacConfig(max_planes=127, hyps=hyps, min_inliers=1, thresh_m=thresh_m, seed=seed, frame_id=frame_id)
+    planes, n_planes, labels = ransac_regions(pts, valid, region, cfg, ctx=ctx, stream=stream)
+    if ev:
+        ev[4].record(st)
+    st.synchronize()
+    t0 = time.perf_counter()
+    nr = int(n_reg.cpu().item())
+    recs = planes_to_numpy(planes, 127)
+    polys = region_polygons(region, nr, eps_px)
+    stored = [g for g in range(nr) if recs[g]["hyp_index"] >= 0]
+    t1 = time.perf_counter()
+    mres = None
+    if drift_map is not None and pose is not None:
+        obs = [(recs[g]["n"], recs[g]["d"], recs[g]["centroid"], recs[g]["inliers"], polys[g]) for g in stored]
+        mres = drift_map.integrate(K, pose[0], pose[1], obs)
+    t2 = time.perf_counter()
+    if times is not None:
+        for name, a, b in (("diffusion", 0, 1), ("normals", 1, 2), ("segmentation", 2, 3), ("region_ransac", 3, 4)):
+            times[name] = times.get(name, 0.0) + ev[a].elapsed_time(ev[b])
+        times["polygons_host"] = times.get("polygons_host", 0.0) + (t1 - t0) * 1e3
+        times["map_host"] = times.get("map_host", 0.0) + (t2 - t1) * 1e3
+    return dict(depth_mm=dmm, points=pts, normals=nrm, valid=valid, region=region, n_regions=nr, labels=labels,
+                planes={g: recs[g] for g in stored}, polygons=polys, map=mres)
 
 
 def ransac_regions(points, valid, region, cfg: RansacConfig, planes=None, n_planes=None, labels=None,
