@@ -307,12 +307,13 @@ def region_polygons(region, n_regions: int, eps_px: float = 1.5):
     H, W = reg.shape
     off = np.zeros(n_regions + 1, np.int32)
     L = N.lib()
-    st = L.pp_region_polygons(reg.ctypes.data, _desc(H, W), int(n_regions), float(eps_px), None, 0, off.ctypes.data)
-    if st not in (N.PP_OK, N.PP_E_NOMEM):
-        raise PPError(st, "pp_region_polygons")
-    xy = np.zeros((max(int(off[-1]), 1), 2), np.int32)
-    st = L.pp_region_polygons(reg.ctypes.data, _desc(H, W), int(n_regions), float(eps_px), xy.ctypes.data,
-                              int(off[-1]), off.ctypes.data)
+    xy = np.zeros((16384, 2), np.int32)
+    st = L.pp_region_polygons(reg.ctypes.data, _desc(H, W), int(n_regions), float(eps_px), xy.ctypes.data, len(xy),
+                              off.ctypes.data)
+    if st == N.PP_E_NOMEM:  # more vertices than the first buffer holds: again with the exact size
+        xy = np.zeros((int(off[-1]), 2), np.int32)
+        st = L.pp_region_polygons(reg.ctypes.data, _desc(H, W), int(n_regions), float(eps_px), xy.ctypes.data,
+                                  len(xy), off.ctypes.data)
     if st != N.PP_OK:
         raise PPError(st, "pp_region_polygons")
     return [xy[off[g]:off[g + 1]].copy() for g in range(n_regions)]

@@ -130,6 +130,7 @@ struct RegionDev {
     int32_t* counts;         // [R][hyps]
     double* errors;          // [R][hyps]
     int32_t* jstar;          // [R]
+    double* cpart;           // [chunks][3] partial sums of the inliers' coordinates
     // caller outputs
     pp_plane* planes;        // [R]
     int32_t* n_planes;

@@ -10,8 +10,9 @@
 //                  chunk in list order, and the inlier count (|r| < t)
 //   k_reg_select   per region: errors summed over chunks in order; the first
 //                  smallest error wins; stored iff 10 inliers > 9 n_g
-//   k_reg_label    per stored region: labels and the FP64 centroid of the
-//                  inliers (fixed-order reduction)
+//   k_reg_label    per chunk of a stored region: labels of the inliers and
+//                  FP64 partial sums of their coordinates (fixed order)
+//   k_reg_centroid per stored region: the partial sums in chunk order
 //
 // Every sum has a fixed order, so results do not depend on scheduling.  The
 // residual is the canonical FP32 expression the whole-frame scorers use.
@@ -267,16 +268,28 @@ __global__ __launch_bounds__(kBlock) void k_reg_select(RegionDev r) {
     }
 }
 
+// Labels and the centroid's partial sums, one block per 512-point chunk of a
+// stored region's list: FP64 sums per thread in list order, then the waves
+// in order, so the result does not depend on scheduling.
 __global__ __launch_bounds__(kBlock) void k_reg_label(RegionDev r) {
     __shared__ double sh[3][kBlock / 64];
-    const int g = blockIdx.x;
+    const int c = blockIdx.x;
+    if (c >= r.choff[r.R]) return;
+    int lo = 0, hi = r.R - 1;  // the last region whose first chunk is <= c
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (r.choff[mid] <= c) lo = mid;
+        else hi = mid - 1;
+    }
+    const int g = lo;
     const int js = r.jstar[g];
     if (js < 0 || r.planes[g].hyp_index < 0) return;
     const float4 h = r.hyp[g * r.hyps + js];
-    const int o = r.off[g], n = r.npts[g];
+    const int k0 = r.off[g] + (c - r.choff[g]) * kRegionChunk;
+    const int k1 = min(k0 + kRegionChunk, r.off[g + 1]);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) {
-        const int off = r.list[o + i];
+    for (int i = k0 + threadIdx.x; i < k1; i += kBlock) {
+        const int off = r.list[i];
         const float3 p = reg_point(r, off);
         if (fabsf(canon_res(h, p.x, p.y, p.z)) < r.thresh) {
             r.labels[off] = (int8_t)g;
@@ -295,14 +308,22 @@ __global__ __launch_bounds__(kBlock) void k_reg_label(RegionDev r) {
         sh[2][w] = s2;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const double cnt = (double)r.planes[g].inliers;
-        for (int a = 0; a < 3; ++a) {
-            double s = 0.0;
-            for (int k = 0; k < kBlock / 64; ++k) s += sh[a][k];
-            r.planes[g].centroid[a] = s / cnt;
-        }
+    if (threadIdx.x < 3) {
+        double s = 0.0;
+        for (int k = 0; k < kBlock / 64; ++k) s += sh[threadIdx.x][k];
+        r.cpart[(size_t)c * 3 + threadIdx.x] = s;
     }
+}
+
+// Centroid of each stored region: its chunks' partial sums in order.
+__global__ __launch_bounds__(kBlock) void k_reg_centroid(RegionDev r) {
+    const int g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= r.R || r.jstar[g] < 0 || r.planes[g].hyp_index < 0) return;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int c = r.choff[g]; c < r.choff[g + 1]; ++c)
+        for (int a = 0; a < 3; ++a) s[a] += r.cpart[(size_t)c * 3 + a];
+    const double cnt = (double)r.planes[g].inliers;
+    for (int a = 0; a < 3; ++a) r.planes[g].centroid[a] = s[a] / cnt;
 }
 
 template <typename T>
@@ -334,6 +355,7 @@ size_t region_bind_scratch(RegionDev& r, void* scratch) {
     r.counts = carve<int32_t>(p, rh);
     r.errors = carve<double>(p, rh);
     r.jstar = carve<int32_t>(p, r.R);
+    r.cpart = carve<double>(p, (size_t)region_max_chunks(r.W, r.H, r.R) * 3);
     return (size_t)(p - base);
 }
 
@@ -354,7 +376,8 @@ hipError_t launch_regions(const RegionDev& r, hipStream_t s) {
     hipLaunchKernelGGL(k_reg_hypgen, dim3((r.R * r.hyps + kBlock - 1) / kBlock), blk, 0, s, r);
     hipLaunchKernelGGL(k_reg_score, dim3(region_max_chunks(r.W, r.H, r.R)), blk, 0, s, r);
     hipLaunchKernelGGL(k_reg_select, dim3(r.R), blk, 0, s, r);
-    hipLaunchKernelGGL(k_reg_label, dim3(r.R), blk, 0, s, r);
+    hipLaunchKernelGGL(k_reg_label, dim3(region_max_chunks(r.W, r.H, r.R)), blk, 0, s, r);
+    hipLaunchKernelGGL(k_reg_centroid, dim3((r.R + kBlock - 1) / kBlock), blk, 0, s, r);
     return hipGetLastError();
 }
 

@@ -33,11 +33,16 @@ namespace {
 
 constexpr uint8_t kBarrier = 4, kWeak = 8, kStrong = 16, kEdge = 32;
 
-__device__ __forceinline__ int uf_find(const int32_t* parent, int x) {
+// Root of x, halving the path on the way: a non-root node is re-pointed to
+// its grandparent, always an ancestor, so concurrent hooks of roots (the only
+// other writes) stay valid; a node that is not a root never becomes one.
+__device__ __forceinline__ int uf_find(int32_t* parent, int x) {
     while (true) {
         const int p = __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (p == x) return x;
-        x = p;
+        const int gp = __hip_atomic_load(parent + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (gp != p) __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = gp;
     }
 }
 
@@ -176,16 +181,23 @@ __global__ __launch_bounds__(kBlock) void k_uf_union_regions(SegDev s) {
     if (y + 1 < s.H && s.parent2[p + s.W] >= 0) uf_unite(s.parent2, p, p + s.W);
 }
 
+// Component sizes: one atomic add per distinct root in each wave (the pixels
+// of a wave mostly share one).
 __global__ __launch_bounds__(kBlock) void k_seg_count(SegDev s) {
-    int x, y;
-    if (!pix(s, x, y)) return;
+    int x = 0, y = 0;
+    const bool in = pix(s, x, y);
     const int p = y * s.W + x;
     int r = -1;
-    if (s.parent2[p] >= 0) {
-        r = uf_find(s.parent2, p);
-        atomicAdd(&s.cnt[r], 1);
+    if (in && s.parent2[p] >= 0) r = uf_find(s.parent2, p);
+    if (in) s.root[p] = r;
+    unsigned long long pending = __ballot(r >= 0);
+    while (pending) {  // wave-uniform: one pass per distinct root
+        const int leader = __ffsll(pending) - 1;
+        const int R = __shfl(r, leader);
+        const unsigned long long m = __ballot(r == R);
+        if ((int)(threadIdx.x & 63) == leader) atomicAdd(&s.cnt[R], __popcll(m));
+        pending &= ~m;
     }
-    s.root[p] = r;
 }
 
 __global__ __launch_bounds__(kBlock) void k_seg_cand(SegDev s) {
