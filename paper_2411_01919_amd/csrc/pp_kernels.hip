@@ -27,6 +27,11 @@ __device__ __forceinline__ float3 load_point(const FrameDev& f, int off) {
 
 __device__ __forceinline__ bool hyp_valid(const float4 h) { return h.w == h.w; }
 
+// exp(-(x/kappa)^2) as 2^-a with the hardware exponential (v_exp_f32, about
+// 1 ulp).  It skips the library's rescaling for subnormal results: those would
+// contribute less than 1e-30 mm to a flux.
+__device__ __forceinline__ float g_exp(float a) { return __builtin_amdgcn_exp2f(-a); }
+
 // ------------------------------------------------------------------ diffusion
 // One pass = `it` (<= T) explicit iterations on a TX x TY tile whose LDS copy
 // carries a T-pixel halo.  Iteration k updates the tile grown by T - k (for
@@ -96,12 +101,12 @@ __global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__
             if (ve[q] && ey >= s) {
                 const float D = dIe[q] + (s_d[e + 1] - dp);
                 const float a = D * D * gs;
-                s_fe[e] = (rational ? 1.0f / (1.0f + a) : exp2f(-a)) * D;
+                s_fe[e] = (rational ? 1.0f / (1.0f + a) : g_exp(a)) * D;
             }
             if (vs[q] && ex >= s) {
                 const float D = dIs[q] + (s_d[e + EW] - dp);
                 const float a = D * D * gs;
-                s_fs[e] = (rational ? 1.0f / (1.0f + a) : exp2f(-a)) * D;
+                s_fs[e] = (rational ? 1.0f / (1.0f + a) : g_exp(a)) * D;
             }
         }
         __syncthreads();
@@ -148,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__
 //                    enters both of its pixels with opposite signs.
 constexpr int kVarTX = 64, kVarTY = 16, kVarT = 5;
 
-__device__ __forceinline__ float edge_g(float a, bool rational) { return rational ? 1.0f / (1.0f + a) : exp2f(-a); }
+__device__ __forceinline__ float edge_g(float a, bool rational) { return rational ? 1.0f / (1.0f + a) : g_exp(a); }
 
 template <int SCHEME>
 __global__ __launch_bounds__(kBlock) void k_diffuse_var(const FrameDev* __restrict__ tab, int it, int first, int last,
@@ -463,11 +468,11 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
 // it is skipped if that pixel is already assigned or already chosen; 16
 // blocks at most.  The list L is fixed per frame, so the draws of round r do
 // not depend on how many points earlier rounds removed.
-// 4 lanes per hypothesis compute Philox blocks 0..3 and look up their 16
-// candidates in the assignment bitmap; one lane then walks them in order and,
-// only if fewer than 3 were usable, continues with blocks 4..15 itself.  The
-// triple is exactly the sequential draw's.
-constexpr int kHypLanes = 4;
+// 16 lanes per hypothesis compute its 16 Philox blocks at once and look up
+// their 64 candidates in the assignment bitmap; one lane then walks them in
+// draw order, so the triple is exactly the sequential draw's (the serial
+// continuation below only runs if fewer lanes are configured).
+constexpr int kHypLanes = 16;
 constexpr int kHypPerBlock = kBlock / kHypLanes;
 
 __device__ __forceinline__ bool point_taken(const FrameDev& f, int k) { return (f.abm[k >> 5] >> (k & 31)) & 1u; }
@@ -1303,7 +1308,7 @@ static void score_launch(const FrameDev* tab, int nf, int r, int max_pts, int ma
 static void score_cull_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target,
                               hipStream_t s) {
     const int tiles = (max_pts + 63) / 64;
-    hipLaunchKernelGGL(k_tile_box, dim3(clampi((tiles + 3) / 4, 1, 2048), 1, nf), dim3(kBlock), 0, s, tab, r);
+    hipLaunchKernelGGL(k_tile_box, dim3(clampi((tiles + 3) / 4, 1, 65535), 1, nf), dim3(kBlock), 0, s, tab, r);
     const int groups = (max_hyps + 63) / 64;
     const int per_frame_cap = clampi(16384 / (nf > 0 ? nf : 1), 8, 4096);
     const int bx = clampi((max_pts + target - 1) / target, 1, clampi(per_frame_cap / groups, 1, 1024));
