@@ -38,10 +38,9 @@ __device__ __forceinline__ float g_exp(float a) { return __builtin_amdgcn_exp2f(
 // it == T) pixels, so the last one is exact on the tile.  The iterate is kept
 // as delta = I - I0 with I0 the integer input, so the integer part of every
 // edge difference, (I0_q - I0_p), is exact and loop-invariant (precomputed).
-// Each iteration first computes every edge's flux once, g(D) D with
-// D = I_q - I_p, for the east and south edge of each pixel (zero across the
-// border and into holes), then every pixel adds lam times the fluxes of its
-// four edges: the flux leaves one pixel exactly as it enters the other.
+// Each iteration, every pixel computes the fluxes g(D) D of its four edges
+// from the previous iterate and writes its new value to the other LDS buffer
+// (one barrier per iteration).
 template <int TX, int TY, int T>
 __global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__ tab, int it, int first, int last,
                                                      int src, int dst) {
@@ -52,9 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__
     constexpr int EW = TX + 2 * T, EH = TY + 2 * T, EN = EW * EH;
     constexpr int NPT = (EN + kBlock - 1) / kBlock;  // extended pixels per thread
     __shared__ float s_i0[EN];
-    __shared__ float s_d[EN];
-    __shared__ float s_fe[EN];  // flux over the east edge of each pixel
-    __shared__ float s_fs[EN];  // flux over the south edge
+    __shared__ float s_d[2][EN];  // the iterate, read from one while the other is written
     const float* __restrict__ din = f.delta[src];
     for (int e = threadIdx.x; e < EN; e += kBlock) {
         const int ex = e % EW, ey = e / EW;
@@ -65,64 +62,62 @@ __global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__
             if (!first && i0 > 0.f) d = din[(size_t)y * W + x];
         }
         s_i0[e] = i0;
-        s_d[e] = d;
-        s_fe[e] = 0.f;
-        s_fs[e] = 0.f;
+        s_d[0][e] = d;
     }
     __syncthreads();
-    // loop-invariant edge data of this thread's pixels
-    float dIe[NPT], dIs[NPT];
-    bool ve[NPT], vs[NPT], vp[NPT];
+    // loop-invariant data of this thread's pixels: the integer part of the
+    // east and south differences, and which of the four edges are open
+    float i0p[NPT], dIe[NPT], dIs[NPT];
+    uint32_t open[NPT];  // bit 0 pixel valid, 1 east, 2 south, 3 west, 4 north
     int exy[NPT];
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
         const int e = threadIdx.x + q * kBlock;
         const int ex = e % EW, ey = e / EW;
         exy[q] = (ex << 16) | ey;
-        vp[q] = false; ve[q] = false; vs[q] = false; dIe[q] = 0.f; dIs[q] = 0.f;
+        open[q] = 0u; dIe[q] = 0.f; dIs[q] = 0.f; i0p[q] = 0.f;
         if (e < EN) {
             const float i0 = s_i0[e];
-            vp[q] = i0 > 0.f;
-            if (ex + 1 < EW) { const float q0 = s_i0[e + 1]; ve[q] = vp[q] && q0 > 0.f; dIe[q] = q0 - i0; }
-            if (ey + 1 < EH) { const float q0 = s_i0[e + EW]; vs[q] = vp[q] && q0 > 0.f; dIs[q] = q0 - i0; }
+            i0p[q] = i0;
+            if (i0 > 0.f) {
+                uint32_t o = 1u;
+                if (ex + 1 < EW) { const float q0 = s_i0[e + 1]; o |= q0 > 0.f ? 2u : 0u; dIe[q] = q0 - i0; }
+                if (ey + 1 < EH) { const float q0 = s_i0[e + EW]; o |= q0 > 0.f ? 4u : 0u; dIs[q] = q0 - i0; }
+                if (ex >= 1 && s_i0[e - 1] > 0.f) o |= 8u;
+                if (ey >= 1 && s_i0[e - EW] > 0.f) o |= 16u;
+                open[q] = o;
+            }
         }
     }
     const float lam = f.lambda, gs = f.g_scale;
     const bool rational = f.edge_stop == PP_EDGE_RATIONAL;
+    auto flux = [&](float D) {
+        const float a = D * D * gs;
+        return (rational ? 1.0f / (1.0f + a) : g_exp(a)) * D;
+    };
+    int cur = 0;
     for (int k = 1; k <= it; ++k) {
         const int s = T - it + k;  // pixels updated this iteration: [s, EW - s) x [s, EH - s)
-        // fluxes of the edges those pixels touch
+        const float* __restrict__ sd = s_d[cur];
+        float* __restrict__ nd = s_d[cur ^ 1];
 #pragma unroll
         for (int q = 0; q < NPT; ++q) {
             const int e = threadIdx.x + q * kBlock;
             const int ex = exy[q] >> 16, ey = exy[q] & 0xFFFF;
-            if (e >= EN || ex < s - 1 || ex >= EW - s || ey < s - 1 || ey >= EH - s) continue;
-            const float dp = s_d[e];
-            if (ve[q] && ey >= s) {
-                const float D = dIe[q] + (s_d[e + 1] - dp);
-                const float a = D * D * gs;
-                s_fe[e] = (rational ? 1.0f / (1.0f + a) : g_exp(a)) * D;
-            }
-            if (vs[q] && ex >= s) {
-                const float D = dIs[q] + (s_d[e + EW] - dp);
-                const float a = D * D * gs;
-                s_fs[e] = (rational ? 1.0f / (1.0f + a) : g_exp(a)) * D;
-            }
+            if (!(open[q] & 1u) || ex < s || ex >= EW - s || ey < s || ey >= EH - s) continue;
+            const uint32_t o = open[q];
+            const float dp = sd[e];
+            // each edge's flux g(D) D with D = I_q - I_p taken in the same operand order by
+            // both of its pixels (delta form: the integer part is exact), so it leaves one
+            // pixel exactly as it enters the other; closed edges (holes, border) carry none
+            const float fe = (o & 2u) ? flux(dIe[q] + (sd[e + 1] - dp)) : 0.f;
+            const float fs = (o & 4u) ? flux(dIs[q] + (sd[e + EW] - dp)) : 0.f;
+            const float fw = (o & 8u) ? flux((i0p[q] - s_i0[e - 1]) + (dp - sd[e - 1])) : 0.f;
+            const float fn = (o & 16u) ? flux((i0p[q] - s_i0[e - EW]) + (dp - sd[e - EW])) : 0.f;
+            nd[e] = dp + lam * ((fe - fw) + (fs - fn));
         }
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NPT; ++q) {
-            const int e = threadIdx.x + q * kBlock;
-            const int ex = exy[q] >> 16, ey = exy[q] & 0xFFFF;
-            if (e >= EN || !vp[q] || ex < s || ex >= EW - s || ey < s || ey >= EH - s) continue;
-            // fluxes into holes or across the border are zero: their slots were never written
-            const float fe = ve[q] ? s_fe[e] : 0.f;
-            const float fw = s_i0[e - 1] > 0.f ? s_fe[e - 1] : 0.f;
-            const float fs = vs[q] ? s_fs[e] : 0.f;
-            const float fn = s_i0[e - EW] > 0.f ? s_fs[e - EW] : 0.f;
-            s_d[e] = s_d[e] + lam * ((fe - fw) + (fs - fn));
-        }
-        __syncthreads();
+        cur ^= 1;
     }
     float* __restrict__ dout = f.delta[dst];
     for (int e = threadIdx.x; e < TX * TY; e += kBlock) {
@@ -131,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__
         if (x >= W || y >= H) continue;
         const int ee = (ty + T) * EW + (tx + T);
         const float i0 = s_i0[ee];
-        const float d = i0 > 0.f ? s_d[ee] : 0.f;
+        const float d = i0 > 0.f ? s_d[cur][ee] : 0.f;
         if (last)
             f.dmm[(size_t)y * f.pitch + x] = i0 > 0.f ? i0 + d : 0.f;
         else
