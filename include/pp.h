@@ -354,8 +354,10 @@ pp_status pp_batch_run_eager(pp_ctx* ctx, int32_t n_frames, const pp_frame_job* 
 
 /* ---------------------------------------------------------------- tuning */
 /* Launch-shape knobs the autotuner searches (0 = library default).
- * diffuse_tile: index of the diffusion tile shape, diffuse_t: iterations
- * fused per pass (temporal blocking depth), score_hb: the FP32 scorer's
+ * diffuse_tile: the diffusion kernel's tile shape (1-4: LDS tiles of 64x16,
+ * 128x16, 64x32 and 128x32 pixels; 5, 6: register-resident columns, one
+ * wave per 64 - 2T columns and 8 or 16 rows), diffuse_t: iterations fused
+ * per pass (temporal blocking depth), score_hb: the FP32 scorer's
  * hypotheses per block (1: 8, 2: 16, 3: 32 on the vector ALUs; 4: 64 with
  * tile culling, each 64-point tile's bounding box first decides for every
  * hypothesis whether all, none or only some of its points can be inliers),

@@ -15,7 +15,7 @@ import json
 import os
 from typing import Dict, Optional, Sequence
 
-TILES = (1, 2, 3, 4)                 # 64x16, 128x16, 64x32, 128x32 (pp_tuning.diffuse_tile)
+TILES = (1, 2, 3, 4, 5, 6)           # LDS 64x16, 128x16, 64x32, 128x32; register columns of 8, 16 rows
 DEPTHS = (1, 2, 3, 4, 5, 8, 10)      # iterations per diffusion pass
 HB = (1, 2, 3, 4)                    # 8, 16, 32 hypotheses per VALU scoring block; 64 with tile culling
 CHUNKS = (1, 2, 3, 4)                # 1024 ... 8192 points per scoring block

@@ -34,8 +34,8 @@ struct GraphEntry {
 
 }  // namespace
 
-// 64x16 diffusion tiles, 3 iterations a pass, the culled scorer, 2048 points a scoring block
-constexpr ppk::Tuning kDefaultTuning{0, 3, 3, 1};
+// register-resident diffusion (16 rows a wave), 4 iterations a pass, the culled scorer, 2048 points a scoring block
+constexpr ppk::Tuning kDefaultTuning{5, 4, 3, 1};
 
 struct pp_ctx {
     int device = 0;

@@ -76,18 +76,16 @@ struct FrameDev {
 };
 
 struct Tuning {
-    int diffuse_tile;  // index into the tile table
+    int diffuse_tile;  // LDS tiles 64x16, 128x16, 64x32, 128x32; register-resident waves of TY = 8, 16 rows
     int diffuse_t;     // iterations per pass
     int score_hb;      // index into {8, 16, 32, 64 with tile culling}
     int score_chunk;   // index into {1024, 2048, 4096, 8192}
 };
 
-constexpr int kNumTiles = 4;
+constexpr int kNumTiles = 6;
 constexpr int kMaxT = 10;
 constexpr int kNumHB = 4;
 constexpr int kNumChunk = 4;
-int tile_w(int tile);
-int tile_h(int tile);
 int hb_value(int idx);
 int chunk_value(int idx);
 bool t_supported(int t);

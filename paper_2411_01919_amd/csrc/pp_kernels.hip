@@ -134,6 +134,122 @@ __global__ __launch_bounds__(kBlock) void k_diffuse(const FrameDev* __restrict__
     }
 }
 
+// Lane l receives lane l - 1's value (DPP wave_shr:1); lane 0 receives 0.
+__device__ __forceinline__ float from_west_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+// Lane l receives lane l + 1's value (DPP wave_shl:1); lane 63 receives 0.
+__device__ __forceinline__ float from_east_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+
+// The same iteration as k_diffuse with the iterate held in registers: lane l
+// of a wave owns image column x0 - T + l and the R = TY + 2T rows around the
+// wave's TY output rows.  A pixel's east neighbour is the next lane (a DPP
+// shift), its south neighbour the next register, so each edge's flux g(D) D is
+// computed once per iteration, by the pixel west (north) of it, and reaches
+// the other pixel by a lane shift (the previous row's value); no LDS and no
+// barriers.  After k iterations lanes [k, 63 - k] and rows [k, R - 1 - k] hold
+// exact values, so a wave writes its 64 - 2T middle columns.  Every flux is
+// the expression k_diffuse evaluates for that edge, so the results are
+// bitwise the same.
+template <int TY, int T, bool RATIONAL>
+__device__ __forceinline__ void diffuse_wc_body(const FrameDev& f, int it, int first, int last, int src, int dst) {
+    constexpr int R = TY + 2 * T;
+    constexpr int OW = 64 - 2 * T;  // output columns per wave
+    const int W = f.W, H = f.H;
+    const int lane = threadIdx.x & 63;
+    const int ox0 = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * OW;
+    const int y0 = blockIdx.y * TY;
+    if (ox0 >= W || y0 >= H) return;  // whole waves only: nothing below synchronises across waves
+    const int x = ox0 - T + lane;
+    const bool xin = x >= 0 && x < W;
+    const int xc = min(max(x, 0), W - 1);
+    typedef const __attribute__((address_space(1))) uint16_t* gu16_ptr;
+    typedef const __attribute__((address_space(1))) float* gf32_ptr;
+    const gu16_ptr dep = (gu16_ptr)f.depth;
+    const gf32_ptr din = (gf32_ptr)f.delta[src];
+    float d[R], dIe[R], dIs[R], ce[R], cs[R];
+    {
+        // every row's loads issued at once: addresses clamped into the frame, values masked after
+        float i0[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = y0 - T + r;
+            const int yc = min(max(y, 0), H - 1);
+            const float v = (float)dep[(size_t)yc * f.pitch + xc];
+            i0[r] = (xin && y >= 0 && y < H) ? v : 0.f;
+        }
+        if (first) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) d[r] = 0.f;
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int yc = min(max(y0 - T + r, 0), H - 1);
+                const float v = din[(size_t)yc * W + xc];
+                d[r] = i0[r] > 0.f ? v : 0.f;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float ie = from_east_lane(i0[r]);  // 0 beyond the wave: a closed edge in the halo
+            dIe[r] = ie - i0[r];
+            ce[r] = (i0[r] > 0.f && ie > 0.f) ? 1.f : 0.f;
+            if (r + 1 < R) {
+                dIs[r] = i0[r + 1] - i0[r];
+                cs[r] = (i0[r] > 0.f && i0[r + 1] > 0.f) ? 1.f : 0.f;
+            } else {
+                dIs[r] = 0.f;
+                cs[r] = 0.f;
+            }
+        }
+    }
+    const float lam = f.lambda, gs = f.g_scale;
+    auto flux = [&](float D) {
+        const float a = D * D * gs;
+        return (RATIONAL ? 1.0f / (1.0f + a) : g_exp(a)) * D;
+    };
+#pragma unroll
+    for (int k = 1; k <= T; ++k) {
+        if (k <= T - it) continue;  // a short pass runs its `it` iterations as the last ones of T
+        // rows [k, R - 1 - k]; the south flux of row k - 1 is the first north flux
+        float fn = flux(dIs[k - 1] + (d[k] - d[k - 1])) * cs[k - 1];
+#pragma unroll
+        for (int r = k; r <= R - 1 - k; ++r) {
+            const float dp = d[r];
+            const float fe = flux(dIe[r] + (from_east_lane(dp) - dp)) * ce[r];
+            const float fs = flux(dIs[r] + (d[r + 1] - dp)) * cs[r];
+            const float fw = from_west_lane(fe);
+            d[r] = dp + lam * ((fe - fw) + (fs - fn));
+            fn = fs;
+        }
+    }
+    if (lane < T || lane >= 64 - T || x >= W) return;
+    float* __restrict__ dout = f.delta[dst];
+#pragma unroll
+    for (int r = T; r < T + TY; ++r) {
+        const int y = y0 - T + r;
+        if (y >= H) break;
+        if (last) {
+            const float i0 = (float)f.depth[(size_t)y * f.pitch + x];
+            f.dmm[(size_t)y * f.pitch + x] = i0 > 0.f ? i0 + d[r] : 0.f;
+        } else {
+            dout[(size_t)y * W + x] = d[r];
+        }
+    }
+}
+
+template <int TY, int T>
+__global__ __launch_bounds__(kBlock) void k_diffuse_wc(const FrameDev* __restrict__ tab, int it, int first, int last,
+                                                        int src, int dst) {
+    const FrameDev& f = tab[blockIdx.z];
+    if (f.edge_stop == PP_EDGE_RATIONAL)
+        diffuse_wc_body<TY, T, true>(f, it, first, last, src, dst);
+    else
+        diffuse_wc_body<TY, T, false>(f, it, first, last, src, dst);
+}
+
 // Other discretisations of Eq. 1, on the same tiling, temporal blocking and
 // delta form as k_diffuse (fixed 64 x 16 tiles, up to kVarT iterations a pass):
 //  PP_DIFFUSE_PIXEL  Alg. 1 as printed.  Each pixel takes c_p = g(|grad I_p|),
@@ -1198,13 +1314,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
 }
 
 // ------------------------------------------------------------------ launchers
-static const int kTileW[kNumTiles] = {64, 128, 64, 128};
-static const int kTileH[kNumTiles] = {16, 16, 32, 32};
 static const int kHB[kNumHB] = {8, 16, 32, 64};  // 64: the culled scorer
 static const int kChunk[kNumChunk] = {1024, 2048, 4096, 8192};
 
-int tile_w(int t) { return kTileW[t]; }
-int tile_h(int t) { return kTileH[t]; }
 int hb_value(int i) { return kHB[i]; }
 int chunk_value(int i) { return kChunk[i]; }
 bool t_supported(int t) { return t == 1 || t == 2 || t == 3 || t == 4 || t == 5 || t == 8 || t == 10; }
@@ -1214,6 +1326,30 @@ static void diffuse_pass(const FrameDev* tab, int nf, int maxW, int maxH, int it
                          int dst, hipStream_t s) {
     dim3 grid((maxW + TX - 1) / TX, (maxH + TY - 1) / TY, nf);
     hipLaunchKernelGGL((k_diffuse<TX, TY, T>), grid, dim3(kBlock), 0, s, tab, it, first, last, src, dst);
+}
+
+// Register-resident form: 4 waves of 64 lanes side by side, each writing
+// 64 - 2T columns and TY rows.
+template <int TY, int T>
+static void diffuse_pass_wc(const FrameDev* tab, int nf, int maxW, int maxH, int it, int first, int last, int src,
+                            int dst, hipStream_t s) {
+    constexpr int OW = 64 - 2 * T;
+    dim3 grid((maxW + (kBlock / 64) * OW - 1) / ((kBlock / 64) * OW), (maxH + TY - 1) / TY, nf);
+    hipLaunchKernelGGL((k_diffuse_wc<TY, T>), grid, dim3(kBlock), 0, s, tab, it, first, last, src, dst);
+}
+
+template <int TY>
+static void diffuse_pass_wc_t(int T, const FrameDev* tab, int nf, int maxW, int maxH, int it, int first, int last,
+                              int src, int dst, hipStream_t s) {
+    switch (T) {
+        case 1: diffuse_pass_wc<TY, 1>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        case 2: diffuse_pass_wc<TY, 2>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        case 3: diffuse_pass_wc<TY, 3>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        case 4: diffuse_pass_wc<TY, 4>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        case 5: diffuse_pass_wc<TY, 5>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        case 8: diffuse_pass_wc<TY, 8>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+        default: diffuse_pass_wc<TY, 10>(tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+    }
 }
 
 template <int TX, int TY>
@@ -1264,7 +1400,9 @@ hipError_t launch_diffuse(const FrameDev* tab, int nf, int maxW, int maxH, int i
             case 0: diffuse_pass_t<64, 16>(T, tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
             case 1: diffuse_pass_t<128, 16>(T, tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
             case 2: diffuse_pass_t<64, 32>(T, tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
-            default: diffuse_pass_t<128, 32>(T, tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+            case 3: diffuse_pass_t<128, 32>(T, tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+            case 4: diffuse_pass_wc_t<8>(T, tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
+            default: diffuse_pass_wc_t<16>(T, tab, nf, maxW, maxH, it, first, last, src, dst, s); break;
         }
         done += it;
         src = dst;

@@ -56,7 +56,7 @@ def test_all_tunings_give_bitwise_identical_diffusion(pp):
     f = scenes.make_frame(2, 1)
     ctx = pp.Context(0)
     outs = []
-    for tile in (1, 2, 3, 4):
+    for tile in (1, 2, 3, 4, 5, 6):
         for T in (1, 3, 5, 10):
             ctx.set_tuning(diffuse_tile=tile, diffuse_t=T)
             outs.append(pp.diffuse(to_dev(f.depth), 20, ctx=ctx).cpu().numpy())
