@@ -11,7 +11,7 @@
  *   3. the normal image from Sobel gradients (Sec. III-C, Eq. 2, Alg. 1),
  *   4. RANSAC plane extraction: random 3-point hypotheses, inlier scoring with
  *      the point-to-plane distance (Eq. 3, Alg. 2), selection, a
- *      least-squares refit of the winning plane ("optimal plane model",
+ *      least-squares refit of the winning plane (the best plane model of
  *      Sec. III-A) and removal of its inliers, repeated for up to
  *      max_planes planes per frame.
  * Every stage runs as hand-written HIP kernels on the GPU.

@@ -255,7 +255,7 @@ int orc_valid_list(const uint8_t* valid, int npx, int32_t* L) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Alg. 2: "select random subset of 3 points", "fit plane model".            */
+/* Alg. 2: the random choice of 3 points and the plane through them.       */
 /* ------------------------------------------------------------------------ */
 static void point_at(const double* P, size_t n, int px, double out[3]) {
     out[0] = P[px];
@@ -434,7 +434,7 @@ void orc_eig3(const double A_in[9], double w[3], double V[9]) {
 
 /* Least-squares refit: the plane through the centroid whose normal is the
  * direction of least scatter minimises the sum of squared distances (the
- * "optimal plane model" of Sec. III-A, Eq. 3 with a squared distance). */
+ * best plane of Sec. III-A, Eq. 3 with a squared distance). */
 int orc_refit(const double* P, int W, int H, const int32_t* idx, int cnt, double plane[4], double centroid[3]) {
     size_t n = (size_t)W * H;
     plane[0] = plane[1] = plane[2] = plane[3] = 0.0;

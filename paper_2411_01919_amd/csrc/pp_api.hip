@@ -118,7 +118,7 @@ bool intrinsics_ok(const pp_intrinsics& K) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t delta, L, list, abm, hyp, triples, counts, partials, chunk_cnt, chunk_cnt_q, tbox, st, total;
+    size_t delta, L, list, taken, hyp, triples, counts, partials, chunk_cnt, chunk_cnt_q, tbox, st, total;
 };
 
 Layout slot_layout(size_t px, int hyps) {
@@ -129,7 +129,7 @@ Layout slot_layout(size_t px, int hyps) {
     l.delta = o; o += align256(2 * px * sizeof(float));
     l.L = o; o += align256(px * sizeof(int32_t));
     l.list = o; o += align256(2 * px * sizeof(float4));
-    l.abm = o; o += align256((px + 31) / 32 * sizeof(uint32_t));
+    l.taken = o; o += align256((px + 3) / 4 * 4);
     l.hyp = o; o += align256((size_t)hyps * sizeof(float4));
     l.triples = o; o += align256((size_t)hyps * 3 * sizeof(int32_t));
     l.counts = o; o += align256((size_t)hyps * sizeof(int32_t));
@@ -181,7 +181,7 @@ void bind_slot(const pp_ctx* c, int i, FrameDev& f) {
     f.L = reinterpret_cast<int32_t*>(b + l.L);
     f.list[0] = reinterpret_cast<float4*>(b + l.list);
     f.list[1] = f.list[0] + s.px_cap;
-    f.abm = reinterpret_cast<uint32_t*>(b + l.abm);
+    f.taken = reinterpret_cast<uint8_t*>(b + l.taken);
     f.hyp = reinterpret_cast<float4*>(b + l.hyp);
     f.triples = reinterpret_cast<int32_t*>(b + l.triples);
     f.counts = reinterpret_cast<int32_t*>(b + l.counts);

@@ -122,7 +122,7 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
     }
 }
 
-// FP32 plane through three points (Alg. 2 "fit plane model"): n = e1 x e2
+// FP32 plane through three points (the plane model of Alg. 2): n = e1 x e2
 // normalised, d = -n.p0, camera-facing (d >= 0); degenerate when
 // |e1 x e2| <= 1e-3 |e1||e2|, returned as d = NaN (never an inlier).
 __device__ __forceinline__ float4 plane_from_points(float3 p0, float3 p1, float3 p2) {

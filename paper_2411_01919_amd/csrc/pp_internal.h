@@ -61,7 +61,7 @@ struct FrameDev {
     float* delta[2];         // [H][W] diffusion ping-pong (delta = I - I0)
     int32_t* L;              // [W*H] valid list (pixel offsets y*pitch+x)
     float4* list[2];         // [W*H] remaining points (x, y, z, valid-list position bits)
-    uint32_t* abm;           // [ceil(W*H/32)] bit k set iff the point at valid-list position k is assigned
+    uint8_t* taken;          // [W*H rounded up to 4] 1 iff the point at valid-list position k is assigned
     float4* hyp;             // [hyps] (n, d); d = NaN when invalid
     int32_t* triples;        // [hyps][3]
     int32_t* counts;         // [hyps]

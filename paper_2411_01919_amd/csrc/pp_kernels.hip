@@ -485,8 +485,9 @@ __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restri
     const int npx = f.W * f.H;
     const int nch = (npx + kValidChunk - 1) / kValidChunk;
     if (blockIdx.x == 0 && threadIdx.x == 0) f.st->p1max_bits = 0u;
-    const int nwords = (npx + 31) >> 5;
-    for (int w = blockIdx.x * kBlock + threadIdx.x; w < nwords; w += gridDim.x * kBlock) f.abm[w] = 0u;
+    const int nwords = (npx + 3) >> 2;
+    uint32_t* __restrict__ tw = reinterpret_cast<uint32_t*>(f.taken);
+    for (int w = blockIdx.x * kBlock + threadIdx.x; w < nwords; w += gridDim.x * kBlock) tw[w] = 0u;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         int cnt = 0;
         for (int i = threadIdx.x; i < kValidChunk; i += kBlock) {
@@ -574,19 +575,21 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
 }
 
 // ------------------------------------------------------------------ hypotheses
-// Alg. 2 "select random subset of 3 points": word w of Philox block
+// The random choice of 3 points in Alg. 2: word w of Philox block
 // (j, r, b, 0) under key (seed, frame) picks list position floor(w * M0 / 2^64);
 // it is skipped if that pixel is already assigned or already chosen; 16
 // blocks at most.  The list L is fixed per frame, so the draws of round r do
 // not depend on how many points earlier rounds removed.
 // 16 lanes per hypothesis compute its 16 Philox blocks at once and look up
-// their 64 candidates in the assignment bitmap; one lane then walks them in
-// draw order, so the triple is exactly the sequential draw's (the serial
-// continuation below only runs if fewer lanes are configured).
+// their 64 candidates in the per-position assignment bytes; one lane then
+// walks them in draw order, so the triple is exactly the sequential draw's
+// (the serial continuation below only runs if fewer lanes are configured).
+// The bytes are set by plain stores when a round removes its inliers (a
+// bitmap would need atomic ORs, which contend on shared words).
 constexpr int kHypLanes = 16;
 constexpr int kHypPerBlock = kBlock / kHypLanes;
 
-__device__ __forceinline__ bool point_taken(const FrameDev& f, int k) { return (f.abm[k >> 5] >> (k & 31)) & 1u; }
+__device__ __forceinline__ bool point_taken(const FrameDev& f, int k) { return f.taken[k] != 0; }
 
 // Round 0's scoring list: the depth-valid points in 8x8-block scan order,
 // each tagged with its valid-list position (w), by ordered compaction over
@@ -618,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restr
 }
 
 __global__ __launch_bounds__(kBlock) void k_hypgen(const FrameDev* __restrict__ tab, int r) {
-    __shared__ int cand[kHypPerBlock][4 * kHypLanes];
+    __shared__ int cand[kHypPerBlock][4 * kHypLanes];  // list position, -1 if assigned
     const FrameDev& f = tab[blockIdx.z];
     const RoundState* st = f.st;
     if (!st->active[r]) return;
@@ -1287,7 +1290,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
                 const int pos = __float_as_int(p[s].w);
                 const int off = f.L[pos];
                 f.labels[off] = (int8_t)r;
-                atomicOr(&f.abm[pos >> 5], 1u << (pos & 31));
+                f.taken[pos] = 1;
                 if (f.dbg.masks) {
                     const int y = off / f.pitch, x = off - y * f.pitch;
                     f.dbg.masks[(size_t)r * f.W * f.H + (size_t)y * f.W + x] |= 2;
