@@ -813,16 +813,24 @@ __device__ __forceinline__ uint32_t cull_tile(const float4* box, const float4* h
     uint32_t cnt = in ? (uint32_t)__float_as_int(c.w) : 0u;
     unsigned long long S = __ballot(!in && !out);
     if (!S) return cnt;
-    const unsigned long long live = __ballot(tile * 64 + (int)(threadIdx.x & 63) < M);
-    const float3 p = ld_global_xyz(pts, min(tile * 64 + (int)(threadIdx.x & 63), M - 1));
+    // lanes past the end hold a NaN point, which no hypothesis takes as an inlier
+    const bool live = tile * 64 + (int)(threadIdx.x & 63) < M;
+    float3 p = ld_global_xyz(pts, min(tile * 64 + (int)(threadIdx.x & 63), M - 1));
+    const float qnan = __int_as_float(0x7fc00000);
+    if (!live) p = make_float3(qnan, qnan, qnan);
+    asm volatile("" : "+v"(p.x), "+v"(p.y), "+v"(p.z));  // keeps the select out of the loop below
     int tmp = 0;
-    while (S) {
-        const int k = __ffsll(S) - 1;
-        S &= S - 1;
-        const float4 h = hyp_lds[k];
-        const int m = __popcll(__ballot(fabsf(canon_res(h, p.x, p.y, p.z)) < t) & live);
-        tmp += (int)(threadIdx.x & 63) == k ? m : 0;
-    }
+    do {
+        const int k = __builtin_ctzll(S);
+        const unsigned long long onehot = 1ull << k;  // lane k's bit: clears S and selects the lane
+        S &= ~onehot;
+        // the LDS byte offset formed by one vector shift (a scalar shift and a copy otherwise)
+        int off;
+        asm("v_lshlrev_b32 %0, 4, %1" : "=v"(off) : "s"(k));
+        const float4 h = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(hyp_lds) + off);
+        const int m = __popcll(__ballot(fabsf(canon_res(h, p.x, p.y, p.z)) < t));
+        tmp += __builtin_amdgcn_inverse_ballot_w64(onehot) ? m : 0;
+    } while (S);
     return cnt + (uint32_t)tmp;
 }
 
