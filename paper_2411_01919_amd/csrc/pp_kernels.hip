@@ -729,56 +729,6 @@ __global__ __launch_bounds__(kBlock) void k_score(const FrameDev* __restrict__ t
 }
 
 // ------------------------------------------------------------------ culled scoring
-// Bounding boxes of the 64-point tiles of round r's list (one wave per tile):
-// centre c (w: the tile's point count as integer bits) and half extents e,
-// widened so that [c - e, c + e] holds every point of the tile.
-__global__ __launch_bounds__(kBlock) void k_tile_box(const FrameDev* __restrict__ tab, int r) {
-    const FrameDev& f = tab[blockIdx.z];
-    const RoundState* st = f.st;
-    if (!st->active[r]) return;
-    const int M = st->M[r];
-    const int ntiles = (M + 63) >> 6;
-    const int lane = threadIdx.x & 63;
-    const float4* __restrict__ pts = f.list[r & 1];
-    for (int tile = blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += gridDim.x * 4) {
-        const int i = tile * 64 + lane;
-        float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
-        if (i < M) {
-            const float4 p = pts[i];
-            lx = hx = p.x;
-            ly = hy = p.y;
-            lz = hz = p.z;
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            lx = fminf(lx, __shfl_xor(lx, o));
-            ly = fminf(ly, __shfl_xor(ly, o));
-            lz = fminf(lz, __shfl_xor(lz, o));
-            hx = fmaxf(hx, __shfl_xor(hx, o));
-            hy = fmaxf(hy, __shfl_xor(hy, o));
-            hz = fmaxf(hz, __shfl_xor(hz, o));
-        }
-        if (lane == 0) {
-            const float cx = 0.5f * (lx + hx), cy = 0.5f * (ly + hy), cz = 0.5f * (lz + hz);
-            // the rounded differences may fall short of the true ones by an ulp: widen by 2^-20
-            const float w = 1.0f + 9.5367432e-7f;
-            const float ex = fmaxf(hx - cx, cx - lx) * w, ey = fmaxf(hy - cy, cy - ly) * w, ez = fmaxf(hz - cz, cz - lz) * w;
-            const int n = min(64, M - tile * 64);
-            f.tbox[2 * tile] = make_float4(cx, cy, cz, __int_as_float(n));
-            f.tbox[2 * tile + 1] = make_float4(ex, ey, ez, 0.f);
-        }
-    }
-}
-
-// Inlier counts with tile culling.  A block holds 64 hypotheses, one per lane.
-// For each 64-point tile, every lane bounds its hypothesis' residual over the
-// tile's box: |n.c + d| -/+ (|nx| ex + |ny| ey + |nz| ez).  With a margin of
-// 16 u (P1 + |d|) (u = 2^-24, P1 = max |p|_1 of the frame), which exceeds
-// the FP32 rounding of the bound and of the canonical residual, a tile lies
-// wholly outside (no inliers) or wholly inside (all its points are inliers)
-// exactly as the canonical formula decides; only the hypotheses left
-// straddling are evaluated point by point (one point per lane), and their
-// counts are the canonical ones.
 // Loads through the global address space (global_load rather than the
 // generic flat path).  Only for data no kernel of the same launch writes.
 typedef float v4f_t __attribute__((ext_vector_type(4)));
@@ -797,6 +747,76 @@ __device__ __forceinline__ float3 ld_global_xyz(const float4* p, int i) {
     return make_float3(v.x, v.y, v.z);
 }
 
+// min / max over the wave with DPP lane permutes (no LDS): pairs, quads, rows
+// of 16 by rotation, then the row broadcasts; lane 63 ends with the result.
+template <bool MAX, int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_extreme(float a) {
+    const float b = __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(a), __float_as_int(a), CTRL, ROW_MASK, 0xF, false));
+    return MAX ? fmaxf(a, b) : fminf(a, b);
+}
+
+template <bool MAX>
+__device__ __forceinline__ float wave_extreme_to_lane63(float v) {
+    v = dpp_extreme<MAX, 0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v = dpp_extreme<MAX, 0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = dpp_extreme<MAX, 0x124, 0xF>(v);  // row_ror:4
+    v = dpp_extreme<MAX, 0x128, 0xF>(v);  // row_ror:8
+    v = dpp_extreme<MAX, 0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_extreme<MAX, 0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// Bounding boxes of the 64-point tiles of round r's list (a wave reduces
+// kBoxTilesPerWave tiles, one point per lane, their loads issued together):
+// centre c (w: the tile's point count as integer bits) and half extents e,
+// widened so that [c - e, c + e] holds every point of the tile.
+constexpr int kBoxTilesPerWave = 4;
+
+__global__ __launch_bounds__(kBlock) void k_tile_box(const FrameDev* __restrict__ tab, int r) {
+    const FrameDev& f = tab[blockIdx.z];
+    const RoundState* st = f.st;
+    if (!st->active[r]) return;
+    const int M = st->M[r];
+    const int ntiles = (M + 63) >> 6;
+    const int lane = threadIdx.x & 63;
+    const float4* __restrict__ pts = f.list[r & 1];
+    const int wave_stride = gridDim.x * (kBlock / 64) * kBoxTilesPerWave;
+    for (int t0 = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * kBoxTilesPerWave; t0 < ntiles; t0 += wave_stride) {
+        // all of this wave's tiles in flight at once; lanes past the end repeat the last point
+        float4 p[kBoxTilesPerWave];
+#pragma unroll
+        for (int q = 0; q < kBoxTilesPerWave; ++q) p[q] = ld_global4(pts, min((t0 + q) * 64 + lane, M - 1));
+#pragma unroll
+        for (int q = 0; q < kBoxTilesPerWave; ++q) {
+            const int tile = t0 + q;
+            if (tile >= ntiles) break;
+            const float lx = wave_extreme_to_lane63<false>(p[q].x), hx = wave_extreme_to_lane63<true>(p[q].x);
+            const float ly = wave_extreme_to_lane63<false>(p[q].y), hy = wave_extreme_to_lane63<true>(p[q].y);
+            const float lz = wave_extreme_to_lane63<false>(p[q].z), hz = wave_extreme_to_lane63<true>(p[q].z);
+            if (lane == 63) {
+                const float cx = 0.5f * (lx + hx), cy = 0.5f * (ly + hy), cz = 0.5f * (lz + hz);
+                // the rounded differences may fall short of the true ones by an ulp: widen by 2^-20
+                const float w = 1.0f + 9.5367432e-7f;
+                const float ex = fmaxf(hx - cx, cx - lx) * w, ey = fmaxf(hy - cy, cy - ly) * w,
+                            ez = fmaxf(hz - cz, cz - lz) * w;
+                const int n = min(64, M - tile * 64);
+                f.tbox[2 * tile] = make_float4(cx, cy, cz, __int_as_float(n));
+                f.tbox[2 * tile + 1] = make_float4(ex, ey, ez, 0.f);
+            }
+        }
+    }
+}
+
+// Inlier counts with tile culling.  A block holds 64 hypotheses, one per lane.
+// For each 64-point tile, every lane bounds its hypothesis' residual over the
+// tile's box: |n.c + d| -/+ (|nx| ex + |ny| ey + |nz| ez).  With a margin of
+// 16 u (P1 + |d|) (u = 2^-24, P1 = max |p|_1 of the frame), which exceeds
+// the FP32 rounding of the bound and of the canonical residual, a tile lies
+// wholly outside (no inliers) or wholly inside (all its points are inliers)
+// exactly as the canonical formula decides; only the hypotheses left
+// straddling are evaluated point by point (one point per lane), and their
+// counts are the canonical ones.
 // One tile of k_score_cull for this lane's hypothesis: the box test, then,
 // only if some hypothesis of the block straddles, the tile's points (one per
 // lane; the index is clamped and lanes past the end are masked out of every
@@ -1452,7 +1472,9 @@ static void score_launch(const FrameDev* tab, int nf, int r, int max_pts, int ma
 static void score_cull_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target,
                               hipStream_t s) {
     const int tiles = (max_pts + 63) / 64;
-    hipLaunchKernelGGL(k_tile_box, dim3(clampi((tiles + 3) / 4, 1, 65535), 1, nf), dim3(kBlock), 0, s, tab, r);
+    const int per_block = (kBlock / 64) * kBoxTilesPerWave;
+    hipLaunchKernelGGL(k_tile_box, dim3(clampi((tiles + per_block - 1) / per_block, 1, 65535), 1, nf), dim3(kBlock), 0,
+                       s, tab, r);
     const int groups = (max_hyps + 63) / 64;
     const int per_frame_cap = clampi(16384 / (nf > 0 ? nf : 1), 8, 4096);
     const int bx = clampi((max_pts + target - 1) / target, 1, clampi(per_frame_cap / groups, 1, 1024));
