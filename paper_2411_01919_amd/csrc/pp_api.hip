@@ -223,7 +223,7 @@ __global__ void k_set_frame(FrameDev* dst, FrameDev v) { *dst = v; }
 
 __global__ void k_force_active(FrameDev* tab) {
     RoundState* st = tab[0].st;
-    st->active[0] = st->M0 > 0 ? 1 : 0;
+    st->round[0].active = st->M0 > 0 ? 1 : 0;
 }
 
 pp_status put_plain(pp_ctx* c, const FrameDev& f, hipStream_t s) {

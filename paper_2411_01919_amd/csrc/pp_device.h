@@ -9,10 +9,23 @@
 
 namespace ppk {
 
+// v plus the value of the lane that DPP control CTRL selects (0 in rows that
+// ROW_MASK leaves out).
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ int dpp_add(int v) {
+    return v + __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// Sum over the wave, returned to every lane: quad permutes and row rotations
+// give each row's sum, the row broadcasts carry it into lane 63 (DPP, no LDS).
 __device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v = dpp_add<0xB1>(v);        // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E>(v);        // quad_perm [2,3,0,1]
+    v = dpp_add<0x124>(v);       // row_ror:4
+    v = dpp_add<0x128>(v);       // row_ror:8
+    v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 __device__ __forceinline__ double wave_sum_d(double v) {
@@ -38,6 +51,21 @@ __device__ __forceinline__ int block_sum(int v, int* sh) {
     if (l == 0) sh[w] = v;
     __syncthreads();
     return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Two block sums at once (sh holds 8 ints).
+__device__ __forceinline__ void block_sum2(int& a, int& b, int* sh) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) {
+        sh[w] = a;
+        sh[4 + w] = b;
+    }
+    __syncthreads();
+    a = sh[0] + sh[1] + sh[2] + sh[3];
+    b = sh[4] + sh[5] + sh[6] + sh[7];
 }
 
 __device__ __forceinline__ unsigned long long lanemask_lt() {

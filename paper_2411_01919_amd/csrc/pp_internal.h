@@ -2,6 +2,8 @@
 // (pp_api.hip) of libpp.so.  Not installed; the public interface is pp.h.
 #pragma once
 
+#include <cstddef>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -19,18 +21,25 @@ constexpr int kScanBlock = 8;     // the scoring list walks the image in 8x8-pix
 // Per-frame RANSAC state in device memory.  Fields indexed by the round r are
 // written only by an earlier kernel than the ones that read them, so no
 // kernel reads a field another block of the same launch may be writing.
+// One round's flags, read together by a single 16-byte scalar load.
+struct RoundRec {
+    int32_t active;  // round r runs iff active
+    int32_t M;       // |R_r|: unassigned points entering round r
+    int32_t stop;    // round r found no valid hypothesis
+    int32_t jstar;
+};
+
 struct RoundState {
     int32_t M0;                        // |L|: depth-valid pixels
-    int32_t active[kMaxRounds + 1];    // round r runs iff active[r]
-    int32_t M[kMaxRounds + 1];         // |R_r|: unassigned points entering round r
-    int32_t stop[kMaxRounds + 1];      // round r found no valid hypothesis
-    int32_t jstar[kMaxRounds + 1];
+    uint32_t p1max_bits;               // max |x|+|y|+|z| over the frame's points (float bits)
+    int32_t s_count;
+    int32_t pad;
+    RoundRec round[kMaxRounds + 1];
     double shift[3];                   // moment origin of the current round (a point of j*)
     double plane[4];                   // refit plane of the current round
     double centroid[3];
-    int32_t s_count;
-    uint32_t p1max_bits;               // max |x|+|y|+|z| over the frame's points (float bits)
 };
+static_assert(offsetof(RoundState, M0) == 0 && offsetof(RoundState, round) % 16 == 0, "RoundState layout");
 
 // Everything a kernel needs about one frame.  Kernels read a table of these
 // from device memory and take the frame index from blockIdx.z.

@@ -27,6 +27,15 @@ __device__ __forceinline__ float3 load_point(const FrameDev& f, int off) {
 
 __device__ __forceinline__ bool hyp_valid(const float4 h) { return h.w == h.w; }
 
+// Round r's flags by one scalar load.  No kernel writes the record it reads
+// this way (each round's record is written by the kernels before it).
+__device__ __forceinline__ RoundRec round_rec(const FrameDev& f, int r) {
+    typedef int v4i_t __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(4))) v4i_t* ci4_ptr;
+    const v4i_t v = ((ci4_ptr)(f.st->round + r))[0];
+    return RoundRec{v.x, v.y, v.z, v.w};
+}
+
 // exp(-(x/kappa)^2) as 2^-a with the hardware exponential (v_exp_f32, about
 // 1 ulp).  It skips the library's rescaling for subnormal results: those would
 // contribute less than 1e-30 mm to a flux.
@@ -565,9 +574,9 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
         if (c == nch - 1 && threadIdx.x == 0) {
             RoundState* st = f.st;
             st->M0 = run;
-            st->M[0] = run;
-            st->active[0] = (run >= 3 && f.max_planes >= 1) ? 1 : 0;
-            for (int r = 1; r <= kMaxRounds; ++r) st->active[r] = 0;
+            st->round[0].M = run;
+            st->round[0].active = (run >= 3 && f.max_planes >= 1) ? 1 : 0;
+            for (int r = 1; r <= kMaxRounds; ++r) st->round[r].active = 0;
             f.n_planes[0] = 0;
             if (f.dbg.n_valid) f.dbg.n_valid[0] = run;
         }
@@ -589,7 +598,18 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
 constexpr int kHypLanes = 16;
 constexpr int kHypPerBlock = kBlock / kHypLanes;
 
-__device__ __forceinline__ bool point_taken(const FrameDev& f, int k) { return f.taken[k] != 0; }
+// Read through the global address space: a generic (flat) load may alias LDS,
+// so the compiler would not issue the next one before the preceding LDS store.
+typedef const __attribute__((address_space(1))) uint8_t* gu8_cptr;
+typedef const __attribute__((address_space(1))) int32_t* gi32_cptr;
+typedef const __attribute__((address_space(1))) float* gf32_cptr;
+__device__ __forceinline__ bool point_taken(const FrameDev& f, int k) { return ((gu8_cptr)f.taken)[k] != 0; }
+__device__ __forceinline__ int list_pixel(const FrameDev& f, int k) { return ((gi32_cptr)f.L)[k]; }
+__device__ __forceinline__ float3 load_point_g(const FrameDev& f, int off) {
+    const size_t plane = (size_t)f.H * f.pitch;
+    const gf32_cptr p = (gf32_cptr)f.pts;
+    return make_float3(p[off], p[plane + off], p[2 * plane + off]);
+}
 
 // Round 0's scoring list: the depth-valid points in 8x8-block scan order,
 // each tagged with its valid-list position (w), by ordered compaction over
@@ -623,12 +643,12 @@ __global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restr
 __global__ __launch_bounds__(kBlock) void k_hypgen(const FrameDev* __restrict__ tab, int r) {
     __shared__ int cand[kHypPerBlock][4 * kHypLanes];  // list position, -1 if assigned
     const FrameDev& f = tab[blockIdx.z];
-    const RoundState* st = f.st;
-    if (!st->active[r]) return;
+    const RoundRec rr = round_rec(f, r);
+    const uint64_t M0 = (uint64_t)((const __attribute__((address_space(4))) int32_t*)f.st)[0];  // RoundState::M0
+    if (!rr.active) return;
     const int hl = threadIdx.x / kHypLanes, b = threadIdx.x % kHypLanes;
     const int j = blockIdx.x * kHypPerBlock + hl;
     if (blockIdx.x * kHypPerBlock >= f.hyps) return;
-    const uint64_t M0 = (uint64_t)st->M0;
     if (j < f.hyps) {
         uint64_t c[4] = {(uint64_t)j, (uint64_t)r, (uint64_t)b, 0ull};
         philox4x64_10(c, f.seed, f.frame_id);
@@ -657,7 +677,9 @@ __global__ __launch_bounds__(kBlock) void k_hypgen(const FrameDev* __restrict__ 
         }
     }
     float4 h = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
-    if (got == 3) h = plane_from_points(load_point(f, f.L[slot[0]]), load_point(f, f.L[slot[1]]), load_point(f, f.L[slot[2]]));
+    if (got == 3)
+        h = plane_from_points(load_point_g(f, list_pixel(f, slot[0])), load_point_g(f, list_pixel(f, slot[1])),
+                              load_point_g(f, list_pixel(f, slot[2])));
     f.hyp[j] = h;
     f.counts[j] = 0;
     f.triples[3 * j + 0] = got == 3 ? slot[0] : -1;
@@ -695,8 +717,9 @@ template <int HB>
 __global__ __launch_bounds__(kBlock) void k_score(const FrameDev* __restrict__ tab, int r) {
     const FrameDev& f = tab[blockIdx.z];
     const RoundState* st = f.st;
-    if (!st->active[r]) return;
-    const int M = st->M[r];
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active) return;
+    const int M = rr.M;
     const int h0 = blockIdx.y * HB;
     if (h0 >= f.hyps) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -776,8 +799,9 @@ constexpr int kBoxTilesPerWave = 4;
 __global__ __launch_bounds__(kBlock) void k_tile_box(const FrameDev* __restrict__ tab, int r) {
     const FrameDev& f = tab[blockIdx.z];
     const RoundState* st = f.st;
-    if (!st->active[r]) return;
-    const int M = st->M[r];
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active) return;
+    const int M = rr.M;
     const int ntiles = (M + 63) >> 6;
     const int lane = threadIdx.x & 63;
     const float4* __restrict__ pts = f.list[r & 1];
@@ -857,8 +881,9 @@ __device__ __forceinline__ uint32_t cull_tile(const float4* box, const float4* h
 __global__ __launch_bounds__(kBlock) void k_score_cull(const FrameDev* __restrict__ tab, int r) {
     const FrameDev& f = tab[blockIdx.z];
     const RoundState* st = f.st;
-    if (!st->active[r]) return;
-    const int M = __builtin_amdgcn_readfirstlane(st->M[r]);
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active) return;
+    const int M = rr.M;
     const int h0 = blockIdx.y * 64;
     const int hyps = __builtin_amdgcn_readfirstlane(f.hyps);
     if (h0 >= hyps) return;
@@ -915,8 +940,9 @@ template <int PREC, int G>  // G: hypothesis groups of 16 per wave
 __global__ __launch_bounds__(kBlock) void k_score_mfma(const FrameDev* __restrict__ tab, int r) {
     const FrameDev& f = tab[blockIdx.z];
     const RoundState* st = f.st;
-    if (!st->active[r]) return;
-    const int M = st->M[r];
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active) return;
+    const int M = rr.M;
     const int h0 = blockIdx.y * (16 * G);
     if (h0 >= f.hyps || M <= 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1083,8 +1109,9 @@ __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __rest
     __shared__ double shd[4][10];
     const FrameDev& f = tab[blockIdx.z];
     RoundState* st = f.st;
-    if (!st->active[r]) return;
-    const int M = st->M[r];
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active) return;
+    const int M = rr.M;
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
     if ((int)blockIdx.x >= nch) return;
     if (blockIdx.x == 0 && f.dbg.counts)
@@ -1092,7 +1119,7 @@ __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __rest
     const int js = select_jstar(f, shk);
     if (js < 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            st->stop[r] = 1;
+            st->round[r].stop = 1;
             if (f.dbg.round_info) {
                 int32_t* ri = f.dbg.round_info + 4 * r;
                 ri[0] = -1; ri[1] = 0; ri[2] = 0; ri[3] = 1;
@@ -1134,8 +1161,8 @@ __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __rest
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->stop[r] = 0;
-        st->jstar[r] = js;
+        st->round[r].stop = 0;
+        st->round[r].jstar = js;
         st->shift[0] = sx; st->shift[1] = sy; st->shift[2] = sz;
     }
 }
@@ -1228,8 +1255,9 @@ __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restri
     __shared__ double s_red[10 * kBlock];
     const FrameDev& f = tab[blockIdx.z];
     RoundState* st = f.st;
-    if (!st->active[r] || st->stop[r]) return;
-    const int M = st->M[r];
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active || rr.stop) return;
+    const int M = rr.M;
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
     if ((int)blockIdx.x >= nch) return;
     solve_refit(f, M, s_plane, s_cent, &s_n, s_red);
@@ -1260,16 +1288,23 @@ constexpr int kApplySteps = kRefitChunk / kBlock;
 // with r, write the plane record, and compact the survivors (in order) into
 // the next round's list; otherwise the frame stops without emitting.
 __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ tab, int r) {
-    __shared__ int sh[4];
+    __shared__ int sh[8];
     const FrameDev& f = tab[blockIdx.z];
     RoundState* st = f.st;
-    if (!st->active[r] || st->stop[r]) return;
-    const int M = st->M[r];
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active || rr.stop) return;
+    const int M = rr.M;
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
     if ((int)blockIdx.x >= nch) return;
-    int ftot = 0;
-    for (int c = threadIdx.x; c < nch; c += kBlock) ftot += f.chunk_cnt[c];
-    ftot = block_sum(ftot, sh);
+    // |F| and the inliers of the chunks before this block's first one, in one pass
+    const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt;
+    int ftot = 0, pre = 0;
+    for (int c = threadIdx.x; c < nch; c += kBlock) {
+        const int v = ccnt[c];
+        ftot += v;
+        pre += c < (int)blockIdx.x ? v : 0;
+    }
+    block_sum2(ftot, pre, sh);
     const bool emit = ftot >= f.min_inliers;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const int next = M - (emit ? ftot : 0);
@@ -1279,15 +1314,15 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
             pl.d = st->plane[3];
             for (int k = 0; k < 3; ++k) pl.centroid[k] = st->centroid[k];
             pl.inliers = ftot;
-            pl.hyp_index = st->jstar[r];
+            pl.hyp_index = rr.jstar;
             f.planes[r] = pl;
             f.n_planes[0] = r + 1;
         }
-        st->M[r + 1] = next;
-        st->active[r + 1] = (emit && next >= 3 && r + 1 < f.max_planes) ? 1 : 0;
+        st->round[r + 1].M = next;
+        st->round[r + 1].active = (emit && next >= 3 && r + 1 < f.max_planes) ? 1 : 0;
         if (f.dbg.round_info) {
             int32_t* ri = f.dbg.round_info + 4 * r;
-            ri[0] = st->jstar[r]; ri[1] = st->s_count; ri[2] = ftot; ri[3] = emit ? 0 : 2;
+            ri[0] = rr.jstar; ri[1] = st->s_count; ri[2] = ftot; ri[3] = emit ? 0 : 2;
         }
     }
     if (!emit) return;
@@ -1296,35 +1331,47 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
     const float t = f.thresh;
     const float4* __restrict__ pts = f.list[r & 1];
     float4* __restrict__ out = f.list[(r + 1) & 1];
+    const gi32_cptr Lg = (gi32_cptr)f.L;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        int before = 0;
-        for (int i = threadIdx.x; i < c; i += kBlock) before += kRefitChunk - f.chunk_cnt[i];
-        before = block_sum(before, sh);
+        if (c != (int)blockIdx.x) {  // later chunks of this block (frames of more than 1024 chunks)
+            pre = 0;
+            for (int i = threadIdx.x; i < c; i += kBlock) pre += ccnt[i];
+            pre = block_sum(pre, sh);
+        }
+        // survivors before chunk c: every chunk before it is full
+        const int before = c * kRefitChunk - pre;
         const int e = min(M, (c + 1) * kRefitChunk);
         // every point of this thread in flight at once: point c*chunk + s*256 + tid of step s
         float4 p[kApplySteps];
 #pragma unroll
         for (int s = 0; s < kApplySteps; ++s) {
             const int i = c * kRefitChunk + s * kBlock + threadIdx.x;
-            p[s] = pts[min(i, e - 1)];
+            p[s] = ld_global4(pts, min(i, e - 1));
         }
+        bool inF[kApplySteps];
+        int off[kApplySteps];
+#pragma unroll
+        for (int s = 0; s < kApplySteps; ++s) {
+            const int i = c * kRefitChunk + s * kBlock + threadIdx.x;
+            inF[s] = i < e && fabsf(refit_res(q, p[s].x, p[s].y, p[s].z)) < t;
+        }
+        // the pixels of the inliers, all looked up before any store
+#pragma unroll
+        for (int s = 0; s < kApplySteps; ++s) off[s] = Lg[inF[s] ? __float_as_int(p[s].w) : 0];
         unsigned long long keepm[kApplySteps];
 #pragma unroll
         for (int s = 0; s < kApplySteps; ++s) {
             const int i = c * kRefitChunk + s * kBlock + threadIdx.x;
-            const bool inF = i < e && fabsf(refit_res(q, p[s].x, p[s].y, p[s].z)) < t;
-            if (inF) {
-                const int pos = __float_as_int(p[s].w);
-                const int off = f.L[pos];
-                f.labels[off] = (int8_t)r;
-                f.taken[pos] = 1;
+            if (inF[s]) {
+                f.labels[off[s]] = (int8_t)r;
+                f.taken[__float_as_int(p[s].w)] = 1;
                 if (f.dbg.masks) {
-                    const int y = off / f.pitch, x = off - y * f.pitch;
+                    const int y = off[s] / f.pitch, x = off[s] - y * f.pitch;
                     f.dbg.masks[(size_t)r * f.W * f.H + (size_t)y * f.W + x] |= 2;
                 }
             }
-            keepm[s] = __ballot(i < e && !inF);
+            keepm[s] = __ballot(i < e && !inF[s]);
             if (lane == 0) s_cnt[s][wave] = __popcll(keepm[s]);
         }
         __syncthreads();
