@@ -118,7 +118,7 @@ bool intrinsics_ok(const pp_intrinsics& K) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t delta, L, list, taken, hyp, triples, counts, partials, chunk_cnt, chunk_cnt_q, tbox, st, total;
+    size_t delta, L, list, taken, hyp, hyp_p0, triples, counts, partials, chunk_cnt, chunk_cnt_q, tbox, st, total;
 };
 
 Layout slot_layout(size_t px, int hyps) {
@@ -131,6 +131,7 @@ Layout slot_layout(size_t px, int hyps) {
     l.list = o; o += align256(2 * px * sizeof(float4));
     l.taken = o; o += align256((px + 3) / 4 * 4);
     l.hyp = o; o += align256((size_t)hyps * sizeof(float4));
+    l.hyp_p0 = o; o += align256((size_t)hyps * sizeof(float4));
     l.triples = o; o += align256((size_t)hyps * 3 * sizeof(int32_t));
     l.counts = o; o += align256((size_t)hyps * sizeof(int32_t));
     l.partials = o; o += align256(nch_refit * 10 * sizeof(double));
@@ -183,6 +184,7 @@ void bind_slot(const pp_ctx* c, int i, FrameDev& f) {
     f.list[1] = f.list[0] + s.px_cap;
     f.taken = reinterpret_cast<uint8_t*>(b + l.taken);
     f.hyp = reinterpret_cast<float4*>(b + l.hyp);
+    f.hyp_p0 = reinterpret_cast<float4*>(b + l.hyp_p0);
     f.triples = reinterpret_cast<int32_t*>(b + l.triples);
     f.counts = reinterpret_cast<int32_t*>(b + l.counts);
     f.partials = reinterpret_cast<double*>(b + l.partials);

@@ -43,6 +43,24 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
+// Max (or min) over the wave, returned to every lane, by the same DPP steps.
+template <bool MAX, int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ int dpp_ext(int v) {
+    const int b = __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xF, false);
+    return MAX ? max(v, b) : min(v, b);
+}
+
+template <bool MAX>
+__device__ __forceinline__ int wave_ext(int v) {
+    v = dpp_ext<MAX, 0xB1>(v);
+    v = dpp_ext<MAX, 0x4E>(v);
+    v = dpp_ext<MAX, 0x124>(v);
+    v = dpp_ext<MAX, 0x128>(v);
+    v = dpp_ext<MAX, 0x142, 0xA>(v);
+    v = dpp_ext<MAX, 0x143, 0xC>(v);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // Sum over the 256 threads of a block; every thread gets the total.
 __device__ __forceinline__ int block_sum(int v, int* sh) {
     v = wave_sum(v);

@@ -72,6 +72,7 @@ struct FrameDev {
     float4* list[2];         // [W*H] remaining points (x, y, z, valid-list position bits)
     uint8_t* taken;          // [W*H rounded up to 4] 1 iff the point at valid-list position k is assigned
     float4* hyp;             // [hyps] (n, d); d = NaN when invalid
+    float4* hyp_p0;          // [hyps] the first point of each hypothesis' triple (the refit's moment origin)
     int32_t* triples;        // [hyps][3]
     int32_t* counts;         // [hyps]
     double* partials;        // [refit chunks][10]

@@ -677,10 +677,13 @@ __global__ __launch_bounds__(kBlock) void k_hypgen(const FrameDev* __restrict__ 
         }
     }
     float4 h = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
-    if (got == 3)
-        h = plane_from_points(load_point_g(f, list_pixel(f, slot[0])), load_point_g(f, list_pixel(f, slot[1])),
-                              load_point_g(f, list_pixel(f, slot[2])));
+    float3 p0 = make_float3(0.f, 0.f, 0.f);
+    if (got == 3) {
+        p0 = load_point_g(f, list_pixel(f, slot[0]));
+        h = plane_from_points(p0, load_point_g(f, list_pixel(f, slot[1])), load_point_g(f, list_pixel(f, slot[2])));
+    }
     f.hyp[j] = h;
+    f.hyp_p0[j] = make_float4(p0.x, p0.y, p0.z, 0.f);
     f.counts[j] = 0;
     f.triples[3 * j + 0] = got == 3 ? slot[0] : -1;
     f.triples[3 * j + 1] = got == 3 ? slot[1] : -1;
@@ -700,8 +703,9 @@ __global__ __launch_bounds__(kBlock) void k_hyp_from_triples(const FrameDev* __r
     const FrameDev& f = tab[0];
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
-    const float4 h = plane_from_points(load_point(f, tri[3 * j]), load_point(f, tri[3 * j + 1]), load_point(f, tri[3 * j + 2]));
-    f.hyp[j] = h;
+    // scoring only: hyp and counts are the caller's n-entry buffers here, and no
+    // refit follows, so the slot's per-hypothesis arrays (sized for one) stay untouched
+    f.hyp[j] = plane_from_points(load_point(f, tri[3 * j]), load_point(f, tri[3 * j + 1]), load_point(f, tri[3 * j + 2]));
     f.counts[j] = 0;
 }
 
@@ -1087,25 +1091,54 @@ __global__ __launch_bounds__(kBlock) void k_score_mfma(const FrameDev* __restric
 // index) is recomputed by every block from the counts; then the FP64 moments
 // (n, sum q, sum q q^T with q = p - p0 of j*) of j*'s inliers are summed per
 // fixed chunk of the point list, in a fixed order.
-__device__ __forceinline__ int select_jstar(const FrameDev& f, unsigned long long* sh) {
-    unsigned long long best = 0ull;
-    for (int j = threadIdx.x; j < f.hyps; j += kBlock) {
-        if (!hyp_valid(f.hyp[j])) continue;
-        const unsigned long long key = ((unsigned long long)(uint32_t)f.counts[j] << 32) | (0xFFFFFFFFull - (uint32_t)j);
-        best = key > best ? key : best;
+constexpr int kChunkSteps = kRefitChunk / kBlock;  // points per thread of a refit / removal chunk
+
+// j* = the valid hypothesis with the most inliers, the lowest index among
+// equal counts; -1 if no hypothesis is valid.  Every block computes it.
+constexpr int kSelPerThread = 4;
+__device__ __forceinline__ int select_jstar(const FrameDev& f, int* sh) {
+    const int H = f.hyps;
+    const gf32_cptr hw = (gf32_cptr)f.hyp;  // d of hypothesis j at 4 j + 3 (NaN: invalid)
+    const gi32_cptr cn = (gi32_cptr)f.counts;
+    int bc = -1, bj = 0x7FFFFFFF;
+    for (int j0 = threadIdx.x; j0 < H; j0 += kBlock * kSelPerThread) {
+        float d[kSelPerThread];
+        int cnt[kSelPerThread];
+#pragma unroll
+        for (int q = 0; q < kSelPerThread; ++q) {
+            const int jj = min(j0 + q * kBlock, H - 1);
+            d[q] = hw[4 * jj + 3];
+            cnt[q] = cn[jj];
+        }
+#pragma unroll
+        for (int q = 0; q < kSelPerThread; ++q) {
+            const int j = j0 + q * kBlock;
+            if (j < H && d[q] == d[q] && (cnt[q] > bc || (cnt[q] == bc && j < bj))) {
+                bc = cnt[q];
+                bj = j;
+            }
+        }
     }
-    best = wave_max_u64(best);
+    const int wc = wave_ext<true>(bc);
+    const int wj = wave_ext<false>(bc == wc ? bj : 0x7FFFFFFF);
+    const int w = threadIdx.x >> 6;
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = best;
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = wc;
+        sh[4 + w] = wj;
+    }
     __syncthreads();
-    best = sh[0];
-    for (int i = 1; i < 4; ++i) best = sh[i] > best ? sh[i] : best;
-    if (best == 0ull) return -1;
-    return (int)(0xFFFFFFFFull - (best & 0xFFFFFFFFull));
+    int best = sh[0], js = sh[4];
+    for (int i = 1; i < 4; ++i)
+        if (sh[i] > best || (sh[i] == best && sh[4 + i] < js)) {
+            best = sh[i];
+            js = sh[4 + i];
+        }
+    return best < 0 ? -1 : js;
 }
 
 __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __restrict__ tab, int r) {
-    __shared__ unsigned long long shk[4];
+    __shared__ int shk[8];
     __shared__ double shd[4][10];
     const FrameDev& f = tab[blockIdx.z];
     RoundState* st = f.st;
@@ -1127,17 +1160,22 @@ __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __rest
         }
         return;
     }
-    const float4 h = f.hyp[js];
-    const float3 p0 = load_point(f, f.L[f.triples[3 * js]]);
+    const float4 h = ld_global4(f.hyp, js);
+    const float4 p0 = ld_global4(f.hyp_p0, js);  // the first point of j*'s triple
     const double sx = p0.x, sy = p0.y, sz = p0.z;
     const float t = f.thresh;
     const float4* __restrict__ pts = f.list[r & 1];
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         const int e = min(M, (c + 1) * kRefitChunk);
-        for (int i = c * kRefitChunk + threadIdx.x; i < e; i += kBlock) {
-            const float4 p = pts[i];
-            if (!(fabsf(canon_res(h, p.x, p.y, p.z)) < t)) continue;
+        // every point of this thread in flight at once, then accumulated in index order
+        float4 pp[kChunkSteps];
+#pragma unroll
+        for (int s = 0; s < kChunkSteps; ++s) pp[s] = ld_global4(pts, min(c * kRefitChunk + s * kBlock + (int)threadIdx.x, e - 1));
+#pragma unroll
+        for (int s = 0; s < kChunkSteps; ++s) {
+            const float4 p = pp[s];
+            if (!(c * kRefitChunk + s * kBlock + (int)threadIdx.x < e && fabsf(canon_res(h, p.x, p.y, p.z)) < t)) continue;
             const double qx = (double)p.x - sx, qy = (double)p.y - sy, qz = (double)p.z - sz;
             m[0] += 1.0;
             m[1] += qx; m[2] += qy; m[3] += qz;
@@ -1268,10 +1306,12 @@ __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restri
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         int cnt = 0;
         const int e = min(M, (c + 1) * kRefitChunk);
-        for (int i = c * kRefitChunk + threadIdx.x; i < e; i += kBlock) {
-            const float4 p = pts[i];
-            cnt += fabsf(refit_res(q, p.x, p.y, p.z)) < t ? 1 : 0;
-        }
+        float4 pp[kChunkSteps];
+#pragma unroll
+        for (int s = 0; s < kChunkSteps; ++s) pp[s] = ld_global4(pts, min(c * kRefitChunk + s * kBlock + (int)threadIdx.x, e - 1));
+#pragma unroll
+        for (int s = 0; s < kChunkSteps; ++s)
+            cnt += (c * kRefitChunk + s * kBlock + (int)threadIdx.x < e && fabsf(refit_res(q, pp[s].x, pp[s].y, pp[s].z)) < t) ? 1 : 0;
         cnt = block_sum(cnt, sh);
         if (threadIdx.x == 0) f.chunk_cnt[c] = cnt;
     }
@@ -1282,7 +1322,6 @@ __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restri
     }
 }
 
-constexpr int kApplySteps = kRefitChunk / kBlock;
 
 // F = the refit plane's inliers among R_r.  If |F| >= min_inliers: label F
 // with r, write the plane record, and compact the survivors (in order) into
@@ -1326,7 +1365,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
         }
     }
     if (!emit) return;
-    __shared__ int s_cnt[kApplySteps][kBlock / 64];
+    __shared__ int s_cnt[kChunkSteps][kBlock / 64];
     const SplitPlane q = split_plane(st->plane);
     const float t = f.thresh;
     const float4* __restrict__ pts = f.list[r & 1];
@@ -1343,25 +1382,25 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
         const int before = c * kRefitChunk - pre;
         const int e = min(M, (c + 1) * kRefitChunk);
         // every point of this thread in flight at once: point c*chunk + s*256 + tid of step s
-        float4 p[kApplySteps];
+        float4 p[kChunkSteps];
 #pragma unroll
-        for (int s = 0; s < kApplySteps; ++s) {
+        for (int s = 0; s < kChunkSteps; ++s) {
             const int i = c * kRefitChunk + s * kBlock + threadIdx.x;
             p[s] = ld_global4(pts, min(i, e - 1));
         }
-        bool inF[kApplySteps];
-        int off[kApplySteps];
+        bool inF[kChunkSteps];
+        int off[kChunkSteps];
 #pragma unroll
-        for (int s = 0; s < kApplySteps; ++s) {
+        for (int s = 0; s < kChunkSteps; ++s) {
             const int i = c * kRefitChunk + s * kBlock + threadIdx.x;
             inF[s] = i < e && fabsf(refit_res(q, p[s].x, p[s].y, p[s].z)) < t;
         }
         // the pixels of the inliers, all looked up before any store
 #pragma unroll
-        for (int s = 0; s < kApplySteps; ++s) off[s] = Lg[inF[s] ? __float_as_int(p[s].w) : 0];
-        unsigned long long keepm[kApplySteps];
+        for (int s = 0; s < kChunkSteps; ++s) off[s] = Lg[inF[s] ? __float_as_int(p[s].w) : 0];
+        unsigned long long keepm[kChunkSteps];
 #pragma unroll
-        for (int s = 0; s < kApplySteps; ++s) {
+        for (int s = 0; s < kChunkSteps; ++s) {
             const int i = c * kRefitChunk + s * kBlock + threadIdx.x;
             if (inF[s]) {
                 f.labels[off[s]] = (int8_t)r;
@@ -1378,7 +1417,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
         // survivors keep their order: step-major, then wave, then lane
         int base = before;
 #pragma unroll
-        for (int s = 0; s < kApplySteps; ++s) {
+        for (int s = 0; s < kChunkSteps; ++s) {
             int mine = base;
             for (int w = 0; w < kBlock / 64; ++w) {
                 const int n = s_cnt[s][w];
