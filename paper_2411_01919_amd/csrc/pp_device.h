@@ -106,6 +106,33 @@ __device__ __forceinline__ int block_rank(bool flag, int* sh, int* total) {
     return before + in_wave;
 }
 
+// block_rank for S steps at once, ordered step-major (all of step 0, then
+// step 1, ...), each step by wave then lane; one barrier pair.  sh holds 4 S ints.
+template <int S>
+__device__ __forceinline__ void block_rank_steps(const bool (&flag)[S], int* sh, int (&rank)[S], int& total) {
+    const int w = threadIdx.x >> 6;
+    unsigned long long m[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) m[k] = __ballot(flag[k]);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < S; ++k) sh[4 * k + w] = __popcll(m[k]);
+    __syncthreads();
+    int base = 0;
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        int before = base;
+        for (int i = 0; i < 4; ++i) {
+            const int n = sh[4 * k + i];
+            before += i < w ? n : 0;
+            base += n;
+        }
+        rank[k] = before + __popcll(m[k] & lanemask_lt());
+    }
+    total = base;
+}
+
 // The canonical FP32 residual n.p + d of a hypothesis plane.  Every scorer
 // and the refit decide |r| < t with exactly this expression.
 __device__ __forceinline__ float canon_res(const float4 h, float x, float y, float z) {

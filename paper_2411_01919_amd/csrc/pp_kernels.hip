@@ -20,6 +20,12 @@
 
 namespace ppk {
 
+// Read-only pointers in the global address space: their loads need not wait
+// for earlier LDS or generic stores, which a generic (flat) load might alias.
+typedef const __attribute__((address_space(1))) uint8_t* gu8_cptr;
+typedef const __attribute__((address_space(1))) int32_t* gi32_cptr;
+typedef const __attribute__((address_space(1))) float* gf32_cptr;
+
 __device__ __forceinline__ float3 load_point(const FrameDev& f, int off) {
     const size_t plane = (size_t)f.H * f.pitch;
     return make_float3(f.pts[off], f.pts[plane + off], f.pts[2 * plane + off]);
@@ -406,7 +412,19 @@ __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__
     if (x >= W || y >= H) return;
     const size_t o = (size_t)y * pitch + x;
     const size_t plane = (size_t)H * pitch;
-    const float I = f.dmm[o];
+    // the 3x3 neighbourhood in one batch of loads (indices clamped into the frame;
+    // clamped values are used only where the pixel is not interior, i.e. never)
+    float nbv[3][3];
+    {
+        const gf32_cptr dm = (gf32_cptr)f.dmm;
+        const int xs[3] = {max(x - 1, 0), x, min(x + 1, W - 1)};
+        const int ys[3] = {max(y - 1, 0), y, min(y + 1, H - 1)};
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) nbv[j][i] = dm[(size_t)ys[j] * pitch + xs[i]];
+    }
+    const float I = nbv[1][1];
     const bool dv = I > 0.f;
     float px = 0.f, py = 0.f, pz = 0.f;
     if (dv) {
@@ -421,11 +439,6 @@ __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__
     bool nv = dv && x >= 1 && x <= W - 2 && y >= 1 && y <= H - 2;
     float n0 = 0.f, n1 = 0.f, n2 = 0.f;
     if (nv) {
-        float nbv[3][3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) nbv[j][i] = f.dmm[o + (size_t)(j - 1) * pitch + (i - 1)];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
@@ -497,15 +510,19 @@ __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restri
     const int nwords = (npx + 3) >> 2;
     uint32_t* __restrict__ tw = reinterpret_cast<uint32_t*>(f.taken);
     for (int w = blockIdx.x * kBlock + threadIdx.x; w < nwords; w += gridDim.x * kBlock) tw[w] = 0u;
+    constexpr int S = kValidChunk / kBlock;
+    const gu8_cptr vg = (gu8_cptr)f.valid;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        int cnt = 0;
-        for (int i = threadIdx.x; i < kValidChunk; i += kBlock) {
-            const int p = c * kValidChunk + i;
-            if (p < npx) {
-                const int y = p / f.W, x = p - y * f.W;
-                cnt += f.valid[(size_t)y * f.pitch + x] & 1;
-            }
+        uint8_t vb[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            const int p = min(c * kValidChunk + k * kBlock + (int)threadIdx.x, npx - 1);
+            const int y = p / f.W, x = p - y * f.W;
+            vb[k] = vg[(size_t)y * f.pitch + x];
         }
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < S; ++k) cnt += (c * kValidChunk + k * kBlock + (int)threadIdx.x < npx) ? (vb[k] & 1) : 0;
         cnt = block_sum(cnt, sh);
         if (threadIdx.x == 0) f.chunk_cnt[c] = cnt;
     }
@@ -513,18 +530,26 @@ __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restri
     const int nq = scan_positions(f);
     const int nchq = (nq + kValidChunk - 1) / kValidChunk;
     for (int c = blockIdx.x; c < nchq; c += gridDim.x) {
-        int cnt = 0;
-        for (int i = threadIdx.x; i < kValidChunk; i += kBlock) {
-            int x, y;
-            if (scan_pixel(f, c * kValidChunk + i, x, y)) cnt += f.valid[(size_t)y * f.pitch + x] & 1;
+        uint8_t vb[S];
+        bool in[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            int x = 0, y = 0;
+            in[k] = scan_pixel(f, c * kValidChunk + k * kBlock + threadIdx.x, x, y);
+            if (!in[k]) x = y = 0;
+            vb[k] = vg[(size_t)y * f.pitch + x];
         }
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < S; ++k) cnt += in[k] ? (vb[k] & 1) : 0;
         cnt = block_sum(cnt, sh);
         if (threadIdx.x == 0) f.chunk_cnt_q[c] = cnt;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __restrict__ tab) {
-    __shared__ int sh[4];
+    constexpr int S = kValidChunk / kBlock;  // steps of one chunk
+    __shared__ int sh[4 * S];
     __shared__ float shf[4];
     const FrameDev& f = tab[blockIdx.z];
     const int npx = f.W * f.H;
@@ -533,37 +558,52 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
     // valid-list position of every depth-valid pixel, [H][W]; the diffusion
     // ping-pong buffer is free by now
     int32_t* __restrict__ lpos = reinterpret_cast<int32_t*>(f.delta[0]);
+    const gu8_cptr vg = (gu8_cptr)f.valid;
+    const gf32_cptr pg = (gf32_cptr)f.pts;
+    const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         int before = 0;
-        for (int i = threadIdx.x; i < c; i += kBlock) before += f.chunk_cnt[i];
+        for (int i = threadIdx.x; i < c; i += kBlock) before += ccnt[i];
         before = block_sum(before, sh);
-        int run = before;
-        float p1 = 0.f;
-        for (int s = 0; s < kValidChunk; s += kBlock) {
-            const int p = c * kValidChunk + s + threadIdx.x;
-            bool v = false;
-            int off = 0;
-            if (p < npx) {
-                const int y = p / f.W, x = p - y * f.W;
-                off = y * f.pitch + x;
-                v = f.valid[off] & 1;
-                f.labels[off] = -1;
-            }
-            int tot;
-            const int rank = block_rank(v, sh, &tot);
-            if (v) {
-                const int k = run + rank;
-                f.L[k] = off;
-                lpos[p] = k;
-                if (f.dbg.valid_list) f.dbg.valid_list[k] = off;
-                p1 = fmaxf(p1, fabsf(f.pts[off]) + fabsf(f.pts[plane + off]) + fabsf(f.pts[2 * plane + off]));
-            }
-            run += tot;
-        }
-        // frame-wide bound on |p|_1 for the recheck bands of the matrix-core scorers
-        float pm = p1;
+        // all loads of the chunk's steps first (indices clamped into the frame)
+        int off[S];
+        bool in[S], v[S];
+        uint8_t vb[S];
+        float a1[S];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) pm = fmaxf(pm, __shfl_xor(pm, o));
+        for (int k = 0; k < S; ++k) {
+            const int p = c * kValidChunk + k * kBlock + threadIdx.x;
+            in[k] = p < npx;
+            const int pc = in[k] ? p : 0;
+            const int y = pc / f.W, x = pc - y * f.W;
+            off[k] = y * f.pitch + x;
+        }
+#pragma unroll
+        for (int k = 0; k < S; ++k) vb[k] = vg[off[k]];
+#pragma unroll
+        for (int k = 0; k < S; ++k)
+            a1[k] = fabsf(pg[off[k]]) + fabsf(pg[plane + off[k]]) + fabsf(pg[2 * plane + off[k]]);
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            v[k] = in[k] && (vb[k] & 1);
+            if (in[k]) f.labels[off[k]] = -1;
+        }
+        int rank[S], tot;
+        block_rank_steps<S>(v, sh, rank, tot);
+        float p1 = 0.f;
+#pragma unroll
+        for (int k = 0; k < S; ++k)
+            if (v[k]) {
+                const int kk = before + rank[k];
+                f.L[kk] = off[k];
+                lpos[c * kValidChunk + k * kBlock + threadIdx.x] = kk;
+                if (f.dbg.valid_list) f.dbg.valid_list[kk] = off[k];
+                p1 = fmaxf(p1, a1[k]);
+            }
+        const int run = before + tot;
+        // frame-wide bound on |p|_1 for the recheck bands of the matrix-core scorers
+        // (non-negative floats order as their bit patterns)
+        float pm = __int_as_float(wave_ext<true>(__float_as_int(p1)));
         __syncthreads();
         if ((threadIdx.x & 63) == 0) shf[threadIdx.x >> 6] = pm;
         __syncthreads();
@@ -600,9 +640,6 @@ constexpr int kHypPerBlock = kBlock / kHypLanes;
 
 // Read through the global address space: a generic (flat) load may alias LDS,
 // so the compiler would not issue the next one before the preceding LDS store.
-typedef const __attribute__((address_space(1))) uint8_t* gu8_cptr;
-typedef const __attribute__((address_space(1))) int32_t* gi32_cptr;
-typedef const __attribute__((address_space(1))) float* gf32_cptr;
 __device__ __forceinline__ bool point_taken(const FrameDev& f, int k) { return ((gu8_cptr)f.taken)[k] != 0; }
 __device__ __forceinline__ int list_pixel(const FrameDev& f, int k) { return ((gi32_cptr)f.L)[k]; }
 __device__ __forceinline__ float3 load_point_g(const FrameDev& f, int off) {
@@ -615,28 +652,47 @@ __device__ __forceinline__ float3 load_point_g(const FrameDev& f, int off) {
 // each tagged with its valid-list position (w), by ordered compaction over
 // chunks of 1024 scan positions.
 __global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restrict__ tab) {
-    __shared__ int sh[4];
+    constexpr int S = kValidChunk / kBlock;
+    __shared__ int sh[4 * S];
     const FrameDev& f = tab[blockIdx.z];
     const int nq = scan_positions(f);
     const int nchq = (nq + kValidChunk - 1) / kValidChunk;
     const size_t plane = (size_t)f.H * f.pitch;
-    const int32_t* __restrict__ lpos = reinterpret_cast<const int32_t*>(f.delta[0]);
+    const gi32_cptr lpos = (gi32_cptr)f.delta[0];
+    const gu8_cptr vg = (gu8_cptr)f.valid;
+    const gf32_cptr pg = (gf32_cptr)f.pts;
+    const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt_q;
     for (int c = blockIdx.x; c < nchq; c += gridDim.x) {
         int before = 0;
-        for (int i = threadIdx.x; i < c; i += kBlock) before += f.chunk_cnt_q[i];
-        int run = block_sum(before, sh);
-        for (int s = 0; s < kValidChunk; s += kBlock) {
+        for (int i = threadIdx.x; i < c; i += kBlock) before += ccnt[i];
+        const int run = block_sum(before, sh);
+        int off[S], lp[S];
+        bool v[S];
+        uint8_t vb[S];
+        float px[S], py[S], pz[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
             int x = 0, y = 0;
-            bool v = scan_pixel(f, c * kValidChunk + s + threadIdx.x, x, y);
-            const int off = y * f.pitch + x;
-            v = v && (f.valid[off] & 1);
-            int tot;
-            const int rank = block_rank(v, sh, &tot);
-            if (v)
-                f.list[0][run + rank] = make_float4(f.pts[off], f.pts[plane + off], f.pts[2 * plane + off],
-                                                    __int_as_float(lpos[y * f.W + x]));
-            run += tot;
+            v[k] = scan_pixel(f, c * kValidChunk + k * kBlock + threadIdx.x, x, y);
+            if (!v[k]) x = y = 0;
+            off[k] = y * f.pitch + x;
+            lp[k] = y * f.W + x;
         }
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            vb[k] = vg[off[k]];
+            px[k] = pg[off[k]];
+            py[k] = pg[plane + off[k]];
+            pz[k] = pg[2 * plane + off[k]];
+            lp[k] = lpos[lp[k]];
+        }
+#pragma unroll
+        for (int k = 0; k < S; ++k) v[k] = v[k] && (vb[k] & 1);
+        int rank[S], tot;
+        block_rank_steps<S>(v, sh, rank, tot);
+#pragma unroll
+        for (int k = 0; k < S; ++k)
+            if (v[k]) f.list[0][run + rank[k]] = make_float4(px[k], py[k], pz[k], __int_as_float(lp[k]));
     }
 }
 
