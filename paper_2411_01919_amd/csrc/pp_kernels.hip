@@ -696,15 +696,34 @@ __global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restr
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_hypgen(const FrameDev* __restrict__ tab, int r) {
+// Workgroups go to the 8 XCDs in turn (workgroup i to XCD i mod 8), each XCD
+// with its own L2.  This maps the 1-D grid of nf * bpf blocks (padded to a
+// multiple of 8) so that each XCD takes a contiguous range of (frame, block)
+// pairs, i.e. about nf / 8 whole frames, whose random lookups then share one
+// L2.  False for the padding blocks.
+constexpr int kXcds = 8;
+__device__ __forceinline__ bool xcd_frame_block(int bpf, int nf, int& frame, int& bx) {
+    const int T = bpf * nf;
+    const int per = (int)gridDim.x / kXcds;
+    const int L = blockIdx.x;
+    const int id = (L % kXcds) * per + L / kXcds;
+    if (id >= T) return false;
+    frame = id / bpf;
+    bx = id - frame * bpf;
+    return true;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hypgen(const FrameDev* __restrict__ tab, int r, int bpf, int nf) {
     __shared__ int cand[kHypPerBlock][4 * kHypLanes];  // list position, -1 if assigned
-    const FrameDev& f = tab[blockIdx.z];
+    int frame, bx;
+    if (!xcd_frame_block(bpf, nf, frame, bx)) return;
+    const FrameDev& f = tab[frame];
     const RoundRec rr = round_rec(f, r);
     const uint64_t M0 = (uint64_t)((const __attribute__((address_space(4))) int32_t*)f.st)[0];  // RoundState::M0
     if (!rr.active) return;
     const int hl = threadIdx.x / kHypLanes, b = threadIdx.x % kHypLanes;
-    const int j = blockIdx.x * kHypPerBlock + hl;
-    if (blockIdx.x * kHypPerBlock >= f.hyps) return;
+    const int j = bx * kHypPerBlock + hl;
+    if (bx * kHypPerBlock >= f.hyps) return;
     if (j < f.hyps) {
         uint64_t c[4] = {(uint64_t)j, (uint64_t)r, (uint64_t)b, 0ull};
         philox4x64_10(c, f.seed, f.frame_id);
@@ -1649,7 +1668,9 @@ static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int 
 
 hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_hyps, int precision,
                         const Tuning& tu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    hipLaunchKernelGGL(k_hypgen, dim3((max_hyps + kHypPerBlock - 1) / kHypPerBlock, 1, nf), dim3(kBlock), 0, s, tab, r);
+    const int bpf = (max_hyps + kHypPerBlock - 1) / kHypPerBlock;
+    const int hyp_blocks = (bpf * nf + kXcds - 1) / kXcds * kXcds;
+    hipLaunchKernelGGL(k_hypgen, dim3(hyp_blocks), dim3(kBlock), 0, s, tab, r, bpf, nf);
     if (ev0) (void)hipEventRecord(ev0, s);
     score_dispatch(tab, nf, r, max_px, max_hyps, precision, tu, s);
     if (ev1) (void)hipEventRecord(ev1, s);
