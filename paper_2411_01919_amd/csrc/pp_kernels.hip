@@ -942,19 +942,20 @@ __device__ __forceinline__ uint32_t cull_tile(const float4* box, const float4* h
     const float qnan = __int_as_float(0x7fc00000);
     if (!live) p = make_float3(qnan, qnan, qnan);
     asm volatile("" : "+v"(p.x), "+v"(p.y), "+v"(p.z));  // keeps the select out of the loop below
-    int tmp = 0;
+    // each straddling hypothesis occurs once per tile: its count is written
+    // straight into its lane of w (v_writelane, lane select in M0)
+    int w = 0;
     do {
         const int k = __builtin_ctzll(S);
-        const unsigned long long onehot = 1ull << k;  // lane k's bit: clears S and selects the lane
-        S &= ~onehot;
+        asm("s_bitset0_b64 %0, %1" : "+s"(S) : "s"(k));
         // the LDS byte offset formed by one vector shift (a scalar shift and a copy otherwise)
         int off;
         asm("v_lshlrev_b32 %0, 4, %1" : "=v"(off) : "s"(k));
         const float4 h = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(hyp_lds) + off);
         const int m = __popcll(__ballot(fabsf(canon_res(h, p.x, p.y, p.z)) < t));
-        tmp += __builtin_amdgcn_inverse_ballot_w64(onehot) ? m : 0;
+        asm("v_writelane_b32 %0, %2, %1" : "+v"(w) : "{m0}"(k), "s"(m));
     } while (S);
-    return cnt + (uint32_t)tmp;
+    return cnt + (uint32_t)w;
 }
 
 __global__ __launch_bounds__(kBlock) void k_score_cull(const FrameDev* __restrict__ tab, int r) {
