@@ -35,7 +35,6 @@ struct RoundState {
     int32_t s_count;
     int32_t pad;
     RoundRec round[kMaxRounds + 1];
-    double shift[3];                   // moment origin of the current round (a point of j*)
     double plane[4];                   // refit plane of the current round
     double centroid[3];
 };

@@ -1213,6 +1213,89 @@ __device__ __forceinline__ int select_jstar(const FrameDev& f, int* sh) {
     return best < 0 ? -1 : js;
 }
 
+
+// Symmetric 3x3 eigenproblem by cyclic Jacobi rotations in the tau form
+// (a'_rp = a_rp - s (a_rq + tau a_rp), tau = s / (1 + c)); columns of v are
+// the eigenvectors.
+__device__ void jacobi3(double a[3][3], double v[3][3]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) v[i][j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+        const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+        if (off == 0.0 || off <= 1e-40 * dia) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                const double apq = a[p][q];
+                if (apq == 0.0) continue;
+                const double theta = 0.5 * (a[q][q] - a[p][p]) / apq;
+                double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
+                if (theta < 0.0) t = -t;
+                const double c = 1.0 / sqrt(1.0 + t * t), s = t * c, tau = s / (1.0 + c);
+                a[p][p] -= t * apq;
+                a[q][q] += t * apq;
+                a[p][q] = a[q][p] = 0.0;
+                const int o = 3 - p - q;  // the remaining index
+                const double g = a[o][p], hh = a[o][q];
+                a[o][p] = a[p][o] = g - s * (hh + g * tau);
+                a[o][q] = a[q][o] = hh + s * (g - hh * tau);
+                for (int k = 0; k < 3; ++k) {
+                    const double vg = v[k][p], vh = v[k][q];
+                    v[k][p] = vg - s * (vh + vg * tau);
+                    v[k][q] = vh + s * (vg - vh * tau);
+                }
+            }
+    }
+}
+
+// Reduce the chunk moments in a fixed order (thread t sums chunks t, t+256,
+// ... in order, then a fixed tree over threads), so every block obtains the
+// same bits.  Then the least-squares plane: centroid c = shift + S/n,
+// scatter C = Q - S S^T / n, normal = eigenvector of the smallest eigenvalue,
+// d = -n.c, flipped so that d >= 0.  All threads call; thread 0 solves.
+__device__ void solve_refit(const FrameDev& f, int M, double sx, double sy, double sz, double* plane, double* centroid,
+                            double* nmom, double* sh) {
+    const int nch = (M + kRefitChunk - 1) / kRefitChunk;
+    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int c = threadIdx.x; c < nch; c += kBlock)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) m[k] += f.partials[(size_t)c * 10 + k];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) sh[k * kBlock + threadIdx.x] = m[k];
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 10; ++k) sh[k * kBlock + threadIdx.x] += sh[k * kBlock + threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) m[k] = sh[k * kBlock];
+    const double n = m[0];
+    const double mx = m[1] / n, my = m[2] / n, mz = m[3] / n;
+    double a[3][3];
+    a[0][0] = m[4] - m[1] * mx; a[0][1] = m[5] - m[1] * my; a[0][2] = m[6] - m[1] * mz;
+    a[1][1] = m[7] - m[2] * my; a[1][2] = m[8] - m[2] * mz; a[2][2] = m[9] - m[3] * mz;
+    a[1][0] = a[0][1]; a[2][0] = a[0][2]; a[2][1] = a[1][2];
+    double v[3][3];
+    jacobi3(a, v);
+    int kmin = 0;
+    if (a[1][1] < a[kmin][kmin]) kmin = 1;
+    if (a[2][2] < a[kmin][kmin]) kmin = 2;
+    double nx = v[0][kmin], ny = v[1][kmin], nz = v[2][kmin];
+    const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+    nx /= nn; ny /= nn; nz /= nn;
+    const double cx = sx + mx, cy = sy + my, cz = sz + mz;
+    double d = -(nx * cx + ny * cy + nz * cz);
+    if (d < 0.0) {
+        nx = -nx; ny = -ny; nz = -nz; d = -d;
+    }
+    plane[0] = nx; plane[1] = ny; plane[2] = nz; plane[3] = d;
+    centroid[0] = cx; centroid[1] = cy; centroid[2] = cz;
+    *nmom = n;
+}
+
 __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __restrict__ tab, int r) {
     __shared__ int shk[8];
     __shared__ double shd[4][10];
@@ -1277,106 +1360,37 @@ __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __rest
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->round[r].stop = 0;
         st->round[r].jstar = js;
-        st->shift[0] = sx; st->shift[1] = sy; st->shift[2] = sz;
     }
 }
 
-// Symmetric 3x3 eigenproblem by cyclic Jacobi rotations in the tau form
-// (a'_rp = a_rp - s (a_rq + tau a_rp), tau = s / (1 + c)); columns of v are
-// the eigenvectors.
-__device__ void jacobi3(double a[3][3], double v[3][3]) {
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) v[i][j] = i == j ? 1.0 : 0.0;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
-        const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
-        if (off == 0.0 || off <= 1e-40 * dia) break;
-        for (int p = 0; p < 2; ++p)
-            for (int q = p + 1; q < 3; ++q) {
-                const double apq = a[p][q];
-                if (apq == 0.0) continue;
-                const double theta = 0.5 * (a[q][q] - a[p][p]) / apq;
-                double t = 1.0 / (fabs(theta) + sqrt(1.0 + theta * theta));
-                if (theta < 0.0) t = -t;
-                const double c = 1.0 / sqrt(1.0 + t * t), s = t * c, tau = s / (1.0 + c);
-                a[p][p] -= t * apq;
-                a[q][q] += t * apq;
-                a[p][q] = a[q][p] = 0.0;
-                const int o = 3 - p - q;  // the remaining index
-                const double g = a[o][p], hh = a[o][q];
-                a[o][p] = a[p][o] = g - s * (hh + g * tau);
-                a[o][q] = a[q][o] = hh + s * (g - hh * tau);
-                for (int k = 0; k < 3; ++k) {
-                    const double vg = v[k][p], vh = v[k][q];
-                    v[k][p] = vg - s * (vh + vg * tau);
-                    v[k][q] = vh + s * (vg - vh * tau);
-                }
-            }
-    }
-}
-
-// Reduce the chunk moments in a fixed order (thread t sums chunks t, t+256,
-// ... in order, then a fixed tree over threads), so every block obtains the
-// same bits.  Then the least-squares plane: centroid c = shift + S/n,
-// scatter C = Q - S S^T / n, normal = eigenvector of the smallest eigenvalue,
-// d = -n.c, flipped so that d >= 0.  All threads call; thread 0 solves.
-__device__ void solve_refit(const FrameDev& f, int M, double* plane, double* centroid, double* nmom, double* sh) {
-    const int nch = (M + kRefitChunk - 1) / kRefitChunk;
-    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int c = threadIdx.x; c < nch; c += kBlock)
-#pragma unroll
-        for (int k = 0; k < 10; ++k) m[k] += f.partials[(size_t)c * 10 + k];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) sh[k * kBlock + threadIdx.x] = m[k];
+// One block per frame: the refit plane from the moments pass's partials,
+// once (the kernel boundary orders the partials of every block before it).
+__global__ __launch_bounds__(kBlock) void k_refit_solve(const FrameDev* __restrict__ tab, int r) {
+    __shared__ double s_plane[4], s_cent[3], s_n;
+    __shared__ double s_red[10 * kBlock];
+    const FrameDev& f = tab[blockIdx.z];
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active || rr.stop) return;
+    const float4 p0 = ld_global4(f.hyp_p0, rr.jstar);  // the moments' origin
+    solve_refit(f, rr.M, p0.x, p0.y, p0.z, s_plane, s_cent, &s_n, s_red);
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-#pragma unroll
-            for (int k = 0; k < 10; ++k) sh[k * kBlock + threadIdx.x] += sh[k * kBlock + threadIdx.x + w];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        RoundState* st = f.st;
+        for (int k = 0; k < 4; ++k) st->plane[k] = s_plane[k];
+        for (int k = 0; k < 3; ++k) st->centroid[k] = s_cent[k];
+        st->s_count = (int)s_n;
     }
-    if (threadIdx.x != 0) return;
-#pragma unroll
-    for (int k = 0; k < 10; ++k) m[k] = sh[k * kBlock];
-    const double n = m[0];
-    const double mx = m[1] / n, my = m[2] / n, mz = m[3] / n;
-    double a[3][3];
-    a[0][0] = m[4] - m[1] * mx; a[0][1] = m[5] - m[1] * my; a[0][2] = m[6] - m[1] * mz;
-    a[1][1] = m[7] - m[2] * my; a[1][2] = m[8] - m[2] * mz; a[2][2] = m[9] - m[3] * mz;
-    a[1][0] = a[0][1]; a[2][0] = a[0][2]; a[2][1] = a[1][2];
-    double v[3][3];
-    jacobi3(a, v);
-    int kmin = 0;
-    if (a[1][1] < a[kmin][kmin]) kmin = 1;
-    if (a[2][2] < a[kmin][kmin]) kmin = 2;
-    double nx = v[0][kmin], ny = v[1][kmin], nz = v[2][kmin];
-    const double nn = sqrt(nx * nx + ny * ny + nz * nz);
-    nx /= nn; ny /= nn; nz /= nn;
-    const RoundState* st = f.st;
-    const double cx = st->shift[0] + mx, cy = st->shift[1] + my, cz = st->shift[2] + mz;
-    double d = -(nx * cx + ny * cy + nz * cz);
-    if (d < 0.0) {
-        nx = -nx; ny = -ny; nz = -nz; d = -d;
-    }
-    plane[0] = nx; plane[1] = ny; plane[2] = nz; plane[3] = d;
-    centroid[0] = cx; centroid[1] = cy; centroid[2] = cz;
-    *nmom = n;
 }
 
 __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restrict__ tab, int r) {
-    __shared__ double s_plane[4], s_cent[3], s_n;
     __shared__ int sh[4];
-    __shared__ double s_red[10 * kBlock];
     const FrameDev& f = tab[blockIdx.z];
-    RoundState* st = f.st;
     const RoundRec rr = round_rec(f, r);
     if (!rr.active || rr.stop) return;
     const int M = rr.M;
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
     if ((int)blockIdx.x >= nch) return;
-    solve_refit(f, M, s_plane, s_cent, &s_n, s_red);
-    __syncthreads();
-    const SplitPlane q = split_plane(s_plane);
+    const SplitPlane q = split_plane(f.st->plane);  // solved by the last block of the moments pass
     const float t = f.thresh;
     const float4* __restrict__ pts = f.list[r & 1];
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
@@ -1390,11 +1404,6 @@ __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restri
             cnt += (c * kRefitChunk + s * kBlock + (int)threadIdx.x < e && fabsf(refit_res(q, pp[s].x, pp[s].y, pp[s].z)) < t) ? 1 : 0;
         cnt = block_sum(cnt, sh);
         if (threadIdx.x == 0) f.chunk_cnt[c] = cnt;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        for (int k = 0; k < 4; ++k) st->plane[k] = s_plane[k];
-        for (int k = 0; k < 3; ++k) st->centroid[k] = s_cent[k];
-        st->s_count = (int)s_n;
     }
 }
 
@@ -1678,6 +1687,7 @@ hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_
     const int nch = (max_px + kRefitChunk - 1) / kRefitChunk;
     const int gx = clampi(nch, 1, 1024);
     hipLaunchKernelGGL(k_refit_moments, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
+    hipLaunchKernelGGL(k_refit_solve, dim3(1, 1, nf), dim3(kBlock), 0, s, tab, r);
     hipLaunchKernelGGL(k_refit_final, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
     hipLaunchKernelGGL(k_apply, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
     return hipGetLastError();
