@@ -46,7 +46,10 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 // Max (or min) over the wave, returned to every lane, by the same DPP steps.
 template <bool MAX, int CTRL, int ROW_MASK = 0xF>
 __device__ __forceinline__ int dpp_ext(int v) {
-    const int b = __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xF, false);
+    // all rows enabled: every source lane is valid, so no old value is needed
+    // and the compiler can fold the permute into the min / max
+    const int b = ROW_MASK == 0xF ? __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true)
+                                  : __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xF, false);
     return MAX ? max(v, b) : min(v, b);
 }
 

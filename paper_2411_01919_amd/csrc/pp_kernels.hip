@@ -849,30 +849,27 @@ __device__ __forceinline__ float3 ld_global_xyz(const float4* p, int i) {
     return make_float3(v.x, v.y, v.z);
 }
 
+// Floats as integers of the same order (the sign-magnitude bits of negative
+// values flipped), so that min / max over a wave are integer DPP min / max.
+__device__ __forceinline__ int ordered_bits(float v) {
+    const int b = __float_as_int(v);
+    return b ^ ((b >> 31) & 0x7FFFFFFF);
+}
+__device__ __forceinline__ float from_ordered_bits(int b) { return __int_as_float(b ^ ((b >> 31) & 0x7FFFFFFF)); }
+
 // min / max over the wave with DPP lane permutes (no LDS): pairs, quads, rows
 // of 16 by rotation, then the row broadcasts; lane 63 ends with the result.
-template <bool MAX, int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_extreme(float a) {
-    const float b = __int_as_float(
-        __builtin_amdgcn_update_dpp(__float_as_int(a), __float_as_int(a), CTRL, ROW_MASK, 0xF, false));
-    return MAX ? fmaxf(a, b) : fminf(a, b);
-}
-
 template <bool MAX>
-__device__ __forceinline__ float wave_extreme_to_lane63(float v) {
-    v = dpp_extreme<MAX, 0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
-    v = dpp_extreme<MAX, 0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
-    v = dpp_extreme<MAX, 0x124, 0xF>(v);  // row_ror:4
-    v = dpp_extreme<MAX, 0x128, 0xF>(v);  // row_ror:8
-    v = dpp_extreme<MAX, 0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    v = dpp_extreme<MAX, 0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+__device__ __forceinline__ int wave_extreme_to_lane63(int v) {
+    v = dpp_ext<MAX, 0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_ext<MAX, 0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_ext<MAX, 0x124>(v);  // row_ror:4
+    v = dpp_ext<MAX, 0x128>(v);  // row_ror:8
+    v = dpp_ext<MAX, 0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_ext<MAX, 0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
     return v;
 }
 
-// Bounding boxes of the 64-point tiles of round r's list (a wave reduces
-// kBoxTilesPerWave tiles, one point per lane, their loads issued together):
-// centre c (w: the tile's point count as integer bits) and half extents e,
-// widened so that [c - e, c + e] holds every point of the tile.
 constexpr int kBoxTilesPerWave = 4;
 
 __global__ __launch_bounds__(kBlock) void k_tile_box(const FrameDev* __restrict__ tab, int r) {
@@ -894,9 +891,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_box(const FrameDev* __restrict_
         for (int q = 0; q < kBoxTilesPerWave; ++q) {
             const int tile = t0 + q;
             if (tile >= ntiles) break;
-            const float lx = wave_extreme_to_lane63<false>(p[q].x), hx = wave_extreme_to_lane63<true>(p[q].x);
-            const float ly = wave_extreme_to_lane63<false>(p[q].y), hy = wave_extreme_to_lane63<true>(p[q].y);
-            const float lz = wave_extreme_to_lane63<false>(p[q].z), hz = wave_extreme_to_lane63<true>(p[q].z);
+            const int bx = ordered_bits(p[q].x), by = ordered_bits(p[q].y), bz = ordered_bits(p[q].z);
+            const float lx = from_ordered_bits(wave_extreme_to_lane63<false>(bx));
+            const float hx = from_ordered_bits(wave_extreme_to_lane63<true>(bx));
+            const float ly = from_ordered_bits(wave_extreme_to_lane63<false>(by));
+            const float hy = from_ordered_bits(wave_extreme_to_lane63<true>(by));
+            const float lz = from_ordered_bits(wave_extreme_to_lane63<false>(bz));
+            const float hz = from_ordered_bits(wave_extreme_to_lane63<true>(bz));
             if (lane == 63) {
                 const float cx = 0.5f * (lx + hx), cy = 0.5f * (ly + hy), cz = 0.5f * (lz + hz);
                 // the rounded differences may fall short of the true ones by an ulp: widen by 2^-20
