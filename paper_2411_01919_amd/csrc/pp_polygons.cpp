@@ -10,6 +10,7 @@
 //     iff its distance to the current chord exceeds eps pixels.
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <vector>
 
 #include "pp.h"
@@ -60,13 +61,6 @@ void trace(const Labels& L, int g, Px s, std::vector<Px>& out, size_t cap) {
     }
 }
 
-double line_dist(const Px& p, const Px& a, const Px& b) {
-    const double dx = b.x - a.x, dy = b.y - a.y;
-    const double len = std::sqrt(dx * dx + dy * dy);
-    if (len == 0.0) return std::sqrt((double)(p.x - a.x) * (p.x - a.x) + (double)(p.y - a.y) * (p.y - a.y));
-    return std::fabs(dx * (p.y - a.y) - dy * (p.x - a.x)) / len;
-}
-
 // Douglas-Peucker over chain[0..n-1]; appends the kept points except the last to out.
 void simplify(const std::vector<Px>& chain, double eps, std::vector<Px>& out) {
     const int n = (int)chain.size();
@@ -77,15 +71,28 @@ void simplify(const std::vector<Px>& chain, double eps, std::vector<Px>& out) {
         const auto [lo, hi] = todo.back();
         todo.pop_back();
         if (hi - lo < 2) continue;
-        double best = -1.0;
+        // distance of each point to the chord lo-hi, |cross| / len (to the point lo if the
+        // chord is empty); the first farthest point splits.  The cross products (and the
+        // squared distances) are exact integers, and distinct ones keep their order after
+        // the division by len (the square root), so the search runs on the integers and
+        // only the farthest point's distance is formed.
+        const Px a = chain[lo], b = chain[hi];
+        const int64_t ix = b.x - a.x, iy = b.y - a.y;
+        const bool empty = ix == 0 && iy == 0;
+        int64_t bestk = -1;
         int at = -1;
         for (int i = lo + 1; i < hi; ++i) {
-            const double d = line_dist(chain[i], chain[lo], chain[hi]);
-            if (d > best) {
-                best = d;
+            const Px& p = chain[i];
+            const int64_t px = p.x - a.x, py = p.y - a.y;
+            int64_t k = empty ? px * px + py * py : ix * py - iy * px;
+            if (k < 0) k = -k;
+            if (k > bestk) {
+                bestk = k;
                 at = i;
             }
         }
+        const double dx = (double)ix, dy = (double)iy;
+        const double best = empty ? std::sqrt((double)bestk) : (double)bestk / std::sqrt(dx * dx + dy * dy);
         if (best > eps) {
             keep[at] = 1;
             todo.push_back({lo, at});
@@ -108,14 +115,25 @@ extern "C" pp_status pp_region_polygons(const int16_t* region_host, pp_frame_des
     const Labels L{region_host, desc.width, desc.height, desc.pitch_px};
     std::vector<Px> first(n_regions, Px{-1, -1});
     int left = n_regions;
-    for (int y = 0; y < L.H && left > 0; ++y)
-        for (int x = 0; x < L.W; ++x) {
-            const int g = region_host[(size_t)y * L.pitch + x];
+    for (int y = 0; y < L.H && left > 0; ++y) {
+        const int16_t* row = region_host + (size_t)y * L.pitch;
+        for (int x = 0; x < L.W && left > 0;) {
+            const int g = row[x];
             if (g >= 0 && g < n_regions && first[g].x < 0) {
                 first[g] = {x, y};
                 --left;
             }
+            // the rest of this run carries the same label: four labels per 64-bit compare
+            const uint64_t rep = (uint64_t)(uint16_t)g * 0x0001000100010001ull;
+            int e = x + 1;
+            for (uint64_t v; e + 4 <= L.W; e += 4) {
+                std::memcpy(&v, row + e, 8);
+                if (v != rep) break;
+            }
+            while (e < L.W && row[e] == g) ++e;
+            x = e;
         }
+    }
     const size_t cap = 4 * (size_t)L.W * L.H + 8;
     std::vector<Px> contour, poly, chain;
     int64_t total = 0;
@@ -128,12 +146,14 @@ extern "C" pp_status pp_region_polygons(const int16_t* region_host, pp_frame_des
         if (m <= 2) {
             poly = contour;
         } else {
+            // the first contour point farthest from the start (squared distances are exact
+            // integers, and distinct ones keep their order under the square root)
             const Px s = contour[0];
             int far = 0;
-            double fd = -1.0;
+            int64_t fd = -1;
             for (int i = 1; i < m; ++i) {
-                const double d = std::sqrt((double)(contour[i].x - s.x) * (contour[i].x - s.x) +
-                                           (double)(contour[i].y - s.y) * (contour[i].y - s.y));
+                const int64_t ex = contour[i].x - s.x, ey = contour[i].y - s.y;
+                const int64_t d = ex * ex + ey * ey;
                 if (d > fd) {
                     fd = d;
                     far = i;
