@@ -65,6 +65,27 @@ def test_all_tunings_give_bitwise_identical_diffusion(pp):
     ctx.close()
 
 
+@pytest.mark.parametrize("H,W", [(3, 3), (3, 300), (300, 3), (4, 57), (17, 57), (33, 130), (65, 129)])
+def test_register_diffusion_on_small_and_ragged_shapes(pp, orc, H, W):
+    """The register-resident kernel (one wave per 64 - 2T columns and 16 rows)
+    on frames narrower or shorter than one of its tiles: bitwise the LDS
+    tiles' result at every fusion depth, and the oracle's within 1e-3 mm."""
+    rng = np.random.default_rng(1000 * H + W)
+    y, x = np.mgrid[0:H, 0:W]
+    img = np.rint(1500 + 2.0 * x + 3.0 * y + rng.normal(0.0, 10.0, (H, W))).astype(np.uint16)
+    img[rng.random((H, W)) < 0.05] = 0
+    ctx = pp.Context(0)
+    outs = []
+    for tile, T in ((1, 3), (6, 1), (6, 4), (6, 10), (5, 5)):
+        ctx.set_tuning(diffuse_tile=tile, diffuse_t=T)
+        outs.append(pp.diffuse(to_dev(img), 20, 0.2, 30.0, ctx=ctx).cpu().numpy())
+    ctx.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    ref = orc.diffuse(img, 20, 0.2, 30.0)
+    assert np.abs(outs[0].astype(np.float64) - ref).max() <= 1e-3
+
+
 # ------------------------------------------------------------------ normals
 @pytest.mark.parametrize("cid,k", [(1, 0), (2, 0), (3, 1)])
 def test_points_and_normals_match_oracle(pp, orc, cid, k):
@@ -329,6 +350,26 @@ def test_batch_graph_eager_and_plain_are_bitwise_equal(pp):
             for a, b in zip(got, ref):
                 assert np.array_equal(a, b), mode
     log(f"  batch of {len(spec)} ragged frames: plain == eager == graph (x2)")
+
+
+def test_batch_of_nine_frames_equals_the_plain_path(pp):
+    """More frames than XCDs and not a multiple of 8: the XCD-ordered grid of
+    the hypothesis kernel still covers every (frame, block) once."""
+    import torch
+    spec = [(1, 0), (1, 1), (1, 2), (3, 0), (3, 1), (3, 2), (2, 0), (2, 1), (2, 2)]
+    frames = _batch_frames(pp, spec)
+    for _, fo in frames:
+        pp.run_frame(fo)
+    torch.cuda.synchronize()
+    plain = [_snapshot(fo) for _, fo in frames]
+    for _, fo in frames:
+        for t in (fo.depth_mm, fo.points, fo.normals, fo.planes, fo.labels):
+            t.zero_()
+    pp.batch_run([fo for _, fo in frames], graph=True)
+    torch.cuda.synchronize()
+    for (f, fo), ref in zip(frames, plain):
+        for a, b in zip(_snapshot(fo), ref):
+            assert np.array_equal(a, b)
 
 
 def test_shuffled_batch_and_repeats_are_deterministic(pp):
