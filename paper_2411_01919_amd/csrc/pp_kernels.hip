@@ -405,24 +405,38 @@ __global__ __launch_bounds__(kBlock) void k_diffuse_copy(const FrameDev* __restr
 // weights sum to zero, Sx P = z_c (8/fx, 0, 0) + sum_k wx_k (z_k - z_c) ray_k
 // (and likewise for Sy): evaluating it in that form avoids the cancellation of
 // summing nearly equal points.  Depth is kept in mm (a common scale factor).
+// Element i of a row-major plane in the global address space, addressed by a
+// 32-bit byte offset from a uniform base (one VGPR offset per access, no 64-bit
+// address arithmetic).  Requires i * sizeof(T) < 2^32: a plane holds at most
+// 2^30 pixels.
+typedef __attribute__((address_space(1))) char gbyte;
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* plane_at(T* base, uint32_t i) {
+    return (__attribute__((address_space(1))) T*)((gbyte*)base + (i * (uint32_t)sizeof(T)));
+}
+__device__ __forceinline__ float plane_ld(const float* base, uint32_t i) {
+    return *(const __attribute__((address_space(1))) float*)((const gbyte*)base + i * 4u);
+}
+
 __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__ tab) {
     const FrameDev& f = tab[blockIdx.z];
     const int W = f.W, H = f.H, pitch = f.pitch;
     const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= W || y >= H) return;
-    const size_t o = (size_t)y * pitch + x;
+    const uint32_t o = (uint32_t)y * (uint32_t)pitch + (uint32_t)x;
     const size_t plane = (size_t)H * pitch;
     // the 3x3 neighbourhood in one batch of loads (indices clamped into the frame;
     // clamped values are used only where the pixel is not interior, i.e. never)
     float nbv[3][3];
     {
-        const gf32_cptr dm = (gf32_cptr)f.dmm;
-        const int xs[3] = {max(x - 1, 0), x, min(x + 1, W - 1)};
-        const int ys[3] = {max(y - 1, 0), y, min(y + 1, H - 1)};
+        const float* dm = f.dmm;
+        const uint32_t xs[3] = {(uint32_t)max(x - 1, 0), (uint32_t)x, (uint32_t)min(x + 1, W - 1)};
+        const uint32_t ys[3] = {(uint32_t)max(y - 1, 0), (uint32_t)y, (uint32_t)min(y + 1, H - 1)};
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) nbv[j][i] = dm[(size_t)ys[j] * pitch + xs[i]];
+            for (int i = 0; i < 3; ++i)
+                nbv[j][i] = plane_ld(dm, ys[j] * (uint32_t)pitch + xs[i]);
     }
     const float I = nbv[1][1];
     const bool dv = I > 0.f;
@@ -433,9 +447,9 @@ __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__
         py = z * ((float)y - f.cy) / f.fy;
         pz = z;
     }
-    f.pts[o] = px;
-    f.pts[plane + o] = py;
-    f.pts[2 * plane + o] = pz;
+    *plane_at(f.pts, o) = px;
+    *plane_at(f.pts + plane, o) = py;
+    *plane_at(f.pts + 2 * plane, o) = pz;
     bool nv = dv && x >= 1 && x <= W - 2 && y >= 1 && y <= H - 2;
     float n0 = 0.f, n1 = 0.f, n2 = 0.f;
     if (nv) {
@@ -444,7 +458,8 @@ __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__
 #pragma unroll
             for (int i = 0; i < 3; ++i) nv = nv && (nbv[j][i] > 0.f);
         if (nv) {
-            // sums of w * dI * (u - cx), w * dI * (v - cy), w * dI for both kernels
+            // sums of w * dI * (u - cx), w * dI * (v - cy), w * dI for both kernels;
+            // w dI is exact (w is 0, +-1 or +-2), one rounding per term
             float ax = 0.f, bx = 0.f, cx_ = 0.f, ay = 0.f, by = 0.f, cy_ = 0.f;
             const float wrow[3] = {1.f, 2.f, 1.f};
 #pragma unroll
@@ -457,27 +472,31 @@ __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__
                     const float dI = nbv[j][i] - I;
                     const float uu = (float)(x + i - 1) - f.cx;
                     const float vv = (float)(y + j - 1) - f.cy;
-                    ax += wx * dI * uu; bx += wx * dI * vv; cx_ += wx * dI;
-                    ay += wy * dI * uu; by += wy * dI * vv; cy_ += wy * dI;
+                    const float ex = wx * dI, ey = wy * dI;
+                    ax = fmaf(ex, uu, ax); bx = fmaf(ex, vv, bx); cx_ += ex;
+                    ay = fmaf(ey, uu, ay); by = fmaf(ey, vv, by); cy_ += ey;
                 }
-            const float sxx = (8.f * I + ax) / f.fx, sxy = bx / f.fy, sxz = cx_;
-            const float syx = ay / f.fx, syy = (8.f * I + by) / f.fy, syz = cy_;
+            // the Sobel responses of the points: the image-plane ones scaled by 1/fx, 1/fy
+            const float ifx = 1.0f / f.fx, ify = 1.0f / f.fy;
+            const float sxx = (8.f * I + ax) * ifx, sxy = bx * ify, sxz = cx_;
+            const float syx = ay * ifx, syy = (8.f * I + by) * ify, syz = cy_;
             const float mx = sxy * syz - sxz * syy;
             const float my = sxz * syx - sxx * syz;
             const float mz = sxx * syy - sxy * syx;
-            const float mn = sqrtf(mx * mx + my * my + mz * mz);
-            nv = mn > 0.f;
+            const float m2 = fmaf(mx, mx, fmaf(my, my, mz * mz));
+            nv = m2 > 0.f;
             if (nv) {
-                n0 = -mx / mn;
-                n1 = -my / mn;
-                n2 = -mz / mn;
+                const float inv = -__frsqrt_rn(m2);
+                n0 = mx * inv;
+                n1 = my * inv;
+                n2 = mz * inv;
             }
         }
     }
-    f.nrm[o] = n0;
-    f.nrm[plane + o] = n1;
-    f.nrm[2 * plane + o] = n2;
-    f.valid[o] = (uint8_t)((dv ? 1 : 0) | (nv ? 2 : 0));
+    *plane_at(f.nrm, o) = n0;
+    *plane_at(f.nrm + plane, o) = n1;
+    *plane_at(f.nrm + 2 * plane, o) = n2;
+    *plane_at(f.valid, o) = (uint8_t)((dv ? 1 : 0) | (nv ? 2 : 0));
 }
 
 // ------------------------------------------------------------------ valid list
