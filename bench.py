@@ -62,9 +62,15 @@ def score_kernel_name(precision, tuning):
 
 
 def source_hash():
+    """Hash of the kernel source's code: comments and white space removed, so
+    that only a change to the code itself detaches the stored traffic figures."""
+    import re
     h = hashlib.sha256()
     for f in ("paper_2411_01919_amd/csrc/pp_kernels.hip",):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        src = open(os.path.join(ROOT, f), encoding="utf-8").read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,17 +1,23 @@
 // HIP kernels of the plane-extraction path for gfx950 (MI355X, wave64).
 //
 // Stage map (arXiv 2411.01919):
-//   k_diffuse        Perona-Malik diffusion, Eq. 1 / Alg. 1 (LDS halo tiles,
-//                    T iterations fused per pass, FP32 on delta = I - I0)
+//   k_diffuse_wc     Perona-Malik diffusion, Eq. 1 / Alg. 1: T iterations fused
+//                    per pass, FP32 on delta = I - I0, the iterate in registers
+//                    (one wave per column strip); k_diffuse: the same on LDS tiles
 //   k_normals        back-projection (Alg. 2) + Sobel normal image (Eq. 2)
-//   k_valid_*        row-major list of depth-valid pixels (Alg. 2 point set)
+//   k_valid_*,       row-major list of depth-valid pixels (Alg. 2 point set) and
+//   k_list_scatter   the round-0 scoring list in 8x8-block order
 //   k_hypgen         3-point hypotheses from Philox4x64-10 (Alg. 2)
-//   k_score          inlier counts, point-to-plane distance < t (Eq. 3, Alg. 2)
-//   k_refit_*        selection + least-squares refit (FP64 moments, Jacobi)
+//   k_tile_box,      inlier counts, point-to-plane distance < t (Eq. 3, Alg. 2):
+//   k_score_cull     64-point tiles decided from their bounding boxes, the rest
+//                    point by point (k_score: every point)
+//   k_refit_*        selection, FP64 moments, the least-squares plane (Jacobi,
+//                    one block per frame), its inliers per chunk
 //   k_apply          remove / label the refit plane's inliers, next round
 //
 // Every kernel takes a device table of FrameDev and reads its frame from
-// blockIdx.z, so one launch serves one frame or a ragged batch alike.
+// blockIdx.z (k_hypgen: from an XCD-aware 1-D grid), so one launch serves one
+// frame or a ragged batch alike.
 
 #include <math.h>
 
