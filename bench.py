@@ -89,6 +89,17 @@ def load_traffic(kernel_hash):
     return d.get("bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(frames, cfg, budget_s=12.0, max_frames=2048):
     """The float64 oracle on the host cores over the bench's frames, cycled
     until about budget_s of CPU work is done (whole frames only)."""
@@ -104,7 +115,8 @@ def cpu_baseline(frames, cfg, budget_s=12.0, max_frames=2048):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "frames/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": done / dt, "unit": "frames/s", "cores": oracle.num_threads(), "cpu_model": cpu_model(),
+            "kind": "oracle",
             "sample": f"{done} frames of the 640x480 workload ({min(done, len(frames))} distinct, cycled) through "
                       f"the float64 oracle (diffusion, normals, sequential RANSAC), {dt:.1f} s"}
 
