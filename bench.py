@@ -100,6 +100,20 @@ def cpu_model():
     return "unknown"
 
 
+def cpu_one_thread(budget_s=6.0):
+    """The same oracle workload on one host thread, in a child process started
+    with OMP_NUM_THREADS=1 (OpenMP reads it when the oracle loads).  The child
+    touches no GPU."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-one-thread", str(budget_s)],
+                           env=env, capture_output=True, text=True, timeout=budget_s + 120)
+        return json.loads(r.stdout.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError, OSError):
+        return None
+
+
 def cpu_baseline(frames, cfg, budget_s=12.0, max_frames=2048):
     """The float64 oracle on the host cores over the bench's frames, cycled
     until about budget_s of CPU work is done (whole frames only)."""
@@ -371,7 +385,14 @@ def main():
     ap.add_argument("--no-chain", action="store_true", help="skip the paper-chain leg (segmentation, region RANSAC, map)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy (reference for HBM byte counters) and exit")
+    ap.add_argument("--oracle-one-thread", type=float, default=0.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_one_thread > 0:  # the child of cpu_one_thread: oracle only, no GPU
+        import scenes
+        cfg = scenes.CONFIGS[2]
+        rec = cpu_baseline([scenes.make_frame(2, k) for k in range(4)], cfg, budget_s=args.oracle_one_thread)
+        print(json.dumps({"value": rec["value"], "cores": rec["cores"], "sample": rec["sample"]}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
@@ -512,6 +533,9 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         base = cpu_baseline(frames, cfg)
+        one = cpu_one_thread()
+        if one:
+            base["one_thread"] = one
         log(f"cpu baseline: {base}")
 
     rec = {
