@@ -1408,15 +1408,37 @@ __global__ __launch_bounds__(kBlock) void k_refit_solve(const FrameDev* __restri
     }
 }
 
+// |F| per chunk, for the removal.  SOLVE: each block first solves the refit
+// plane itself (solve_refit, the same reduction order as k_refit_solve, so the
+// same plane bit for bit) and block 0 stores it.  Used when the grid fits in one
+// residency wave (a few frames), where the redundant solves run side by side and
+// the separate solve launch would only add its latency.
+template <bool SOLVE>
 __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restrict__ tab, int r) {
     __shared__ int sh[4];
+    __shared__ double s_plane[4], s_cent[3], s_n;
+    __shared__ double s_red[SOLVE ? 10 * kBlock : 1];
     const FrameDev& f = tab[blockIdx.z];
     const RoundRec rr = round_rec(f, r);
     if (!rr.active || rr.stop) return;
     const int M = rr.M;
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
     if ((int)blockIdx.x >= nch) return;
-    const SplitPlane q = split_plane(f.st->plane);  // solved by the last block of the moments pass
+    SplitPlane q;
+    if constexpr (SOLVE) {
+        const float4 p0 = ld_global4(f.hyp_p0, rr.jstar);  // the moments' origin
+        solve_refit(f, M, p0.x, p0.y, p0.z, s_plane, s_cent, &s_n, s_red);
+        __syncthreads();
+        q = split_plane(s_plane);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            RoundState* st = f.st;
+            for (int k = 0; k < 4; ++k) st->plane[k] = s_plane[k];
+            for (int k = 0; k < 3; ++k) st->centroid[k] = s_cent[k];
+            st->s_count = (int)s_n;
+        }
+    } else {
+        q = split_plane(f.st->plane);  // stored by k_refit_solve
+    }
     const float t = f.thresh;
     const float4* __restrict__ pts = f.list[r & 1];
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
@@ -1702,6 +1724,11 @@ static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int 
     }
 }
 
+// Counting grids of at most this many blocks solve the refit plane in every
+// block (one residency wave: 7 such blocks fit per CU); larger ones solve it
+// once per frame in k_refit_solve.
+constexpr long kFusedSolveBlocks = 1024;
+
 hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_hyps, int precision,
                         const Tuning& tu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const int bpf = (max_hyps + kHypPerBlock - 1) / kHypPerBlock;
@@ -1713,8 +1740,12 @@ hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_
     const int nch = (max_px + kRefitChunk - 1) / kRefitChunk;
     const int gx = clampi(nch, 1, 1024);
     hipLaunchKernelGGL(k_refit_moments, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
-    hipLaunchKernelGGL(k_refit_solve, dim3(1, 1, nf), dim3(kBlock), 0, s, tab, r);
-    hipLaunchKernelGGL(k_refit_final, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
+    if ((long)nf * gx <= kFusedSolveBlocks) {
+        hipLaunchKernelGGL(k_refit_final<true>, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
+    } else {
+        hipLaunchKernelGGL(k_refit_solve, dim3(1, 1, nf), dim3(kBlock), 0, s, tab, r);
+        hipLaunchKernelGGL(k_refit_final<false>, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
+    }
     hipLaunchKernelGGL(k_apply, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
     return hipGetLastError();
 }
