@@ -454,6 +454,7 @@ pp_status pp_normals(pp_ctx* c, const float* depth_mm_dev, pp_frame_desc desc, p
     f.nrm = normals_dev;
     f.valid = valid_dev;
     f.fx = K.fx; f.fy = K.fy; f.cx = K.cx; f.cy = K.cy;
+    f.ifx = 1.0f / K.fx; f.ify = 1.0f / K.fy;
     hipStream_t st = (hipStream_t)stream;
     if ((s = put_plain(c, f, st)) != PP_OK) return s;
     HIPCHK(c, ppk::launch_normals(c->plain_tab, 1, desc.width, desc.height, st));
@@ -781,6 +782,7 @@ pp_status upload_batch_table(pp_ctx* c, const pp_frame_job* jobs, const BatchPla
         fill_diffuse(f, j.diffuse);
         fill_ransac(f, j.ransac);
         f.fx = j.K.fx; f.fy = j.K.fy; f.cx = j.K.cx; f.cy = j.K.cy;
+        f.ifx = 1.0f / j.K.fx; f.ify = 1.0f / j.K.fy;
         f.depth = j.depth;
         f.dmm = j.depth_mm;
         f.pts = j.points;

@@ -55,6 +55,7 @@ struct FrameDev {
     // geometry
     int32_t W, H, pitch, pad0;
     float fx, fy, cx, cy;
+    float ifx, ify;          // 1/fx, 1/fy (correctly rounded, set on the host)
     // diffusion
     int32_t iters;
     float lambda;

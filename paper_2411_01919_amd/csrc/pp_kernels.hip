@@ -427,7 +427,9 @@ __device__ __forceinline__ float plane_ld(const float* base, uint32_t i) {
 __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__ tab) {
     const FrameDev& f = tab[blockIdx.z];
     const int W = f.W, H = f.H, pitch = f.pitch;
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    // a wave is one image row: y and the row offsets are wave-uniform (scalar)
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (x >= W || y >= H) return;
     const uint32_t o = (uint32_t)y * (uint32_t)pitch + (uint32_t)x;
     const size_t plane = (size_t)H * pitch;
@@ -483,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__
                     ay = fmaf(ey, uu, ay); by = fmaf(ey, vv, by); cy_ += ey;
                 }
             // the Sobel responses of the points: the image-plane ones scaled by 1/fx, 1/fy
-            const float ifx = 1.0f / f.fx, ify = 1.0f / f.fy;
+            const float ifx = f.ifx, ify = f.ify;
             const float sxx = (8.f * I + ax) * ifx, sxy = bx * ify, sxz = cx_;
             const float syx = ay * ifx, syy = (8.f * I + by) * ify, syz = cy_;
             const float mx = sxy * syz - sxz * syy;
