@@ -9,7 +9,7 @@ the whole path (diffusion, back-projection, normals, RANSAC) as one
 graph-replayed ragged batch; inputs are resident in HBM before timing.
 
 Prints ONE JSON line (the contract the driver reads).  Progress goes to
-stderr.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+stderr.  `--gpus N` with N > 1 exits: the path runs on one GPU.
 """
 import argparse
 import hashlib
@@ -394,7 +394,7 @@ def main():
         print(json.dumps({"value": rec["value"], "cores": rec["cores"], "sample": rec["sample"]}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the path runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -56,7 +56,7 @@ enum {
     PP_E_HIP = -4,          /* a HIP runtime call failed; the object is poisoned */
     PP_E_NODEVICE = -5,     /* no usable GPU */
     PP_E_CLOSED = -6,       /* server/stream closed or destroyed */
-    PP_E_UNSUPPORTED = -7,  /* valid request outside what this build implements */
+    PP_E_UNSUPPORTED = -7,  /* valid request outside what this library implements */
     PP_E_TIMEOUT = -8,      /* reserved */
     PP_E_AGAIN = -9         /* pp_submit: the stream's staging is full; poll results, then retry */
 };

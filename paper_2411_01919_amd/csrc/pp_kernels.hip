@@ -675,7 +675,7 @@ __device__ __forceinline__ float3 load_point_g(const FrameDev& f, int off) {
     return make_float3(p[off], p[plane + off], p[2 * plane + off]);
 }
 
-// Round 0's scoring list: the depth-valid points in 8x8-block scan order,
+// The first RANSAC round's scoring list: the depth-valid points in 8x8-block scan order,
 // each tagged with its valid-list position (w), by ordered compaction over
 // chunks of 1024 scan positions.
 __global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restrict__ tab) {
