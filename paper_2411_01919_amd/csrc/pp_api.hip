@@ -483,7 +483,7 @@ static pp_status ransac_common(pp_ctx* c, const float* points_dev, const uint8_t
         if (dbg->round_info) HIPCHK(c, hipMemsetAsync(dbg->round_info, 0xFF, sizeof(int32_t) * 4 * p->max_planes, st));
     }
     if ((s = put_plain(c, f, st)) != PP_OK) return s;
-    HIPCHK(c, ppk::launch_valid_list(c->plain_tab, 1, (int)px, st));
+    HIPCHK(c, ppk::launch_valid_list(c->plain_tab, 1, (int)px, desc.width, desc.height, st));
     for (int r = 0; r < p->max_planes; ++r)
         HIPCHK(c, ppk::launch_round(c->plain_tab, 1, r, (int)px, p->hyps_per_plane, p->precision, c->tuning, st,
                                     c->timing ? c->score_ev[r][0] : nullptr, c->timing ? c->score_ev[r][1] : nullptr));
@@ -665,7 +665,7 @@ pp_status pp_debug_score_triples(pp_ctx* c, const float* points_dev, const uint8
     f.n_planes = reinterpret_cast<int32_t*>(static_cast<char*>(c->debug_scratch) + align256(px));
     hipStream_t st = (hipStream_t)stream;
     if ((s = put_plain(c, f, st)) != PP_OK) return s;
-    HIPCHK(c, ppk::launch_valid_list(c->plain_tab, 1, (int)px, st));
+    HIPCHK(c, ppk::launch_valid_list(c->plain_tab, 1, (int)px, desc.width, desc.height, st));
     hipLaunchKernelGGL(k_force_active, dim3(1), dim3(1), 0, st, c->plain_tab);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, ppk::launch_hyp_from_triples(c->plain_tab, triples_dev, n, st));
@@ -736,7 +736,7 @@ pp_status enqueue_batch(pp_ctx* c, const BatchPlan& b, hipStream_t st, bool capt
                                       b.group_iters[g], b.group_scheme[g], c->tuning, st));
     if (timed) HIPCHK(c, hipEventRecord(c->stage_ev[1], st));
     HIPCHK(c, ppk::launch_normals(c->batch_tab, b.nf, b.maxW, b.maxH, st));
-    HIPCHK(c, ppk::launch_valid_list(c->batch_tab, b.nf, b.max_px, st));
+    HIPCHK(c, ppk::launch_valid_list(c->batch_tab, b.nf, b.max_px, b.maxW, b.maxH, st));
     if (timed) HIPCHK(c, hipEventRecord(c->stage_ev[2], st));
     for (int r = 0; r < b.max_rounds; ++r)
         HIPCHK(c, ppk::launch_round(c->batch_tab, b.nf, r, b.max_px, b.max_hyps, b.precision, c->tuning, st,

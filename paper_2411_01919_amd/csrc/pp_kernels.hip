@@ -537,38 +537,42 @@ __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restri
     const int nwords = (npx + 3) >> 2;
     uint32_t* __restrict__ tw = reinterpret_cast<uint32_t*>(f.taken);
     for (int w = blockIdx.x * kBlock + threadIdx.x; w < nwords; w += gridDim.x * kBlock) tw[w] = 0u;
-    constexpr int S = kValidChunk / kBlock;
+    static_assert(kValidChunk == 4 * kBlock, "four pixels per thread and chunk");
     const gu8_cptr vg = (gu8_cptr)f.valid;
+    const bool word_rows = ((f.pitch | (int)(uintptr_t)f.valid) & 3) == 0;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        uint8_t vb[S];
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            const int p = min(c * kValidChunk + k * kBlock + (int)threadIdx.x, npx - 1);
-            const int y = p / f.W, x = p - y * f.W;
-            vb[k] = vg[(size_t)y * f.pitch + x];
-        }
+        // pixels p0..p0+3: one 32-bit load where they share a row, bytes otherwise
+        const int p0 = c * kValidChunk + 4 * (int)threadIdx.x;
         int cnt = 0;
-#pragma unroll
-        for (int k = 0; k < S; ++k) cnt += (c * kValidChunk + k * kBlock + (int)threadIdx.x < npx) ? (vb[k] & 1) : 0;
+        if (p0 < npx) {
+            const int y = p0 / f.W, x = p0 - y * f.W;
+            if (word_rows && x + 3 < f.W && (x & 3) == 0) {
+                const uint32_t w = *(const __attribute__((address_space(1))) uint32_t*)(vg + (size_t)y * f.pitch + x);
+                cnt = __popc(w & 0x01010101u);
+            } else {
+                for (int i = 0; i < 4 && p0 + i < npx; ++i) {
+                    const int yy = (p0 + i) / f.W, xx = p0 + i - yy * f.W;
+                    cnt += vg[(size_t)yy * f.pitch + xx] & 1;
+                }
+            }
+        }
         cnt = block_sum(cnt, sh);
         if (threadIdx.x == 0) f.chunk_cnt[c] = cnt;
     }
-    // the same counts over the 8x8-block scan that orders the scoring list
+    // the same counts over the 8x8-block scan that orders the scoring list:
+    // scan positions q0..q0+3 are 4 pixels of one row of one block
     const int nq = scan_positions(f);
     const int nchq = (nq + kValidChunk - 1) / kValidChunk;
     for (int c = blockIdx.x; c < nchq; c += gridDim.x) {
-        uint8_t vb[S];
-        bool in[S];
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            int x = 0, y = 0;
-            in[k] = scan_pixel(f, c * kValidChunk + k * kBlock + threadIdx.x, x, y);
-            if (!in[k]) x = y = 0;
-            vb[k] = vg[(size_t)y * f.pitch + x];
-        }
+        int x = 0, y = 0;
+        const bool in = scan_pixel(f, c * kValidChunk + 4 * (int)threadIdx.x, x, y);
         int cnt = 0;
-#pragma unroll
-        for (int k = 0; k < S; ++k) cnt += in[k] ? (vb[k] & 1) : 0;
+        if (in && word_rows && x + 3 < f.W) {
+            const uint32_t w = *(const __attribute__((address_space(1))) uint32_t*)(vg + (size_t)y * f.pitch + x);
+            cnt = __popc(w & 0x01010101u);
+        } else if (in) {
+            for (int i = 0; i < 4 && x + i < f.W; ++i) cnt += vg[(size_t)y * f.pitch + x + i] & 1;
+        }
         cnt = block_sum(cnt, sh);
         if (threadIdx.x == 0) f.chunk_cnt_q[c] = cnt;
     }
@@ -1670,13 +1674,17 @@ hipError_t launch_normals(const FrameDev* tab, int nf, int maxW, int maxH, hipSt
 
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, hipStream_t s) {
+hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, int maxW, int maxH, hipStream_t s) {
     const int nch = (max_px + kValidChunk - 1) / kValidChunk;
     const int gx = clampi(nch, 1, 1024);
     hipLaunchKernelGGL(k_valid_count, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab);
     hipLaunchKernelGGL(k_valid_scatter, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab);
-    // block-order chunks: the padded scan covers at most 3.4 max_px + 70 positions
-    const int gq = clampi((int)(((int64_t)4 * max_px + 4096) / kValidChunk + 1), 1, 1024);
+    // block-order chunks: a frame's padded scan covers at most 3.4 W H + 70
+    // positions, and at most the padded maxW x maxH grid; one block per chunk
+    const int64_t pad = kScanBlock;
+    const int64_t grid = (maxW + pad - 1) / pad * pad * ((maxH + pad - 1) / pad * pad);
+    const int64_t scan = grid < (int64_t)4 * max_px + 4096 ? grid : (int64_t)4 * max_px + 4096;
+    const int gq = clampi((int)((scan + kValidChunk - 1) / kValidChunk), 1, 1024);
     hipLaunchKernelGGL(k_list_scatter, dim3(gq, 1, nf), dim3(kBlock), 0, s, tab);
     return hipGetLastError();
 }
