@@ -78,3 +78,26 @@ def hyp_eps(planes_or, triples, L, P, pmax):
         lever = pmax / min(l1, l2)
         eps[j] = 1e-6 + 64 * EPS32 * (pmax + abs(planes_or[j, 3])) * (1.0 + lever * cond)
     return eps
+
+
+def check_removal(points, labels, valid, planes, t, min_inliers, hyps, band=1e-6):
+    """Invariants of sequential removal (Alg. 2) in float64 for one frame:
+    points [3][H][W], labels [H][W] int8 (-1 none), valid [H][W] 0/1, planes as
+    dicts with n, d, inliers, hyp_index in emission order.  Pixels within
+    `band` of t are exempt: the path decides them in compensated FP32 against
+    the FP64 plane."""
+    X = np.asarray(points, np.float64).reshape(3, -1)
+    lab = np.asarray(labels).reshape(-1)
+    val = np.asarray(valid).reshape(-1) > 0
+    assert np.all(lab[~val] == -1) and np.all(lab < len(planes))
+    earlier_far = np.ones(X.shape[1], bool)  # at least t from every plane so far
+    for r, pl in enumerate(planes):
+        dist = np.abs(np.asarray(pl["n"]) @ X + pl["d"])
+        decided = np.abs(dist - t) > band
+        mine = lab == r
+        assert pl["inliers"] == mine.sum() >= min_inliers, r
+        assert 0 <= pl["hyp_index"] < hyps, r
+        assert np.all(dist[mine & decided] < t), r
+        assert not np.any(mine & ~earlier_far), r
+        earlier_far &= (dist >= t) | ~decided
+    assert not np.any(val & (lab == -1) & ~earlier_far)

@@ -1,0 +1,100 @@
+"""The benchmark's workload in the benchmark's launch configuration.
+
+32 frames of the 640x480 straight staircase (frames 0..31, their own frame
+ids) in one HIP-graph batch with the tuning 6,4,4,4 (register-resident
+diffusion, 16 rows a wave, 4 iterations a pass; the culled scorer), replayed
+twice.  Checks:
+  - every frame: diffused depth within 1e-3 mm of the oracle's, points within
+    1e-6 m of the oracle's back-projection of that depth, and the invariants of
+    sequential removal in float64 (Alg. 2): a pixel labelled r lies within t of
+    plane r and at least t from every plane emitted before it; an unlabelled
+    depth-valid pixel lies at least t from every emitted plane; plane r's
+    inlier count is the number of pixels labelled r and reaches min_inliers.
+    Pixels within 1e-6 m of t are exempt (the removal decides in compensated
+    FP32 against the FP64 plane);
+  - sampled frames 0, 13 and 31: bitwise the plain per-frame path, which in
+    turn follows the oracle round by round (hypothesis triples bit-exact,
+    counts within their rounding bands, refit planes 1e-9).
+"""
+import numpy as np
+import pytest
+
+import scenes
+from gpu_util import cfg_params, check_removal, log, to_dev
+from test_gpu_parity import _follow
+
+pytestmark = pytest.mark.gpu
+
+BENCH_TUNING = (6, 4, 4, 4)
+N_FRAMES = 32
+SAMPLED = (0, 13, 31)
+
+
+@pytest.fixture(scope="module")
+def pp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2411_01919_amd as pp
+    pp.default_context(0)
+    return pp
+
+
+@pytest.fixture(scope="module")
+def batch(pp):
+    """(frames, per-frame host results of the 2nd graph replay, ransac configs)."""
+    import torch
+    frames = [scenes.make_frame(2, k) for k in range(N_FRAMES)]
+    outs, rcs = [], []
+    for f in frames:
+        H, W = f.depth.shape
+        dc, rc = cfg_params(2, W, H, f.meta["k"])
+        rcs.append(rc)
+        outs.append(pp.make_outputs(to_dev(f.depth), (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc))
+    ctx = pp.Context(0)
+    ctx.set_tuning(*BENCH_TUNING)
+    log(f"bench workload: {N_FRAMES} x 640x480, graph batch, tuning {BENCH_TUNING}")
+    snaps = []
+    for rep in range(2):
+        pp.batch_run(outs, graph=True, ctx=ctx)
+        torch.cuda.synchronize()
+        snaps.append([dict(depth_mm=fo.depth_mm.cpu().numpy(), points=fo.points.cpu().numpy(),
+                           normals=fo.normals.cpu().numpy(), valid=fo.valid.cpu().numpy(),
+                           labels=fo.labels.cpu().numpy(), n=int(fo.n_planes.cpu().item()),
+                           planes=pp.planes_to_numpy(fo.planes, int(fo.n_planes.cpu().item())))
+                      for fo in outs])
+    ctx.close()
+    for a, b in zip(snaps[0], snaps[1]):
+        for key in ("depth_mm", "points", "normals", "valid", "labels"):
+            assert np.array_equal(a[key], b[key]), key
+        assert a["n"] == b["n"]
+    return frames, snaps[1], rcs
+
+
+def test_every_frame_against_the_oracle_and_the_removal_invariants(pp, orc, batch):
+    frames, res, rcs = batch
+    cfg = scenes.CONFIGS[2]
+    for f, g, rc in zip(frames, res, rcs):
+        k = f.meta["k"]
+        ref = orc.diffuse(f.depth, cfg.diffuse_iters, cfg.lam, cfg.kappa_mm)
+        assert np.abs(g["depth_mm"].astype(np.float64) - ref).max() <= 1e-3, k
+        P, v = orc.backproject(g["depth_mm"].astype(np.float64), f.K)
+        assert np.array_equal(g["valid"] & 1, v), k
+        assert np.abs(g["points"] - P).max() <= 1e-6, k
+        assert 6 <= g["n"] <= rc.max_planes, (k, g["n"])
+        check_removal(g["points"], g["labels"], g["valid"] & 1, g["planes"], rc.thresh_m, rc.min_inliers, rc.hyps)
+    log(f"  {len(frames)} frames: oracle diffusion and points, removal invariants hold")
+
+
+@pytest.mark.parametrize("k", SAMPLED)
+def test_sampled_frames_equal_the_plain_path_that_follows_the_oracle(pp, orc, batch, k):
+    frames, res, _ = batch
+    g = _follow(pp, orc, frames[k], 2, k)
+    b = res[k]
+    for key in ("depth_mm", "points", "normals", "valid", "labels"):
+        assert np.array_equal(b[key], g[key]), (k, key)
+    assert b["n"] == g["n_planes"]
+    for pb, pg in zip(b["planes"], g["planes"]):
+        assert np.array_equal(pb["n"], pg["n"]) and pb["d"] == pg["d"]
+        assert np.array_equal(pb["centroid"], pg["centroid"])
+        assert pb["inliers"] == pg["inliers"] and pb["hyp_index"] == pg["hyp_index"]

@@ -375,3 +375,38 @@ def test_final_set_is_the_refit_planes_inliers_and_min_inliers_is_inclusive(orc)
     for mi, want in [(res.f_count, 0), (res.f_count + 1, 2)]:
         prm2 = orc.RansacParams(hyps=128, min_inliers=mi, seed=3)
         assert orc.ransac_round(P, L, np.zeros_like(valid), prm2, 0).status == want
+
+
+def test_removal_invariants_hold_on_the_oracle_and_fail_on_planted_mistakes(orc):
+    """The float64 removal invariants that the GPU test of the benchmark
+    workload applies to every frame hold on the oracle's own result, and each
+    planted mistake in a copy of that result breaks them: a plane shifted by
+    2t, two pixels of planes 0 and 1 swapped (counts unchanged), an inlier
+    dropped, a relabelled pixel."""
+    from gpu_util import check_removal
+    f = scenes.make_frame(1, 0)
+    cfg = scenes.CONFIGS[1]
+    H, W = f.depth.shape
+    prm = orc.RansacParams(hyps=cfg.hyps, max_planes=cfg.max_planes, min_inliers=cfg.min_inliers(W, H),
+                           thresh=cfg.thresh_m, seed=cfg.ransac_seed)
+    I = orc.diffuse(f.depth, cfg.diffuse_iters, cfg.lam, cfg.kappa_mm)
+    P, valid = orc.backproject(I, f.K)
+    rr = orc.ransac(P, valid, prm)
+    assert rr.n_planes >= 3
+    planes = [dict(n=rr.planes[r, :3], d=rr.planes[r, 3], inliers=int(rr.inliers[r]), hyp_index=int(rr.jstar[r]))
+              for r in range(rr.n_planes)]
+    args = (prm.thresh, prm.min_inliers, prm.hyps)
+    check_removal(P, rr.labels, valid, planes, *args, band=1e-12)
+
+    shifted = [dict(p) for p in planes]
+    shifted[1]["d"] += 2 * prm.thresh
+    with pytest.raises(AssertionError):
+        check_removal(P, rr.labels, valid, shifted, *args, band=1e-12)
+    flat = rr.labels.reshape(-1)
+    i0, i1 = np.flatnonzero(flat == 0)[0], np.flatnonzero(flat == 1)[0]
+    for edit in ({i0: 1, i1: 0}, {i0: -1}, {i0: 1}):
+        lab = rr.labels.copy()
+        for i, v in edit.items():
+            lab.reshape(-1)[i] = v
+        with pytest.raises(AssertionError):
+            check_removal(P, lab, valid, planes, *args, band=1e-12)
