@@ -592,10 +592,14 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
     const gu8_cptr vg = (gu8_cptr)f.valid;
     const gf32_cptr pg = (gf32_cptr)f.pts;
     const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt;
+    // valid pixels before chunk c, carried from this block's previous chunk
+    int before = 0;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        int before = 0;
-        for (int i = threadIdx.x; i < c; i += kBlock) before += ccnt[i];
-        before = block_sum(before, sh);
+        {
+            int add = 0;
+            for (int i = c - (c == (int)blockIdx.x ? c : (int)gridDim.x) + threadIdx.x; i < c; i += kBlock) add += ccnt[i];
+            before += block_sum(add, sh);
+        }
         // all loads of the chunk's steps first (indices clamped into the frame)
         int off[S];
         bool in[S], v[S];
@@ -693,10 +697,14 @@ __global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restr
     const gu8_cptr vg = (gu8_cptr)f.valid;
     const gf32_cptr pg = (gf32_cptr)f.pts;
     const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt_q;
+    // valid pixels before scan chunk c, carried from this block's previous chunk
+    int run = 0;
     for (int c = blockIdx.x; c < nchq; c += gridDim.x) {
-        int before = 0;
-        for (int i = threadIdx.x; i < c; i += kBlock) before += ccnt[i];
-        const int run = block_sum(before, sh);
+        {
+            int add = 0;
+            for (int i = c - (c == (int)blockIdx.x ? c : (int)gridDim.x) + threadIdx.x; i < c; i += kBlock) add += ccnt[i];
+            run += block_sum(add, sh);
+        }
         int off[S], lp[S];
         bool v[S];
         uint8_t vb[S];
@@ -1512,10 +1520,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
     const gi32_cptr Lg = (gi32_cptr)f.L;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        if (c != (int)blockIdx.x) {  // later chunks of this block (frames of more than 1024 chunks)
-            pre = 0;
-            for (int i = threadIdx.x; i < c; i += kBlock) pre += ccnt[i];
-            pre = block_sum(pre, sh);
+        if (c != (int)blockIdx.x) {  // later chunks of this block: add the chunks since its previous one
+            int add = 0;
+            for (int i = c - (int)gridDim.x + threadIdx.x; i < c; i += kBlock) add += ccnt[i];
+            pre += block_sum(add, sh);
         }
         // survivors before chunk c: every chunk before it is full
         const int before = c * kRefitChunk - pre;
