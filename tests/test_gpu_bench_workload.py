@@ -3,7 +3,9 @@
 32 frames of the 640x480 straight staircase (frames 0..31, their own frame
 ids) in one HIP-graph batch with the tuning 6,4,4,4 (register-resident
 diffusion, 16 rows a wave, 4 iterations a pass; the culled scorer), replayed
-twice.  Checks:
+twice, and once more with 6,4,4,3 (4096 instead of 8192 points a scoring
+block), the autotuner's two picks on this workload; all three runs bitwise
+equal.  Checks:
   - every frame: diffused depth within 1e-3 mm of the oracle's, points within
     1e-6 m of the oracle's back-projection of that depth, and the invariants of
     sequential removal in float64 (Alg. 2): a pixel labelled r lies within t of
@@ -26,8 +28,15 @@ from test_gpu_parity import _follow
 pytestmark = pytest.mark.gpu
 
 BENCH_TUNING = (6, 4, 4, 4)
+ALT_TUNING = (6, 4, 4, 3)
 N_FRAMES = 32
 SAMPLED = (0, 13, 31)
+
+
+def _planes_equal(pa, pb):
+    return len(pa) == len(pb) and all(
+        np.array_equal(a["n"], b["n"]) and a["d"] == b["d"] and np.array_equal(a["centroid"], b["centroid"])
+        and a["inliers"] == b["inliers"] and a["hyp_index"] == b["hyp_index"] for a, b in zip(pa, pb))
 
 
 @pytest.fixture(scope="module")
@@ -64,10 +73,25 @@ def batch(pp):
                            planes=pp.planes_to_numpy(fo.planes, int(fo.n_planes.cpu().item())))
                       for fo in outs])
     ctx.close()
-    for a, b in zip(snaps[0], snaps[1]):
-        for key in ("depth_mm", "points", "normals", "valid", "labels"):
-            assert np.array_equal(a[key], b[key]), key
-        assert a["n"] == b["n"]
+    # the autotuner's other pick on this workload: 4096 instead of 8192 points a scoring block
+    ctx = pp.Context(0)
+    ctx.set_tuning(*ALT_TUNING)
+    for fo in outs:
+        for t in (fo.depth_mm, fo.points, fo.normals, fo.planes, fo.labels):
+            t.zero_()
+    pp.batch_run(outs, graph=True, ctx=ctx)
+    torch.cuda.synchronize()
+    snaps.append([dict(depth_mm=fo.depth_mm.cpu().numpy(), points=fo.points.cpu().numpy(),
+                       normals=fo.normals.cpu().numpy(), valid=fo.valid.cpu().numpy(),
+                       labels=fo.labels.cpu().numpy(), n=int(fo.n_planes.cpu().item()),
+                       planes=pp.planes_to_numpy(fo.planes, int(fo.n_planes.cpu().item())))
+                  for fo in outs])
+    ctx.close()
+    for other in snaps[1:]:
+        for a, b in zip(snaps[0], other):
+            for key in ("depth_mm", "points", "normals", "valid", "labels"):
+                assert np.array_equal(a[key], b[key]), key
+            assert a["n"] == b["n"] and _planes_equal(a["planes"], b["planes"])
     return frames, snaps[1], rcs
 
 
@@ -93,8 +117,4 @@ def test_sampled_frames_equal_the_plain_path_that_follows_the_oracle(pp, orc, ba
     b = res[k]
     for key in ("depth_mm", "points", "normals", "valid", "labels"):
         assert np.array_equal(b[key], g[key]), (k, key)
-    assert b["n"] == g["n_planes"]
-    for pb, pg in zip(b["planes"], g["planes"]):
-        assert np.array_equal(pb["n"], pg["n"]) and pb["d"] == pg["d"]
-        assert np.array_equal(pb["centroid"], pg["centroid"])
-        assert pb["inliers"] == pg["inliers"] and pb["hyp_index"] == pg["hyp_index"]
+    assert b["n"] == g["n_planes"] and _planes_equal(b["planes"], g["planes"])
