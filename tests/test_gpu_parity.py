@@ -235,6 +235,16 @@ def test_ransac_follow_mode_spiral_mixed_size(pp, orc):
     _follow(pp, orc, f, 3, 0, hyps=512)
 
 
+def test_ransac_follow_mode_1280x720(pp, orc):
+    """The 720p frames of the large-batch workload: 4096 hypotheses a round,
+    921600 pixels, every round followed."""
+    log("ransac follow mode cfg=4 k=0 (1280x720, 4096 hypotheses)")
+    f = scenes.make_frame(4, 0)
+    assert f.depth.shape == (720, 1280)
+    g = _follow(pp, orc, f, 4, 0)
+    assert g["n_planes"] >= 6
+
+
 def test_ransac_few_hypotheses_and_one_plane(pp, orc):
     f = scenes.make_frame(1, 3)
     _follow(pp, orc, f, 1, 3, hyps=1, max_planes=1)
