@@ -1,0 +1,54 @@
+"""Host-side parts of the benchmark's contract, on the CPU: more than one GPU
+is refused before any GPU is touched, the kernel-source hash that ties the
+stored HBM-traffic figures to the code ignores comments and white space but
+not code, and stored traffic is reported only for the matching hash."""
+import json
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+KERNELS = os.path.join("paper_2411_01919_amd", "csrc", "pp_kernels.hip")
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_more_than_one_gpu_is_refused(n):
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and p.stdout == ""
+
+
+def _tree(tmp_path, text):
+    d = tmp_path / os.path.dirname(KERNELS)
+    d.mkdir(parents=True, exist_ok=True)
+    (tmp_path / KERNELS).write_text(text, encoding="utf-8")
+    return str(tmp_path)
+
+
+def test_source_hash_ignores_comments_and_white_space_only(tmp_path, monkeypatch):
+    src = open(os.path.join(ROOT, KERNELS), encoding="utf-8").read()
+    base = bench.source_hash()
+    monkeypatch.setattr(bench, "ROOT", _tree(tmp_path / "a", "// a new comment\n" + src.replace("\n", "\n\n  ")
+                                             + "\n/* block\n comment */\n"))
+    assert bench.source_hash() == base
+    monkeypatch.setattr(bench, "ROOT", _tree(tmp_path / "b", src.replace("kBoxTilesPerWave = 4", "kBoxTilesPerWave = 2")))
+    assert bench.source_hash() != base
+
+
+def test_stored_traffic_only_for_its_own_kernel_source(tmp_path, monkeypatch):
+    stored = json.load(open(os.path.join(ROOT, "profiles", "score_traffic.json")))
+    h = stored["kernel_source_hash"]
+    assert bench.load_traffic(h) == stored["bytes_per_launch"] > 0
+    assert bench.load_traffic("0" * 16) is None
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))  # no profiles at all
+    assert bench.load_traffic(h) is None
+    (tmp_path / "profiles").mkdir()
+    shutil.copy(os.path.join(ROOT, "profiles", "score_traffic.json"), tmp_path / "profiles")
+    assert bench.load_traffic(h) == stored["bytes_per_launch"]
