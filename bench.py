@@ -135,7 +135,7 @@ def cpu_baseline(frames, cfg, budget_s=12.0, max_frames=2048):
                       f"the float64 oracle (diffusion, normals, sequential RANSAC), {dt:.1f} s"}
 
 
-def served_bench(pp, duration_s=20.0, seed=5):
+def served_bench(pp, duration_s=20.0, seed=5, lanes=4):
     """Eight simulated cameras (3x 424x240, 3x 640x480, 2x 1280x720) at 30 Hz
     with Poisson arrivals and 3x bursts (1 s in every 5 s), straight and
     spiral stair scenes alternating, through the server under an 8 GB budget;
@@ -148,7 +148,7 @@ def served_bench(pp, duration_s=20.0, seed=5):
     pools = {}
     for sid, (w, h) in enumerate(cams):
         pools[sid] = [scenes.make_frame(5, 10 * sid + i, size=(w, h)) for i in range(3)]
-    srv = pp.Server(hbm_budget_bytes=8 << 30, max_batch=32, lanes=2, staging_frames=256, use_graphs=True)
+    srv = pp.Server(hbm_budget_bytes=8 << 30, max_batch=32, lanes=lanes, staging_frames=256, use_graphs=True)
     for sid, (w, h) in enumerate(cams):
         f0 = pools[sid][0]
         dc = pp.DiffuseConfig(cfg.diffuse_iters, cfg.lam, cfg.kappa_mm)
@@ -212,7 +212,7 @@ def served_bench(pp, duration_s=20.0, seed=5):
     st = srv.stats()
     all_lat = np.concatenate([np.array(v) for v in lat.values()]) if lat else np.zeros(1)
     res = {"cameras": "3x424x240 + 3x640x480 + 2x1280x720 at 30 Hz, Poisson, 3x bursts 1 s in 5 s",
-           "seconds": round(duration_s, 1), "offered_frames": len(arrivals), "completed": done,
+           "lanes": lanes, "seconds": round(duration_s, 1), "offered_frames": len(arrivals), "completed": done,
            "rejected": rejected[0], "frames_per_s": round(done / wall, 2),
            "p50_ms": round(float(np.percentile(all_lat, 50)), 3), "p99_ms": round(float(np.percentile(all_lat, 99)), 3),
            "mean_batch": round((st["launches"] - base["launches"]) and
@@ -377,6 +377,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--served-seconds", type=float, default=20.0, help="0 skips the served leg")
+    ap.add_argument("--served-lanes", type=int, default=4, help="concurrent batches (streams) of the server, 1 to 4")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--c4", action="store_true", help="add the precision-form leg (two batches of 256 large frames)")
     ap.add_argument("--tuning", type=str, default="", help="tile,T,hb,chunk (1-based knobs) instead of autotuning")
@@ -515,7 +516,7 @@ def main():
     served = None
     if args.served_seconds > 0:
         log(f"served leg: {args.served_seconds:.0f} s of simulated cameras")
-        served = served_bench(pp, args.served_seconds)
+        served = served_bench(pp, args.served_seconds, lanes=args.served_lanes)
         log(f"served: {served}")
 
     precision = None

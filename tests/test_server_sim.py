@@ -43,6 +43,14 @@ def _drain(s, tickets, sid=0, timeout_s=10.0):
     return out
 
 
+def _wait_launches(s, n, timeout_s=5.0):
+    """Until the scheduler has started n batches (a launch is counted when it starts)."""
+    t_end = time.time() + timeout_s
+    while s.stats()["launches"] < n and time.time() < t_end:
+        time.sleep(0.0005)
+    assert s.stats()["launches"] == n
+
+
 def _frame_bytes():
     # one frame's arena block (inputs, outputs, scratch); read back from the stats of a lone frame
     s = _server()
@@ -96,7 +104,7 @@ def test_close_cancels_queued_frames_and_lets_launched_ones_finish():
     s = _server(hbm_budget_bytes=fb + fb // 2, lanes=1, max_batch=1, dry_run_us=100000)
     _open(s)
     ts = [s.submit(0, _frame(k), k) for k in range(4)]
-    time.sleep(0.02)  # the first frame is launched, the others wait for memory
+    _wait_launches(s, 1)  # the first frame is launched, the others wait for memory
     s.close_stream(0)
     with pytest.raises(pp.PPError) as e:
         s.submit(0, _frame(), 99)
@@ -115,7 +123,7 @@ def test_frames_arriving_during_a_batch_start_on_another_lane():
     s = _server(lanes=2, dry_run_us=100000)
     _open(s)
     t0 = s.submit(0, _frame(0), 0)
-    time.sleep(0.02)  # lane 0 is busy with frame 0
+    _wait_launches(s, 1)  # lane 0 is busy with frame 0
     t1 = s.submit(0, _frame(1), 1)
     r1 = s.poll(t1, 0, timeout_us=1_000_000, labels=False)
     r0 = s.poll(t0, 0, timeout_us=1_000_000, labels=False)
@@ -127,11 +135,13 @@ def test_frames_arriving_during_a_batch_start_on_another_lane():
 
 
 def test_frames_waiting_together_share_a_batch():
-    s = _server(lanes=1, dry_run_us=60000, max_batch=16)
+    s = _server(lanes=1, dry_run_us=200000, max_batch=16)
     _open(s)
-    t0 = s.submit(0, _frame(0), 0)
-    time.sleep(0.01)
-    ts = [s.submit(0, _frame(k), k) for k in range(1, 9)]
+    frames = [_frame(k) for k in range(9)]
+    t0 = s.submit(0, frames[0], 0)
+    # frame 0's batch holds the only lane; the rest queue behind it and leave together
+    _wait_launches(s, 1)
+    ts = [s.submit(0, frames[k], k) for k in range(1, 9)]
     _drain(s, [t0] + ts)
     st = s.stats()
     assert st["launches"] == 2 and abs(st["mean_batch"] - 4.5) < 1e-9
