@@ -552,7 +552,7 @@ class Server:
     results come back through poll().  dry_run_us > 0 exercises admission and
     scheduling without touching a GPU (no planes are computed)."""
 
-    def __init__(self, hbm_budget_bytes: int = 8 << 30, max_batch: int = 32, lanes: int = 2,
+    def __init__(self, hbm_budget_bytes: int = 8 << 30, max_batch: int = 32, lanes: int = 4,
                  staging_frames: int = 64, use_graphs: bool = True, device: int = 0, dry_run_us: int = 0):
         cfg = N.ServerCfg(int(device), int(hbm_budget_bytes), int(max_batch), int(lanes), int(staging_frames),
                           1 if use_graphs else 0, int(dry_run_us))
