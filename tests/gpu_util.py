@@ -58,13 +58,18 @@ def run_plain(frame, dc, rc, ctx=None):
 
 
 def hyp_eps(planes_or, triples, L, P, pmax):
-    """Band inside which an FP32 hypothesis residual may legitimately sit on
-    the other side of t than the float64 one: FP32 rounding of the three
-    points' differences, of the cross product (amplified by the triple's
-    conditioning 1/sin(angle) and lever arm pmax/|e|), and of the canonical
-    residual evaluation."""
+    """Derived bound on how far the residual implied by an FP32 hypothesis
+    plane may sit from the float64 plane through the same three FP32 points,
+    anywhere within |p| <= pmax.  With u = 2^-24 and exact inputs:
+    e = fl(p1 - p0) is off by u|e| per component; each component of
+    m = e1 x e2 (two products and a difference) by at most
+    5u (|e1a e2b| + |e1b e2a|), so |dm| <= 15u |e1||e2|; normalising adds 5u,
+    so |n32 - n| <= 30u cond + 5u with cond = |e1||e2| / |e1 x e2| = 1/sin;
+    d = -fl(n.p0) adds 3u |p0|.  At a point p the residuals then differ by at
+    most |n32 - n| (|p| + |p0|) + |d32 - d| <=
+    u ((30 cond + 5)(pmax + |p0|) + 4 |p0|)."""
     X = P.reshape(3, -1)
-    eps = np.full(len(planes_or), 1e-6)
+    eps = np.full(len(planes_or), 0.0)
     for j, t in enumerate(triples):
         if t[0] < 0:
             continue
@@ -75,9 +80,50 @@ def hyp_eps(planes_or, triples, L, P, pmax):
         if m <= 0 or l1 <= 0 or l2 <= 0:
             continue
         cond = l1 * l2 / m
-        lever = pmax / min(l1, l2)
-        eps[j] = 1e-6 + 64 * EPS32 * (pmax + abs(planes_or[j, 3])) * (1.0 + lever * cond)
+        n0 = np.linalg.norm(p0)
+        eps[j] = EPS32 * ((30.0 * cond + 5.0) * (pmax + n0) + 4.0 * n0)
     return eps
+
+
+def score_margin(hyps32, p1max):
+    """Band around t inside which the canonical FP32 residual
+    fmaf(nx, x, fmaf(ny, y, fmaf(nz, z, d))) may fall on the other side of t
+    than the exact residual of the same FP32 plane: three roundings, each at
+    most u (|d| + |x|+|y|+|z|) since |n_i| <= 1; 16u (P1 + |d|) is the margin
+    the culled scorer itself keeps (P1 = max |x|+|y|+|z| over the frame)."""
+    d = np.abs(np.nan_to_num(np.asarray(hyps32, np.float64)[:, 3]))
+    return 16.0 * EPS32 * (p1max + d)
+
+
+def labels_explained(P_g, P_o, lab_g, lab_o, planes_g, planes_o, t, band=1e-6):
+    """Free-running labels against the oracle's (R20): every pixel whose
+    label differs must be near t for the plane of the first round that
+    claimed it on either side, k = min(lab_g, lab_o): its oracle residual
+    (oracle plane k, oracle point) within `band` of t, or on the other side
+    of t from the GPU's residual (GPU plane k, GPU point) -- the two sides'
+    planes and points are both legitimate and agree to their own tolerances
+    (planes 1e-6 relative, points 2e-6 m), so between them they may split a
+    pixel lying that close to t.  Returns (number of differing pixels,
+    largest band used)."""
+    Xg = np.asarray(P_g, np.float64).reshape(3, -1)
+    Xo = np.asarray(P_o, np.float64).reshape(3, -1)
+    lg = np.asarray(lab_g).reshape(-1).astype(np.int64)
+    lo = np.asarray(lab_o).reshape(-1).astype(np.int64)
+    diff = np.flatnonzero(lg != lo)
+    if diff.size == 0:
+        return 0, 0.0
+    big = 1 << 20
+    k = np.minimum(np.where(lg[diff] >= 0, lg[diff], big), np.where(lo[diff] >= 0, lo[diff], big))
+    assert np.all(k < min(len(planes_g), len(planes_o))), "a differing pixel lies beyond the common planes"
+    used = 0.0
+    for i, kk in zip(diff, k):
+        po, pg = np.asarray(planes_o[kk], np.float64), np.asarray(planes_g[kk], np.float64)
+        ro = abs(po[:3] @ Xo[:, i] + po[3])
+        rg = abs(pg[:3] @ Xg[:, i] + pg[3])
+        allow = band + abs(rg - ro)
+        assert abs(ro - t) <= allow, (int(i), int(kk), ro, rg)
+        used = max(used, allow)
+    return int(diff.size), used
 
 
 def check_removal(points, labels, valid, planes, t, min_inliers, hyps, band=1e-6):

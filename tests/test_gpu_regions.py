@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import scenes
-from gpu_util import hyp_eps, log
+from gpu_util import EPS32, hyp_eps, log
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +62,9 @@ def _check(orc, P32, valid, region, R, hyps, seed, frame_id, got, t=0.01):
     eps = np.zeros((R, hyps))
     for g in range(R):
         L = np.nonzero((flat_v & 1).astype(bool) & (flat_r == g))[0]
-        eps[g] = hyp_eps(ref0.planes[g], ref0.triples[g], L, P, pmax)
+        # plane bound plus the canonical FP32 residual's own rounding, 16u (P1 + |d|)
+        eps[g] = hyp_eps(ref0.planes[g], ref0.triples[g], L, P, pmax) + \
+            16.0 * EPS32 * (pmax + np.abs(np.nan_to_num(ref0.planes[g][:, 3])))
     ref = orc.ransac_regions(P, valid, region, R, prm, eps=eps)
     hv = ~np.isnan(got["hyps"][..., 3])
     assert np.array_equal(hv, ref.hvalid)

@@ -410,3 +410,51 @@ def test_removal_invariants_hold_on_the_oracle_and_fail_on_planted_mistakes(orc)
             lab.reshape(-1)[i] = v
         with pytest.raises(AssertionError):
             check_removal(P, lab, valid, planes, *args, band=1e-12)
+
+
+def test_label_comparison_explains_only_near_threshold_differences(orc):
+    """The free-running label check of the GPU tests (R20): on the oracle's
+    own result against itself nothing differs; a pixel relabelled far from t
+    is caught; a pixel that a second, slightly shifted plane puts on the
+    other side of t is explained by that shift and caught without it; a
+    pixel beyond the common planes is caught."""
+    from gpu_util import labels_explained
+    f = scenes.make_frame(1, 1)
+    cfg = scenes.CONFIGS[1]
+    H, W = f.depth.shape
+    prm = orc.RansacParams(hyps=cfg.hyps, max_planes=cfg.max_planes, min_inliers=cfg.min_inliers(W, H),
+                           thresh=cfg.thresh_m, seed=cfg.ransac_seed, frame=1)
+    I = orc.diffuse(f.depth, cfg.diffuse_iters, cfg.lam, cfg.kappa_mm)
+    P, valid = orc.backproject(I, f.K)
+    rr = orc.ransac(P, valid, prm)
+    t = prm.thresh
+    planes = [rr.planes[r].copy() for r in range(rr.n_planes)]
+    assert labels_explained(P, P, rr.labels, rr.labels, planes, planes, t) == (0, 0.0)
+    X = P.reshape(3, -1)
+    flat = rr.labels.reshape(-1)
+    r0 = np.abs(planes[0][:3] @ X + planes[0][3])
+    # far from t: relabelled as unassigned
+    far = np.flatnonzero((flat == 0) & (r0 < 0.5 * t))[0]
+    lab = rr.labels.copy()
+    lab.reshape(-1)[far] = -1
+    with pytest.raises(AssertionError):
+        labels_explained(P, P, lab, rr.labels, planes, planes, t)
+    # the inlier of plane 0 closest to t, pushed out by a shifted plane 0
+    mine = np.flatnonzero(flat == 0)
+    edge = mine[np.argmax(r0[mine])]
+    gap = t - r0[edge]
+    assert gap > 1e-6
+    shifted = [p.copy() for p in planes]
+    side = np.sign(planes[0][:3] @ X[:, edge] + planes[0][3])
+    shifted[0][3] += side * 2 * gap
+    lab = rr.labels.copy()
+    lab.reshape(-1)[edge] = -1
+    n, used = labels_explained(P, P, lab, rr.labels, shifted, planes, t)
+    assert n == 1 and used >= gap
+    with pytest.raises(AssertionError):
+        labels_explained(P, P, lab, rr.labels, planes, planes, t)
+    # a label no common plane explains
+    lab = rr.labels.copy()
+    lab.reshape(-1)[far] = rr.n_planes
+    with pytest.raises(AssertionError):
+        labels_explained(P, P, lab, rr.labels, planes, planes, t)
