@@ -135,11 +135,15 @@ def cpu_baseline(frames, cfg, budget_s=12.0, max_frames=2048):
                       f"the float64 oracle (diffusion, normals, sequential RANSAC), {dt:.1f} s"}
 
 
-def served_bench(pp, duration_s=20.0, seed=5, lanes=4):
+def served_bench(pp, duration_s=60.0, seed=5, lanes=4, sweep=(2, 4, 8, 16, 32), sweep_s=5.0):
     """Eight simulated cameras (3x 424x240, 3x 640x480, 2x 1280x720) at 30 Hz
     with Poisson arrivals and 3x bursts (1 s in every 5 s), straight and
-    spiral stair scenes alternating, through the server under an 8 GB budget;
-    then a closed-loop saturation run of the three 640x480 cameras."""
+    spiral stair scenes alternating, through the server under an 8 GB budget
+    for duration_s; then the same cameras with every rate multiplied by each
+    factor of `sweep` for sweep_s each (open loop: offered vs completed
+    frames/s, p50/p99), and a closed-loop saturation run of the three
+    640x480 cameras.  Latency is the server's own, from pp_submit to the
+    results on the host."""
     import threading
 
     import scenes
@@ -159,68 +163,89 @@ def served_bench(pp, duration_s=20.0, seed=5, lanes=4):
     for sid, t in enumerate(warm):
         while srv.poll(t, sid, timeout_us=100000, labels=False) is None:
             pass
-    rng = np.random.default_rng(seed)
-    arrivals = []
-    for sid in range(len(cams)):
-        t = 0.0
-        while t < duration_s:
-            rate = 90.0 if (t % 5.0) < 1.0 else 30.0
-            t += rng.exponential(1.0 / rate)
-            if t < duration_s:
-                arrivals.append((t, sid))
-    arrivals.sort()
-    outstanding = []
-    lock = threading.Lock()
-    rejected = [0]
+    fid = [1]
 
-    def submitter():
-        t0 = time.perf_counter()
-        for i, (ta, sid) in enumerate(arrivals):
-            dt = ta - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            tk = srv.try_submit(sid, pools[sid][i % 3].depth, i)
-            with lock:
-                if tk is None:
-                    rejected[0] += 1
-                else:
-                    outstanding.append((tk, sid))
+    def open_loop(seconds, mult, rseed):
+        rng = np.random.default_rng(rseed)
+        arrivals = []
+        for sid in range(len(cams)):
+            t = 0.0
+            while t < seconds:
+                rate = (90.0 if (t % 5.0) < 1.0 else 30.0) * mult
+                t += rng.exponential(1.0 / rate)
+                if t < seconds:
+                    arrivals.append((t, sid))
+        arrivals.sort()
+        outstanding = []
+        lock = threading.Lock()
+        rejected = [0]
 
-    th = threading.Thread(target=submitter)
-    base = srv.stats()
-    th.start()
-    lat = {}
-    done = 0
-    t_start = time.perf_counter()
-    while th.is_alive() or outstanding:
-        with lock:
-            cur = list(outstanding)
-        if not cur:
-            time.sleep(0.001)
-            continue
-        for tk, sid in cur:
-            r = srv.poll(tk, sid, timeout_us=200, labels=False)
-            if r is not None:
-                lat.setdefault(cams[sid], []).append(r["latency_us"] / 1e3)
-                done += 1
+        def submitter():
+            t0 = time.perf_counter()
+            for i, (ta, sid) in enumerate(arrivals):
+                dt = ta - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tk = srv.try_submit(sid, pools[sid][i % 3].depth, fid[0] + i)
                 with lock:
-                    outstanding.remove((tk, sid))
-        if time.perf_counter() - t_start > duration_s + 60:
-            break
-    th.join()
-    wall = time.perf_counter() - t_start
-    st = srv.stats()
-    all_lat = np.concatenate([np.array(v) for v in lat.values()]) if lat else np.zeros(1)
-    res = {"cameras": "3x424x240 + 3x640x480 + 2x1280x720 at 30 Hz, Poisson, 3x bursts 1 s in 5 s",
-           "lanes": lanes, "seconds": round(duration_s, 1), "offered_frames": len(arrivals), "completed": done,
-           "rejected": rejected[0], "frames_per_s": round(done / wall, 2),
-           "p50_ms": round(float(np.percentile(all_lat, 50)), 3), "p99_ms": round(float(np.percentile(all_lat, 99)), 3),
-           "mean_batch": round((st["launches"] - base["launches"]) and
-                               (st["completed"] - base["completed"]) / (st["launches"] - base["launches"]), 2),
-           "hbm_peak_mib": st["hbm_peak"] >> 20}
-    for (w, h), v in sorted(lat.items()):
-        res[f"p50_ms_{w}x{h}"] = round(float(np.percentile(v, 50)), 3)
-        res[f"p99_ms_{w}x{h}"] = round(float(np.percentile(v, 99)), 3)
+                    if tk is None:
+                        rejected[0] += 1
+                    else:
+                        outstanding.append((tk, sid))
+
+        th = threading.Thread(target=submitter)
+        base = srv.stats()
+        th.start()
+        lat = {}
+        done = 0
+        t_start = time.perf_counter()
+        while th.is_alive() or outstanding:
+            with lock:
+                cur = list(outstanding)
+            if not cur:
+                time.sleep(0.0005)
+                continue
+            got = 0
+            for tk, sid in cur:
+                r = srv.poll(tk, sid, timeout_us=0, labels=False)
+                if r is not None:
+                    got += 1
+                    lat.setdefault(cams[sid], []).append(r["latency_us"] / 1e3)
+                    done += 1
+                    with lock:
+                        outstanding.remove((tk, sid))
+            if not got:
+                time.sleep(0.0002)
+            if time.perf_counter() - t_start > seconds + 60:
+                break
+        th.join()
+        fid[0] += len(arrivals)
+        wall = time.perf_counter() - t_start
+        st = srv.stats()
+        all_lat = np.concatenate([np.array(v) for v in lat.values()]) if lat else np.zeros(1)
+        res = {"seconds": round(seconds, 1), "rate_multiplier": mult, "offered_frames": len(arrivals),
+               "offered_frames_per_s": round(len(arrivals) / seconds, 1), "completed": done,
+               "rejected": rejected[0], "frames_per_s": round(done / wall, 2),
+               "p50_ms": round(float(np.percentile(all_lat, 50)), 3),
+               "p99_ms": round(float(np.percentile(all_lat, 99)), 3),
+               "mean_batch": round((st["launches"] - base["launches"]) and
+                                   (st["completed"] - base["completed"]) / (st["launches"] - base["launches"]), 2),
+               "hbm_peak_mib": st["hbm_peak"] >> 20}
+        for (w, h), v in sorted(lat.items()):
+            res[f"p50_ms_{w}x{h}"] = round(float(np.percentile(v, 50)), 3)
+            res[f"p99_ms_{w}x{h}"] = round(float(np.percentile(v, 99)), 3)
+        return res
+
+    res = open_loop(duration_s, 1, seed)
+    res["cameras"] = "3x424x240 + 3x640x480 + 2x1280x720 at 30 Hz, Poisson, 3x bursts 1 s in 5 s"
+    res["lanes"] = lanes
+    log(f"served (nominal rate): {res}")
+    res["rate_sweep"] = []
+    for i, m in enumerate(sweep):
+        r = open_loop(sweep_s, m, seed + 1 + i)
+        log(f"served x{m}: {r}")
+        res["rate_sweep"].append({k: r[k] for k in ("rate_multiplier", "offered_frames_per_s", "frames_per_s",
+                                                    "rejected", "p50_ms", "p99_ms", "mean_batch")})
     # saturation: keep 64 frames in flight on each 640x480 camera for 4 s
     sids = [3, 4, 5]
     inflight = {sid: [] for sid in sids}
@@ -229,7 +254,7 @@ def served_bench(pp, duration_s=20.0, seed=5, lanes=4):
     while time.perf_counter() - t0 < 4.0:
         for sid in sids:
             while len(inflight[sid]) < 64:
-                inflight[sid].append(srv.submit(sid, pools[sid][k % 3].depth, 100000 + k))
+                inflight[sid].append(srv.submit(sid, pools[sid][k % 3].depth, 10 ** 7 + k))
                 k += 1
             keep = []
             for tk in inflight[sid]:
@@ -325,6 +350,67 @@ def precision_bench(pp, reps=3):
     return out
 
 
+def ragged_bench(pp, steps=20, warmup=3, n_frames=64):
+    """The ragged-batch workload: 64 frames of the spiral staircase along a
+    seeded random-walk pose, cycling 424x240 / 640x480 / 848x480 (22/21/21),
+    1024 hypotheses, as ONE graph-replayed batch per step at the tuning the
+    autotuner picks for this layout; beside it the plain per-frame path
+    (pp_diffuse, pp_normals, pp_ransac_planes) over the same frames, and a
+    bitwise comparison of the two forms' labels and planes on every frame."""
+    import torch
+
+    import scenes
+    from paper_2411_01919_amd import autotune
+    cfg = scenes.CONFIGS[3]
+    frames = [scenes.make_frame(3, k) for k in range(n_frames)]
+    outs, plain_outs = [], []
+    for f in frames:
+        H, W = f.depth.shape
+        d = torch.from_numpy(f.depth.view(np.int16)).to("cuda:0")
+        dc = pp.DiffuseConfig(cfg.diffuse_iters, cfg.lam, cfg.kappa_mm)
+        rc = pp.RansacConfig(cfg.max_planes, cfg.hyps, cfg.min_inliers(W, H), cfg.thresh_m, cfg.ransac_seed,
+                             f.meta["k"])
+        K = (f.K.fx, f.K.fy, f.K.cx, f.K.cy)
+        outs.append(pp.make_outputs(d, K, dc, rc))
+        plain_outs.append(pp.make_outputs(d, K, dc, rc))
+    px = sum(f.depth.size for f in frames)
+    ctx = pp.Context(0)
+    tun = autotune.tune(outs, ctx=ctx, log=log)
+    for _ in range(warmup):
+        pp.batch_run(outs, graph=True, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pp.batch_run(outs, graph=True, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fps = n_frames * steps / dt
+    # the plain path over the same frames, one frame after another
+    for fo in plain_outs[:3]:
+        pp.run_frame(fo, ctx=ctx)
+    torch.cuda.synchronize()
+    reps = max(1, steps // 4)
+    a = time.perf_counter()
+    for _ in range(reps):
+        for fo in plain_outs:
+            pp.run_frame(fo, ctx=ctx)
+    torch.cuda.synchronize()
+    plain_fps = n_frames * reps / (time.perf_counter() - a)
+    same = all(int(a.n_planes.cpu().item()) == int(b.n_planes.cpu().item())
+               and torch.equal(a.labels, b.labels)
+               and torch.equal(a.planes[:64 * int(a.n_planes.cpu().item())], b.planes[:64 * int(b.n_planes.cpu().item())])
+               for a, b in zip(outs, plain_outs))
+    ctx.close()
+    rec = {"workload": "64 spiral-staircase frames (22 x 424x240, 21 x 640x480, 21 x 848x480), random-walk poses, "
+                       "20 diffusion iterations, up to 12 planes x 1024 hypotheses, one HIP graph replay per step",
+           "frames_per_s": round(fps, 2), "mpixel_per_s": round(fps * px / n_frames / 1e6, 2),
+           "ms_per_step": round(dt * 1e3 / steps, 3), "steps": steps,
+           "plain_frames_per_s": round(plain_fps, 2), "speedup_vs_plain": round(fps / plain_fps, 2),
+           "identical_to_plain": bool(same),
+           "tuning": {k: tun[k] for k in ("diffuse_tile", "diffuse_t", "score_hb", "score_chunk")}}
+    return rec
+
+
 def paper_chain_bench(pp, n_frames=24):
     """The paper's own per-frame chain at 640x480, one frame at a time with the
     depth resident on the device: diffusion, normals, segmentation of the
@@ -373,16 +459,19 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=32, help="frames per step")
-    ap.add_argument("--plain-frames", type=int, default=24)
+    ap.add_argument("--plain-frames", type=int, default=1000, help="frames per repeat of the plain path")
+    ap.add_argument("--plain-repeats", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--served-seconds", type=float, default=20.0, help="0 skips the served leg")
+    ap.add_argument("--served-seconds", type=float, default=60.0, help="0 skips the served leg")
+    ap.add_argument("--served-sweep-seconds", type=float, default=5.0, help="seconds per rate multiplier")
     ap.add_argument("--served-lanes", type=int, default=4, help="concurrent batches (streams) of the server, 1 to 4")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--c4", action="store_true", help="add the precision-form leg (two batches of 256 large frames)")
     ap.add_argument("--tuning", type=str, default="", help="tile,T,hb,chunk (1-based knobs) instead of autotuning")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mfma_f32", "bf16", "fp16"],
                     help="scoring form of the batched and plain legs (all give identical results)")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the 64-frame ragged spiral batch")
     ap.add_argument("--no-chain", action="store_true", help="skip the paper-chain leg (segmentation, region RANSAC, map)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy (reference for HBM byte counters) and exit")
@@ -493,30 +582,44 @@ def main():
     # ---------------------------------------------------------------- plain per-frame path
     plain = None
     if not args.no_plain:
-        nf = min(args.plain_frames, len(outs))
-        for fo in outs[:2]:
+        # 5 repeats of >= 1000 frames each (the batch's frames cycled): per-frame latency from the first
+        # enqueue to the stream reaching the end of pp_ransac_planes, then throughput with no waits between
+        # frames; the medians of the repeats are reported
+        nf = max(args.plain_frames, 1)
+        for fo in outs[:4]:
             pp.run_frame(fo, ctx=ctx)
         torch.cuda.synchronize()
-        lat = []
-        for i in range(nf):
+        p50s, p99s, fpss = [], [], []
+        for rep in range(args.plain_repeats):
+            lat = np.empty(nf)
+            for i in range(nf):
+                a = time.perf_counter()
+                pp.run_frame(outs[i % len(outs)], ctx=ctx)
+                stream.synchronize()
+                lat[i] = (time.perf_counter() - a) * 1e3
             a = time.perf_counter()
-            pp.run_frame(outs[i], ctx=ctx)
-            stream.synchronize()
-            lat.append((time.perf_counter() - a) * 1e3)
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        for i in range(nf):
-            pp.run_frame(outs[i], ctx=ctx)
-        torch.cuda.synchronize()
-        plain_fps = nf / (time.perf_counter() - a)
-        plain = {"frames_per_s": round(plain_fps, 2), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                 "p99_ms": round(float(np.percentile(lat, 99)), 3), "frames": nf}
+            for i in range(nf):
+                pp.run_frame(outs[i % len(outs)], ctx=ctx)
+            torch.cuda.synchronize()
+            fpss.append(nf / (time.perf_counter() - a))
+            p50s.append(float(np.percentile(lat, 50)))
+            p99s.append(float(np.percentile(lat, 99)))
+        plain = {"frames_per_s": round(float(np.median(fpss)), 2), "p50_ms": round(float(np.median(p50s)), 3),
+                 "p99_ms": round(float(np.median(p99s)), 3), "frames_per_repeat": nf,
+                 "repeats": args.plain_repeats,
+                 "repeat_frames_per_s": [round(v, 1) for v in fpss], "repeat_p99_ms": [round(v, 3) for v in p99s]}
         log(f"plain: {plain}")
+
+    ragged = None
+    if not args.no_ragged:
+        log("ragged-batch leg: 64 spiral frames of three sizes")
+        ragged = ragged_bench(pp, args.steps, args.warmup)
+        log(f"ragged batch: {ragged}")
 
     served = None
     if args.served_seconds > 0:
         log(f"served leg: {args.served_seconds:.0f} s of simulated cameras")
-        served = served_bench(pp, args.served_seconds, lanes=args.served_lanes)
+        served = served_bench(pp, args.served_seconds, lanes=args.served_lanes, sweep_s=args.served_sweep_seconds)
         log(f"served: {served}")
 
     precision = None
@@ -563,6 +666,7 @@ def main():
                    "stage_ms_per_step": {k: round(v / args.steps, 3) for k, v in stage_ms.items()},
                    "planes_per_frame": round(planes_tot / len(outs), 2)},
         "plain": plain,
+        "ragged_batch": ragged,
         "served": served,
         "precision_form": precision,
         "paper_chain": chain,

@@ -34,7 +34,14 @@
  *    poisons the context: every later call on it returns PP_E_HIP until it is
  *    destroyed.  pp_last_error() describes the last failure.
  *  - A pp_ctx is not thread-safe; use one per thread (or serialise).  It owns
- *    scratch memory that grows to the largest shape seen and is reused.
+ *    scratch memory that grows to the largest shape seen and is reused.  Its
+ *    calls may use different streams: a call on a stream other than the
+ *    previous call's first waits (on the device) for the previous call's
+ *    work, since both use the context's frame tables and scratch; work on
+ *    one context therefore runs in call order.  A stream under the caller's
+ *    graph capture is not ordered this way: the caller orders its graph.
+ *    Graphs captured by pp_batch_run are kept per batch layout, at most 64
+ *    (the least recently used is destroyed once its last launch is done).
  */
 #ifndef PP_H
 #define PP_H
@@ -395,6 +402,8 @@ typedef struct {
     int32_t use_graphs;         /* 1: replay cached HIP graphs per batch layout; 0: eager launches */
     int32_t dry_run_us;         /* > 0: no GPU is touched; each batch "completes" after this many us
                                    with no planes -- exercises admission and scheduling only */
+    int32_t dry_run_fail_batch; /* dry run only: the n-th launched batch (1-based) ends as a failed
+                                   HIP batch would, poisoning the server; 0: never */
 } pp_server_cfg;
 
 /* Caller-owned host buffers filled by pp_poll. */
@@ -438,6 +447,13 @@ pp_status pp_submit(pp_server* s, int32_t stream_id, const uint16_t* depth_host,
  * PP_E_CLOSED if cancelled, PP_E_HIP if its batch failed. */
 pp_status pp_poll(pp_server* s, uint64_t ticket, pp_result* out, int32_t timeout_us);
 pp_status pp_server_stats_get(pp_server* s, pp_server_stats* out);
+/* Clear a server (poisoned or not) for new work: waits for the batches on
+ * the device, fails every frame not yet completed (its poll returns
+ * PP_E_HIP if the server was poisoned, PP_E_CLOSED otherwise), frees their
+ * memory, gives every lane a fresh context, and accepts frames again.  Open
+ * streams stay open; completed results stay pollable.  PP_E_HIP (still
+ * poisoned) if the device cannot take new contexts. */
+pp_status pp_server_reset(pp_server* s);
 
 /* ---------------------------------------------------------------- timing */
 /* Stage timing: while enabled, every launch of the inlier-scoring kernel

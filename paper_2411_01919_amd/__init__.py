@@ -553,9 +553,10 @@ class Server:
     scheduling without touching a GPU (no planes are computed)."""
 
     def __init__(self, hbm_budget_bytes: int = 8 << 30, max_batch: int = 32, lanes: int = 4,
-                 staging_frames: int = 64, use_graphs: bool = True, device: int = 0, dry_run_us: int = 0):
+                 staging_frames: int = 64, use_graphs: bool = True, device: int = 0, dry_run_us: int = 0,
+                 dry_run_fail_batch: int = 0):
         cfg = N.ServerCfg(int(device), int(hbm_budget_bytes), int(max_batch), int(lanes), int(staging_frames),
-                          1 if use_graphs else 0, int(dry_run_us))
+                          1 if use_graphs else 0, int(dry_run_us), int(dry_run_fail_batch))
         h = N.c_vp()
         s = N.lib().pp_server_create(ctypes.byref(cfg), ctypes.byref(h))
         if s != N.PP_OK:
@@ -583,6 +584,10 @@ class Server:
         self._check(N.lib().pp_stream_open(self.h, int(stream_id), _desc(H, W), N.Intrinsics(*[float(x) for x in K]),
                                            ctypes.byref(dp), ctypes.byref(rp)))
         self.streams[stream_id] = (W, H, ransac_cfg.max_planes)
+
+    def reset(self):
+        """pp_server_reset: fail every frame not yet completed and accept work again."""
+        self._check(N.lib().pp_server_reset(self.h))
 
     def close_stream(self, stream_id: int):
         self._check(N.lib().pp_stream_close(self.h, int(stream_id)))

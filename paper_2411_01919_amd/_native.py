@@ -88,7 +88,7 @@ class Tuning(ctypes.Structure):
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("device", c_i32), ("hbm_budget_bytes", c_u64), ("max_batch", c_i32), ("lanes", c_i32),
-                ("staging_frames", c_i32), ("use_graphs", c_i32), ("dry_run_us", c_i32)]
+                ("staging_frames", c_i32), ("use_graphs", c_i32), ("dry_run_us", c_i32), ("dry_run_fail_batch", c_i32)]
 
 
 class Result(ctypes.Structure):
@@ -140,6 +140,7 @@ SIGNATURES = {
     "pp_submit": (c_i32, [c_vp, c_i32, c_vp, c_u64, ctypes.POINTER(c_u64)]),
     "pp_poll": (c_i32, [c_vp, c_u64, ctypes.POINTER(Result), c_i32]),
     "pp_server_stats_get": (c_i32, [c_vp, ctypes.POINTER(ServerStats)]),
+    "pp_server_reset": (c_i32, [c_vp]),
     "pp_stage_time": (c_i32, [c_vp, ctypes.POINTER(c_f32), ctypes.POINTER(c_i32)]),
 }
 

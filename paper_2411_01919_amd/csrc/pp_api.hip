@@ -30,7 +30,13 @@ struct Slot {
 
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // recorded after the latest launch of exec
+    uint64_t last_use = 0;
 };
+
+// Captured graphs kept per context (least recently used ones are destroyed
+// beyond this; a server sees one layout per batch size and frame mix).
+constexpr size_t kMaxGraphs = 64;
 
 }  // namespace
 
@@ -56,6 +62,12 @@ struct pp_ctx {
     int ring_pos = 0;
     hipStream_t capture_stream = nullptr;
     std::map<std::string, GraphEntry> graphs;
+    uint64_t graph_clock = 0;
+    // the stream of the latest enqueue and an event after it: a call on
+    // another stream first waits for it (the frame tables and scratch are shared)
+    hipStream_t last_stream = nullptr;
+    hipEvent_t last_ev = nullptr;
+    bool last_valid = false;
     void* debug_scratch = nullptr;
     size_t debug_scratch_bytes = 0;
     void* region_scratch = nullptr;
@@ -91,6 +103,49 @@ pp_status hip_fail(pp_ctx* c, hipError_t e, const char* where) {
         hipError_t e_ = (call);                                  \
         if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
     } while (0)
+
+// Destroy one captured graph once its latest launch has finished.
+void destroy_graph(GraphEntry& g) {
+    if (g.done) {
+        (void)hipEventSynchronize(g.done);
+        (void)hipEventDestroy(g.done);
+    }
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+    g.done = nullptr;
+}
+
+void drop_graphs(pp_ctx* c) {
+    for (auto& kv : c->graphs) destroy_graph(kv.second);
+    c->graphs.clear();
+}
+
+// Work enqueued on one context's shared tables and scratch stays in order
+// across streams: a call on a stream other than the previous call's waits
+// for the previous call's work first.
+// A stream under the caller's graph capture is left alone (an event
+// recorded there is not a recorded event afterwards): the capturing caller
+// orders its own graph.
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+pp_status order_streams(pp_ctx* c, hipStream_t st) {
+    if (c->last_valid && st != c->last_stream && !capturing(st)) HIPCHK(c, hipStreamWaitEvent(st, c->last_ev, 0));
+    return PP_OK;
+}
+
+pp_status mark_stream(pp_ctx* c, hipStream_t st) {
+    if (capturing(st)) {
+        c->last_valid = false;
+        return PP_OK;
+    }
+    HIPCHK(c, hipEventRecord(c->last_ev, st));
+    c->last_stream = st;
+    c->last_valid = true;
+    return PP_OK;
+}
 
 bool desc_ok(const pp_frame_desc& d) {
     return d.width >= 3 && d.height >= 3 && d.width <= 16384 && d.height <= 16384 && d.pitch_px >= d.width &&
@@ -229,6 +284,8 @@ __global__ void k_force_active(FrameDev* tab) {
 }
 
 pp_status put_plain(pp_ctx* c, const FrameDev& f, hipStream_t s) {
+    pp_status ps = order_streams(c, s);
+    if (ps != PP_OK) return ps;
     hipLaunchKernelGGL(k_set_frame, dim3(1), dim3(1), 0, s, c->plain_tab, f);
     HIPCHK(c, hipGetLastError());
     return PP_OK;
@@ -284,6 +341,7 @@ pp_status pp_ctx_create(int32_t device, pp_ctx** out) {
     if (e == hipSuccess) e = hipMalloc(&c->plain_tab, sizeof(FrameDev));
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
     for (int i = 0; e == hipSuccess && i < pp_ctx::kRing; ++i) e = hipEventCreateWithFlags(&c->staging_ev[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->last_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         g_create_error = std::string("context set-up failed: ") + hipGetErrorString(e);
         pp_ctx_destroy(c);
@@ -297,8 +355,8 @@ pp_status pp_ctx_destroy(pp_ctx* c) {
     if (!c) return PP_E_INVAL;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    for (auto& kv : c->graphs)
-        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    drop_graphs(c);
+    if (c->last_ev) (void)hipEventDestroy(c->last_ev);
     for (auto& s : c->slots)
         if (s.base && !s.external) (void)hipFree(s.base);
     if (c->plain_tab) (void)hipFree(c->plain_tab);
@@ -354,7 +412,7 @@ pp_status pp_set_tuning(pp_ctx* c, const pp_tuning* t) {
         n.score_chunk = t->score_chunk - 1;
     }
     c->tuning = n;
-    c->graphs.clear();  // captured launch shapes change
+    drop_graphs(c);  // captured launch shapes change
     return PP_OK;
 }
 
@@ -437,7 +495,7 @@ pp_status pp_diffuse(pp_ctx* c, const uint16_t* depth_dev, float* out_mm_dev, pp
     hipStream_t st = (hipStream_t)stream;
     if ((s = put_plain(c, f, st)) != PP_OK) return s;
     HIPCHK(c, ppk::launch_diffuse(c->plain_tab, 1, desc.width, desc.height, p->iters, p->scheme, c->tuning, st));
-    return PP_OK;
+    return mark_stream(c, st);
 }
 
 pp_status pp_normals(pp_ctx* c, const float* depth_mm_dev, pp_frame_desc desc, pp_intrinsics K, float* points_dev,
@@ -458,7 +516,7 @@ pp_status pp_normals(pp_ctx* c, const float* depth_mm_dev, pp_frame_desc desc, p
     hipStream_t st = (hipStream_t)stream;
     if ((s = put_plain(c, f, st)) != PP_OK) return s;
     HIPCHK(c, ppk::launch_normals(c->plain_tab, 1, desc.width, desc.height, st));
-    return PP_OK;
+    return mark_stream(c, st);
 }
 
 static pp_status ransac_common(pp_ctx* c, const float* points_dev, const uint8_t* valid_dev, pp_frame_desc desc,
@@ -478,6 +536,7 @@ static pp_status ransac_common(pp_ctx* c, const float* points_dev, const uint8_t
     f.planes = planes_dev;
     f.n_planes = n_planes_dev;
     hipStream_t st = (hipStream_t)stream;
+    if ((s = order_streams(c, st)) != PP_OK) return s;
     if (dbg) {
         f.dbg = *dbg;
         if (dbg->round_info) HIPCHK(c, hipMemsetAsync(dbg->round_info, 0xFF, sizeof(int32_t) * 4 * p->max_planes, st));
@@ -488,7 +547,7 @@ static pp_status ransac_common(pp_ctx* c, const float* points_dev, const uint8_t
         HIPCHK(c, ppk::launch_round(c->plain_tab, 1, r, (int)px, p->hyps_per_plane, p->precision, c->tuning, st,
                                     c->timing ? c->score_ev[r][0] : nullptr, c->timing ? c->score_ev[r][1] : nullptr));
     if (c->timing) c->timed_rounds = p->max_planes;
-    return PP_OK;
+    return mark_stream(c, st);
 }
 
 namespace {
@@ -530,6 +589,7 @@ pp_status regions_common(pp_ctx* c, const float* points_dev, const uint8_t* vali
     }
     ppk::region_bind_scratch(r, c->region_scratch);
     hipStream_t st = (hipStream_t)stream;
+    if ((s = order_streams(c, st)) != PP_OK) return s;
     HIPCHK(c, ppk::launch_regions(r, st));
     if (dbg) {
         const size_t R = r.R, rh = (size_t)r.R * r.hyps;
@@ -541,7 +601,7 @@ pp_status regions_common(pp_ctx* c, const float* points_dev, const uint8_t* vali
         if (dbg->counts) HIPCHK(c, hipMemcpyAsync(dbg->counts, r.counts, rh * 4, hipMemcpyDeviceToDevice, st));
         if (dbg->jstar) HIPCHK(c, hipMemcpyAsync(dbg->jstar, r.jstar, R * 4, hipMemcpyDeviceToDevice, st));
     }
-    return PP_OK;
+    return mark_stream(c, st);
 }
 
 }  // namespace
@@ -597,8 +657,9 @@ pp_status pp_segment(pp_ctx* c, const float* normals_dev, const uint8_t* valid_d
         c->seg_scratch_bytes = need;
     }
     ppk::seg_bind_scratch(g, c->seg_scratch);
+    if ((s = order_streams(c, (hipStream_t)stream)) != PP_OK) return s;
     HIPCHK(c, ppk::launch_segment(g, (hipStream_t)stream));
-    return PP_OK;
+    return mark_stream(c, (hipStream_t)stream);
 }
 
 pp_status pp_ransac_regions_dbg(pp_ctx* c, const float* points_dev, const uint8_t* valid_dev,
@@ -670,7 +731,7 @@ pp_status pp_debug_score_triples(pp_ctx* c, const float* points_dev, const uint8
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, ppk::launch_hyp_from_triples(c->plain_tab, triples_dev, n, st));
     HIPCHK(c, ppk::launch_score_only(c->plain_tab, (int)px, n, precision, c->tuning, st));
-    return PP_OK;
+    return mark_stream(c, st);
 }
 
 }  // extern "C"
@@ -763,7 +824,7 @@ pp_status upload_batch_table(pp_ctx* c, const pp_frame_job* jobs, const BatchPla
         }
         HIPCHK(c, hipMalloc(&c->batch_tab, sizeof(FrameDev) * b.nf));
         c->batch_tab_cap = b.nf;
-        c->graphs.clear();  // captured graphs reference the old table
+        drop_graphs(c);  // captured graphs reference the old table
     }
     const int k = c->ring_pos;
     c->ring_pos = (k + 1) % pp_ctx::kRing;
@@ -828,10 +889,21 @@ pp_status batch_run(pp_ctx* c, int32_t n, const pp_frame_job* jobs, void* stream
             sl.external = true;
         }
     }
+    if ((s = order_streams(c, st)) != PP_OK) return s;
     if ((s = upload_batch_table(c, jobs, b, st)) != PP_OK) return s;
-    if (!use_graph) return enqueue_batch(c, b, st, false);
+    if (!use_graph) {
+        if ((s = enqueue_batch(c, b, st, false)) != PP_OK) return s;
+        return mark_stream(c, st);
+    }
     auto it = c->graphs.find(b.key);
     if (it == c->graphs.end()) {
+        if (c->graphs.size() >= kMaxGraphs) {  // the least recently used layout goes
+            auto lru = c->graphs.begin();
+            for (auto g = c->graphs.begin(); g != c->graphs.end(); ++g)
+                if (g->second.last_use < lru->second.last_use) lru = g;
+            destroy_graph(lru->second);
+            c->graphs.erase(lru);
+        }
         hipGraph_t g = nullptr;
         HIPCHK(c, hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
         pp_status es = enqueue_batch(c, b, c->capture_stream, true);
@@ -845,10 +917,17 @@ pp_status batch_run(pp_ctx* c, int32_t n, const pp_frame_job* jobs, void* stream
         e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+        e = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(ge.exec);
+            return hip_fail(c, e, "hipEventCreateWithFlags");
+        }
         it = c->graphs.emplace(b.key, ge).first;
     }
+    it->second.last_use = ++c->graph_clock;
     HIPCHK(c, hipGraphLaunch(it->second.exec, st));
-    return PP_OK;
+    HIPCHK(c, hipEventRecord(it->second.done, st));
+    return mark_stream(c, st);
 }
 
 }  // namespace

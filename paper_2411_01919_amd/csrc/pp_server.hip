@@ -132,6 +132,7 @@ struct Lane {
     pp_ctx* ctx = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
+    bool dry_fail = false;  // dry run: this batch ends as a failed HIP batch would
     double dry_done_at = 0.0;
     std::vector<uint64_t> tickets;
 };
@@ -214,7 +215,15 @@ void poll_lanes(pp_server* s) {
     for (auto& L : s->lanes) {
         if (!L.busy) continue;
         if (s->dry) {
-            if (now_us() >= L.dry_done_at) finish_lane(s, L);
+            if (now_us() < L.dry_done_at) continue;
+            if (L.dry_fail) {
+                L.dry_fail = false;
+                L.busy = false;
+                L.tickets.clear();
+                poison(s, "batch failed: injected failure (dry run)");
+            } else {
+                finish_lane(s, L);
+            }
             continue;
         }
         const hipError_t e = hipEventQuery(L.done);
@@ -263,6 +272,7 @@ pp_status launch_on(pp_server* s, Lane& L) {
     s->launched_frames += take.size();
     if (s->dry) {
         L.dry_done_at = now_us() + s->cfg.dry_run_us;
+        L.dry_fail = s->cfg.dry_run_fail_batch > 0 && s->launches == (uint64_t)s->cfg.dry_run_fail_batch;
         return PP_OK;
     }
     char* base = static_cast<char*>(s->arena_base);
@@ -344,7 +354,7 @@ extern "C" {
 pp_status pp_server_create(const pp_server_cfg* cfg, pp_server** out) {
     if (!cfg || !out || cfg->hbm_budget_bytes < (1u << 20) || cfg->max_batch < 1 || cfg->max_batch > 1024 ||
         cfg->lanes < 1 || cfg->lanes > 4 || cfg->staging_frames < 1 || cfg->staging_frames > 1024 ||
-        cfg->dry_run_us < 0)
+        cfg->dry_run_us < 0 || cfg->dry_run_fail_batch < 0 || (cfg->dry_run_fail_batch > 0 && cfg->dry_run_us == 0))
         return PP_E_INVAL;
     *out = nullptr;
     pp_server* s = new pp_server();
@@ -568,6 +578,59 @@ pp_status pp_poll(pp_server* s, uint64_t ticket, pp_result* out, int32_t timeout
     st.outstanding--;
     s->tickets.erase(ticket);
     return res;
+}
+
+pp_status pp_server_reset(pp_server* s) {
+    if (!s) return PP_E_INVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    // the device work of every lane ends first (a failed batch has ended already)
+    if (!s->dry) {
+        (void)hipSetDevice(s->cfg.device);
+        for (auto& L : s->lanes)
+            if (L.stream) (void)hipStreamSynchronize(L.stream);
+        (void)hipGetLastError();
+    }
+    for (auto& L : s->lanes) {
+        if (L.busy) {
+            if (!s->dry && hipEventQuery(L.done) == hipSuccess) finish_lane(s, L);
+            L.busy = false;
+            L.dry_fail = false;
+            L.tickets.clear();
+        }
+    }
+    // every frame not completed fails; completed results stay pollable
+    for (auto& kv : s->tickets) {
+        Ticket& t = kv.second;
+        if (t.state == T_QUEUED || t.state == T_ADMITTED || t.state == T_INFLIGHT) {
+            t.state = T_FAILED;
+            t.err = s->poisoned ? PP_E_HIP : PP_E_CLOSED;
+        }
+        t.bytes = 0;  // the arena is reset below; completed frames released theirs already
+    }
+    s->queue.clear();
+    s->ready.clear();
+    const size_t peak = s->arena.peak();
+    s->arena.reset(s->cfg.hbm_budget_bytes);
+    (void)peak;
+    // a context that saw a failure stays poisoned: the lanes get fresh ones
+    if (!s->dry) {
+        for (auto& L : s->lanes) {
+            if (L.ctx) pp_ctx_destroy(L.ctx);
+            L.ctx = nullptr;
+            if (pp_ctx_create(s->cfg.device, &L.ctx) != PP_OK) {
+                L.ctx = nullptr;
+                s->poisoned = true;
+                s->err = "reset: context re-creation failed";
+                s->cv_done.notify_all();
+                return PP_E_HIP;
+            }
+        }
+    }
+    s->poisoned = false;
+    s->err.clear();
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+    return PP_OK;
 }
 
 pp_status pp_server_stats_get(pp_server* s, pp_server_stats* out) {

@@ -206,3 +206,67 @@ def test_invalid_server_calls():
     t = N.c_u64()
     assert h.pp_submit(s.h, 77, np.zeros((H, W), np.uint16).ctypes.data, 0, t) == N.PP_E_INVAL
     s.close()
+
+
+def _poll_status(s, t, sid=0, timeout_s=5.0):
+    """The status a ticket's poll ends with (PP_OK or the error)."""
+    t_end = time.time() + timeout_s
+    while time.time() < t_end:
+        try:
+            if s.poll(t, sid, timeout_us=2000, labels=False) is not None:
+                return N.PP_OK
+        except pp.PPError as e:
+            return e.status
+    raise AssertionError("ticket never finished")
+
+
+def test_a_failed_batch_poisons_the_server_and_reset_recovers():
+    """An executor failure (the third batch, injected in the dry run) fails
+    that batch's frames and every frame not yet completed with PP_E_HIP, and
+    poisons the server: submits return PP_E_HIP.  pp_server_reset then fails
+    what is left, frees the arena, and the server completes new frames."""
+    s = _server(max_batch=2, lanes=1, dry_run_us=5000, dry_run_fail_batch=3)
+    _open(s)
+    ts = [s.submit(0, _frame(k), k) for k in range(10)]
+    st = [_poll_status(s, t) for t in ts]
+    assert st[:4] == [N.PP_OK] * 4            # batches 1 and 2
+    assert all(v == N.PP_E_HIP for v in st[4:])  # batch 3 failed, the rest never ran
+    with pytest.raises(pp.PPError) as e:
+        s.submit(0, _frame(), 99)
+    assert e.value.status == N.PP_E_HIP
+    assert "injected failure" in N.lib().pp_server_last_error(s.h).decode()
+    s.reset()
+    stats = s.stats()
+    assert stats["hbm_in_use"] == 0 and stats["queued"] == 0 and stats["in_flight"] == 0
+    ts = [s.submit(0, _frame(k), 100 + k) for k in range(5)]
+    assert all(_poll_status(s, t) == N.PP_OK for t in ts)
+    assert s.stats()["completed"] == 4 + 5
+    s.close()
+
+
+def test_reset_of_a_healthy_server_cancels_unfinished_frames_and_keeps_results():
+    """Reset with frames in every state: completed results stay pollable,
+    frames queued or on the (simulated) device end with PP_E_CLOSED, and the
+    server runs new frames afterwards."""
+    s = _server(max_batch=1, lanes=1, dry_run_us=30000)
+    _open(s)
+    done = s.submit(0, _frame(0), 0)
+    t_end = time.time() + 10.0
+    while s.stats()["completed"] < 1 and time.time() < t_end:  # the first batch has completed
+        time.sleep(0.001)
+    assert s.stats()["completed"] == 1
+    rest = [s.submit(0, _frame(k), k) for k in range(1, 5)]
+    _wait_launches(s, 2)
+    s.reset()
+    assert _poll_status(s, done) == N.PP_OK
+    assert all(_poll_status(s, t) == N.PP_E_CLOSED for t in rest)
+    t = s.submit(0, _frame(7), 7)
+    assert _poll_status(s, t) == N.PP_OK
+    s.close()
+
+
+def test_failure_injection_needs_the_dry_run():
+    with pytest.raises(pp.PPError):
+        pp.Server(hbm_budget_bytes=64 << 20, dry_run_us=0, dry_run_fail_batch=1)
+    with pytest.raises(pp.PPError):
+        pp.Server(hbm_budget_bytes=64 << 20, dry_run_us=100, dry_run_fail_batch=-1)
