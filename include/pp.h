@@ -154,7 +154,8 @@ pp_status pp_ctx_create(int32_t device, pp_ctx** out);
 /* Wait for the context's outstanding work, free its scratch, destroy it. */
 pp_status pp_ctx_destroy(pp_ctx* ctx);
 const char* pp_status_string(pp_status s);
-/* Text of the last failure on ctx (or of the last failing create when ctx is NULL). */
+/* Text of the last failure on ctx (when ctx is NULL: of the calling thread's last
+ * failing pp_ctx_create or pp_ransac_planes_noalloc). */
 const char* pp_last_error(const pp_ctx* ctx);
 
 /* ---------------------------------------------------------------- stages */
@@ -201,6 +202,27 @@ pp_status pp_normals(pp_ctx* ctx, const float* depth_mm_dev, pp_frame_desc desc,
 pp_status pp_ransac_planes(pp_ctx* ctx, const float* points_dev, const uint8_t* valid_dev,
                            const int16_t* region_dev_or_null, pp_frame_desc desc, const pp_ransac_params* params,
                            pp_plane* planes_dev, int32_t* n_planes_dev, int8_t* labels_dev, void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * sequential whole-frame mode of pp_ransac_planes (same kernels, same
+ * results for the same arguments) with no context and no allocation.  Its
+ * scratch is a device array of PP_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on until the process ends; a frame needing more
+ * (about 45.6 bytes per pixel plus 48 per hypothesis: 1280x1024 at 8192
+ * hypotheses fits, 1920x1080 does not) returns PP_E_INVAL before any work.
+ * Runs on the calling thread's current HIP device with the default tuning,
+ * asynchronously on hip_stream; arguments as pp_ransac_planes (no region
+ * image).  All calls on one GPU share that array and each call leaves its
+ * contents behind: calls whose work may overlap on one GPU (other streams,
+ * other threads) race and must be ordered by the caller.  Errors: PP_E_INVAL
+ * for bad arguments, PP_E_HIP for a failed launch (nothing to poison);
+ * pp_last_error(NULL) on the calling thread gives the text.  The first call
+ * on a device looks the array up (hipGetSymbolAddress). */
+#define PP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+pp_status pp_ransac_planes_noalloc(const float* points_dev, const uint8_t* valid_dev, pp_frame_desc desc,
+                                   const pp_ransac_params* params, pp_plane* planes_dev, int32_t* n_planes_dev,
+                                   int8_t* labels_dev, void* hip_stream);
 
 /* Segmentation of the normal image (Sec. III-D: Canny edges on the normal
  * image; the regions between them are the planes region-mode RANSAC fits).

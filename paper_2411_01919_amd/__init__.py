@@ -241,6 +241,26 @@ def ransac_planes(points, valid, cfg: RansacConfig, planes=None, n_planes=None, 
     return planes, n_planes, labels
 
 
+def ransac_planes_noalloc(points, valid, cfg: RansacConfig, planes, n_planes, labels, stream=None):
+    """Step 4 through pp_ransac_planes_noalloc: the same sequential RANSAC on
+    the library's static per-GPU scratch, with no context and no device
+    allocation (the caller passes every output).  Runs on the current device
+    with the default tuning; calls that overlap on one GPU race."""
+    torch = _torch()
+    _check_dev(points, "points", (torch.float32,))
+    _, H, W = points.shape
+    _check_dev(valid, "valid", (torch.uint8,), (H, W))
+    _check_dev(labels, "labels", (torch.int8,), (H, W))
+    if planes.dtype != torch.uint8 or planes.numel() < cfg.max_planes * PLANE_BYTES or n_planes.numel() < 1:
+        raise ValueError("planes must be uint8 [max_planes*64] and n_planes int32 [1]")
+    p = cfg.c()
+    s = N.lib().pp_ransac_planes_noalloc(_ptr(points), _ptr(valid), _desc(H, W), ctypes.byref(p), _ptr(planes),
+                                          _ptr(n_planes), _ptr(labels), _stream(stream))
+    if s != N.PP_OK:
+        raise PPError(s, N.lib().pp_last_error(None).decode())
+    return planes, n_planes, labels
+
+
 def ransac_planes_debug(points, valid, cfg: RansacConfig, ctx: Optional[Context] = None, stream=None):
     """ransac_planes plus per-round introspection (hypotheses, triples,
     counts, round info, S/F masks, valid list)."""

@@ -111,6 +111,7 @@ SIGNATURES = {
     "pp_diffuse": (c_i32, [c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(DiffuseParams), c_vp]),
     "pp_normals": (c_i32, [c_vp, c_vp, FrameDesc, Intrinsics, c_vp, c_vp, c_vp, c_vp]),
     "pp_ransac_planes": (c_i32, [c_vp, c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp, c_vp, c_vp]),
+    "pp_ransac_planes_noalloc": (c_i32, [c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp, c_vp, c_vp]),
     "pp_ransac_planes_dbg": (c_i32, [c_vp, c_vp, c_vp, FrameDesc, ctypes.POINTER(RansacParams), c_vp, c_vp, c_vp,
                                      ctypes.POINTER(RansacDebug), c_vp]),
     "pp_map_create": (c_i32, [ctypes.POINTER(MapParams), ctypes.POINTER(c_vp)]),
@@ -164,6 +165,10 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+# bytes of device scratch pp_ransac_planes_noalloc holds per GPU (PP_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def status_string(s: int) -> str:

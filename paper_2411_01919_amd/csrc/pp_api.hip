@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -228,15 +229,14 @@ pp_status ensure_slot(pp_ctx* c, int i, size_t px, int hyps) {
     return PP_OK;
 }
 
-void bind_slot(const pp_ctx* c, int i, FrameDev& f) {
-    const Slot& s = c->slots[i];
-    Layout l = slot_layout(s.px_cap, s.hyp_cap);
-    char* b = static_cast<char*>(s.base);
+// Point a frame's scratch fields into one block laid out by slot_layout(px_cap, hyp_cap).
+void bind_layout(char* b, size_t px_cap, int hyp_cap, FrameDev& f) {
+    Layout l = slot_layout(px_cap, hyp_cap);
     f.delta[0] = reinterpret_cast<float*>(b + l.delta);
-    f.delta[1] = f.delta[0] + s.px_cap;
+    f.delta[1] = f.delta[0] + px_cap;
     f.L = reinterpret_cast<int32_t*>(b + l.L);
     f.list[0] = reinterpret_cast<float4*>(b + l.list);
-    f.list[1] = f.list[0] + s.px_cap;
+    f.list[1] = f.list[0] + px_cap;
     f.taken = reinterpret_cast<uint8_t*>(b + l.taken);
     f.hyp = reinterpret_cast<float4*>(b + l.hyp);
     f.hyp_p0 = reinterpret_cast<float4*>(b + l.hyp_p0);
@@ -247,6 +247,11 @@ void bind_slot(const pp_ctx* c, int i, FrameDev& f) {
     f.chunk_cnt_q = reinterpret_cast<int32_t*>(b + l.chunk_cnt_q);
     f.tbox = reinterpret_cast<float4*>(b + l.tbox);
     f.st = reinterpret_cast<RoundState*>(b + l.st);
+}
+
+void bind_slot(const pp_ctx* c, int i, FrameDev& f) {
+    const Slot& s = c->slots[i];
+    bind_layout(static_cast<char*>(s.base), s.px_cap, s.hyp_cap, f);
 }
 
 void fill_geometry(FrameDev& f, const pp_frame_desc& d) {
@@ -961,6 +966,91 @@ const char* ctx_error(const pp_ctx* c) { return c->last_error.c_str(); }
 
 }  // namespace ppk
 
+// ------------------------------------------------------------------ RANSAC without allocation
+// Scratch of pp_ransac_planes_noalloc: the one-entry frame table followed by
+// one frame slot (slot_layout).  Each GPU the library runs on holds its own
+// copy until the process ends.  In host code the array's name stands for a
+// host-side shadow, not device memory: only the per-device address that
+// hipGetSymbolAddress returns is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[PP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocDevices] = {};
+
+// Device address of `scratch` on device dev (the current device), looked up
+// once per device.
+pp_status noalloc_scratch(int dev, void** out) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(nullptr, PP_E_HIP,
+                        std::string("pp_ransac_planes_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        }
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return PP_OK;
+}
+
+// Bytes of `scratch` one frame takes: the frame table entry, then its slot.
+size_t noalloc_bytes(const pp_frame_desc& d, int hyps) {
+    return align256(sizeof(FrameDev)) + slot_layout((size_t)d.width * d.height, hyps).total;
+}
+
+}  // namespace
+
 extern "C" {
+
+pp_status pp_ransac_planes_noalloc(const float* points_dev, const uint8_t* valid_dev, pp_frame_desc desc,
+                                   const pp_ransac_params* p, pp_plane* planes_dev, int32_t* n_planes_dev,
+                                   int8_t* labels_dev, void* stream) {
+    if (!points_dev || !valid_dev || !planes_dev || !n_planes_dev || !labels_dev || !desc_ok(desc) ||
+        !ransac_params_ok(p))
+        return fail(nullptr, PP_E_INVAL, "pp_ransac_planes_noalloc: bad argument");
+    const size_t need = noalloc_bytes(desc, p->hyps_per_plane);
+    if (need > PP_NOALLOC_SCRATCH_BYTES)
+        return fail(nullptr, PP_E_INVAL,
+                    "pp_ransac_planes_noalloc: the frame needs " + std::to_string(need) +
+                        " bytes of scratch, more than the " + std::to_string((size_t)PP_NOALLOC_SCRATCH_BYTES) +
+                        " the library holds per GPU");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kNoAllocDevices) {
+        (void)hipGetLastError();
+        return fail(nullptr, e != hipSuccess ? PP_E_HIP : PP_E_UNSUPPORTED,
+                    "pp_ransac_planes_noalloc: no usable current device");
+    }
+    void* base = nullptr;
+    pp_status s = noalloc_scratch(dev, &base);
+    if (s != PP_OK) return s;
+    FrameDev* tab = static_cast<FrameDev*>(base);
+    const size_t px = (size_t)desc.width * desc.height;
+    FrameDev f{};
+    bind_layout(static_cast<char*>(base) + align256(sizeof(FrameDev)), px, p->hyps_per_plane, f);
+    fill_geometry(f, desc);
+    fill_ransac(f, *p);
+    f.pts = const_cast<float*>(points_dev);
+    f.valid = const_cast<uint8_t*>(valid_dev);
+    f.labels = labels_dev;
+    f.planes = planes_dev;
+    f.n_planes = n_planes_dev;
+    // every scratch field the kernels read is written earlier in the same
+    // call (the valid-list kernels set the round state, the per-point bytes,
+    // the lists and the chunk counts), so nothing is cleared here
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_set_frame, dim3(1), dim3(1), 0, st, tab, f);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = ppk::launch_valid_list(tab, 1, (int)px, desc.width, desc.height, st);
+    for (int r = 0; e == hipSuccess && r < p->max_planes; ++r)
+        e = ppk::launch_round(tab, 1, r, (int)px, p->hyps_per_plane, p->precision, kDefaultTuning, st);
+    if (e != hipSuccess) return fail(nullptr, PP_E_HIP, std::string("pp_ransac_planes_noalloc: ") + hipGetErrorString(e));
+    return PP_OK;
+}
 
 }  // extern "C"
