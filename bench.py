@@ -56,8 +56,8 @@ def score_kernel_name(precision, tuning):
         return f"k_score_mfma ({precision} inlier scoring)"
     hb = int(tuning.get("score_hb", 0)) if tuning else 0
     if hb == 4:
-        return ("k_tile_box + k_score_cull (inlier scoring with 64-point tile culling; "
-                "most tiles are decided per hypothesis from their bounding box)")
+        return ("k_score_cull (inlier scoring with 64-point tile culling: most tiles are decided per "
+                "hypothesis from their bounding box, made at the round's start)")
     return f"k_score<{(8, 16, 32)[max(hb, 1) - 1]}> (inlier scoring)"
 
 

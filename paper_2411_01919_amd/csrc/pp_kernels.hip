@@ -7,17 +7,19 @@
 //   k_normals        back-projection (Alg. 2) + Sobel normal image (Eq. 2)
 //   k_valid_*,       row-major list of depth-valid pixels (Alg. 2 point set) and
 //   k_list_scatter   the round-0 scoring list in 8x8-block order
-//   k_hypgen         3-point hypotheses from Philox4x64-10 (Alg. 2)
-//   k_tile_box,      inlier counts, point-to-plane distance < t (Eq. 3, Alg. 2):
-//   k_score_cull     64-point tiles decided from their bounding boxes, the rest
-//                    point by point (k_score: every point)
-//   k_refit_*        selection, FP64 moments, the least-squares plane (Jacobi,
-//                    one block per frame), its inliers per chunk
+//   k_round_start    3-point hypotheses from Philox4x64-10 (Alg. 2) and the
+//                    bounding boxes of the round's 64-point tiles
+//   k_score_cull     inlier counts, point-to-plane distance < t (Eq. 3, Alg. 2):
+//                    tiles decided from their boxes, the rest point by point
+//                    (k_score: every point)
+//   k_refit_*        selection of j*, FP64 moments of its inliers, the
+//                    least-squares plane (Jacobi, solved in every block of the
+//                    final pass) and its inliers per chunk
 //   k_apply          remove / label the refit plane's inliers, next round
 //
 // Every kernel takes a device table of FrameDev and reads its frame from
-// blockIdx.z (k_hypgen: from an XCD-aware 1-D grid), so one launch serves one
-// frame or a ragged batch alike.
+// blockIdx.z (k_round_start: from a 1-D grid, XCD-aware for the hypotheses),
+// so one launch serves one frame or a ragged batch alike.
 
 #include <math.h>
 
@@ -31,6 +33,7 @@ namespace ppk {
 typedef const __attribute__((address_space(1))) uint8_t* gu8_cptr;
 typedef const __attribute__((address_space(1))) int32_t* gi32_cptr;
 typedef const __attribute__((address_space(1))) float* gf32_cptr;
+typedef const __attribute__((address_space(1))) double* gf64_cptr;
 
 __device__ __forceinline__ float3 load_point(const FrameDev& f, int off) {
     const size_t plane = (size_t)f.H * f.pitch;
@@ -736,14 +739,14 @@ __global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restr
 }
 
 // Workgroups go to the 8 XCDs in turn (workgroup i to XCD i mod 8), each XCD
-// with its own L2.  This maps the 1-D grid of nf * bpf blocks (padded to a
-// multiple of 8) so that each XCD takes a contiguous range of (frame, block)
+// with its own L2.  This maps the first nblocks workgroups of a 1-D grid (nf *
+// bpf blocks padded to a multiple of 8) so that each XCD takes a contiguous range of (frame, block)
 // pairs, i.e. about nf / 8 whole frames, whose random lookups then share one
 // L2.  False for the padding blocks.
 constexpr int kXcds = 8;
-__device__ __forceinline__ bool xcd_frame_block(int bpf, int nf, int& frame, int& bx) {
+__device__ __forceinline__ bool xcd_frame_block(int bpf, int nf, int nblocks, int& frame, int& bx) {
     const int T = bpf * nf;
-    const int per = (int)gridDim.x / kXcds;
+    const int per = nblocks / kXcds;
     const int L = blockIdx.x;
     const int id = (L % kXcds) * per + L / kXcds;
     if (id >= T) return false;
@@ -752,44 +755,70 @@ __device__ __forceinline__ bool xcd_frame_block(int bpf, int nf, int& frame, int
     return true;
 }
 
-__global__ __launch_bounds__(kBlock) void k_hypgen(const FrameDev* __restrict__ tab, int r, int bpf, int nf) {
-    __shared__ int cand[kHypPerBlock][4 * kHypLanes];  // list position, -1 if assigned
-    int frame, bx;
-    if (!xcd_frame_block(bpf, nf, frame, bx)) return;
-    const FrameDev& f = tab[frame];
+// The first of this row's candidates (16 lanes, 4 each, draw order 4 b + q)
+// that is still in play; its value in every lane of the row (INT_MAX: none).
+// The row minima are DPP permutes within the row's 16 lanes.
+__device__ __forceinline__ int row_first_candidate(const int (&cand)[4], int b) {
+    int key = 64;
+#pragma unroll
+    for (int q = 3; q >= 0; --q)
+        if (cand[q] >= 0) key = 4 * b + q;
+    key = dpp_ext<false, 0xB1>(key);   // quad_perm [1,0,3,2]
+    key = dpp_ext<false, 0x4E>(key);   // quad_perm [2,3,0,1]
+    key = dpp_ext<false, 0x124>(key);  // row_ror:4
+    key = dpp_ext<false, 0x128>(key);  // row_ror:8
+    int val = 0x7FFFFFFF;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (key == 4 * b + q) val = cand[q];
+    val = dpp_ext<false, 0xB1>(val);
+    val = dpp_ext<false, 0x4E>(val);
+    val = dpp_ext<false, 0x124>(val);
+    val = dpp_ext<false, 0x128>(val);
+    return val;
+}
+
+// Hypotheses of round r for the 16 hypotheses of block bx of frame f.  Each
+// hypothesis is one 16-lane row: lane b draws Philox block b (4 candidate
+// list positions), a candidate whose point is assigned is dropped, and the
+// triple is the first three distinct candidates left in draw order, exactly
+// the sequential draw's (three rounds of: the row's first candidate, then
+// every copy of it dropped).
+__device__ __forceinline__ void hypgen_block(const FrameDev& f, int r, int bx) {
     const RoundRec rr = round_rec(f, r);
     const uint64_t M0 = (uint64_t)((const __attribute__((address_space(4))) int32_t*)f.st)[0];  // RoundState::M0
     if (!rr.active) return;
     const int hl = threadIdx.x / kHypLanes, b = threadIdx.x % kHypLanes;
     const int j = bx * kHypPerBlock + hl;
     if (bx * kHypPerBlock >= f.hyps) return;
+    static_assert(kHypLanes == 16, "one DPP row per hypothesis");
+    int cand[4] = {-1, -1, -1, -1};
     if (j < f.hyps) {
         uint64_t c[4] = {(uint64_t)j, (uint64_t)r, (uint64_t)b, 0ull};
         philox4x64_10(c, f.seed, f.frame_id);
+        int k[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = (int)__umul64hi(c[q], M0);
-            cand[hl][4 * b + q] = point_taken(f, k) ? -1 : k;
+        for (int q = 0; q < 4; ++q) k[q] = (int)__umul64hi(c[q], M0);
+        // the first round removes nothing before it: no lookups then
+        if (rr.M != (int)M0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) k[q] = point_taken(f, k[q]) ? -1 : k[q];
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cand[q] = k[q];
     }
-    __syncthreads();
-    if (b != 0 || j >= f.hyps) return;
-    int slot[3] = {-1, -1, -1};
+    int slot[3];
     int got = 0;
-    for (int i = 0; i < 4 * kHypLanes && got < 3; ++i) {
-        const int k = cand[hl][i];
-        if (k < 0 || k == slot[0] || k == slot[1]) continue;
-        slot[got++] = k;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int v = row_first_candidate(cand, b);
+        slot[s] = v;
+        got += v != 0x7FFFFFFF ? 1 : 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (cand[q] == v) cand[q] = -1;
     }
-    for (int bb = kHypLanes; bb < 16 && got < 3; ++bb) {
-        uint64_t c[4] = {(uint64_t)j, (uint64_t)r, (uint64_t)bb, 0ull};
-        philox4x64_10(c, f.seed, f.frame_id);
-        for (int q = 0; q < 4 && got < 3; ++q) {
-            const int k = (int)__umul64hi(c[q], M0);
-            if (point_taken(f, k) || k == slot[0] || k == slot[1]) continue;
-            slot[got++] = k;
-        }
-    }
+    if (b != 0 || j >= f.hyps) return;
     float4 h = make_float4(0.f, 0.f, 0.f, __int_as_float(0x7fc00000));
     float3 p0 = make_float3(0.f, 0.f, 0.f);
     if (got == 3) {
@@ -823,6 +852,51 @@ __global__ __launch_bounds__(kBlock) void k_hyp_from_triples(const FrameDev* __r
     f.counts[j] = 0;
 }
 
+// ------------------------------------------------------------------ selection
+// j* = the valid hypothesis with the most inliers, the lowest index among
+// equal counts; -1 if no hypothesis is valid.  Every moments block computes it.
+constexpr int kSelPerThread = 4;
+__device__ __forceinline__ int select_jstar(const FrameDev& f, int* sh) {
+    const int H = f.hyps;
+    const gf32_cptr hw = (gf32_cptr)f.hyp;  // d of hypothesis j at 4 j + 3 (NaN: invalid)
+    const gi32_cptr cn = (gi32_cptr)f.counts;
+    int bc = -1, bj = 0x7FFFFFFF;
+    for (int j0 = threadIdx.x; j0 < H; j0 += kBlock * kSelPerThread) {
+        float d[kSelPerThread];
+        int cnt[kSelPerThread];
+#pragma unroll
+        for (int q = 0; q < kSelPerThread; ++q) {
+            const int jj = min(j0 + q * kBlock, H - 1);
+            d[q] = hw[4 * jj + 3];
+            cnt[q] = cn[jj];
+        }
+#pragma unroll
+        for (int q = 0; q < kSelPerThread; ++q) {
+            const int j = j0 + q * kBlock;
+            if (j < H && d[q] == d[q] && (cnt[q] > bc || (cnt[q] == bc && j < bj))) {
+                bc = cnt[q];
+                bj = j;
+            }
+        }
+    }
+    const int wc = wave_ext<true>(bc);
+    const int wj = wave_ext<false>(bc == wc ? bj : 0x7FFFFFFF);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        sh[w] = wc;
+        sh[4 + w] = wj;
+    }
+    __syncthreads();
+    int best = sh[0], js = sh[4];
+    for (int i = 1; i < 4; ++i)
+        if (sh[i] > best || (sh[i] == best && sh[4 + i] < js)) {
+            best = sh[i];
+            js = sh[4 + i];
+        }
+    return best < 0 ? -1 : js;
+}
+
 // ------------------------------------------------------------------ scoring
 // count_j = #{i in R_r : |n_j . p_i + d_j| < t}.  A block owns HB hypotheses
 // (uniform: scalar loads into SGPRs) and a strided share of the points, one
@@ -832,12 +906,7 @@ __global__ __launch_bounds__(kBlock) void k_hyp_from_triples(const FrameDev* __r
 // wave adds its totals to the global counts with one integer atomic per
 // hypothesis (order-free).
 template <int HB>
-__global__ __launch_bounds__(kBlock) void k_score(const FrameDev* __restrict__ tab, int r) {
-    const FrameDev& f = tab[blockIdx.z];
-    const RoundState* st = f.st;
-    const RoundRec rr = round_rec(f, r);
-    if (!rr.active) return;
-    const int M = rr.M;
+__device__ __forceinline__ void score_block(const FrameDev& f, int r, int M) {
     const int h0 = blockIdx.y * HB;
     if (h0 >= f.hyps) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -867,6 +936,14 @@ __global__ __launch_bounds__(kBlock) void k_score(const FrameDev* __restrict__ t
         for (int k = 0; k < HB; ++k)
             if (cnt[k] != 0u && h0 + k < f.hyps) atomicAdd(&f.counts[h0 + k], (int)cnt[k]);
     }
+}
+
+template <int HB>
+__global__ __launch_bounds__(kBlock) void k_score(const FrameDev* __restrict__ tab, int r) {
+    const FrameDev& f = tab[blockIdx.z];
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active) return;
+    score_block<HB>(f, r, rr.M);
 }
 
 // ------------------------------------------------------------------ culled scoring
@@ -911,17 +988,16 @@ __device__ __forceinline__ int wave_extreme_to_lane63(int v) {
 
 constexpr int kBoxTilesPerWave = 4;
 
-__global__ __launch_bounds__(kBlock) void k_tile_box(const FrameDev* __restrict__ tab, int r) {
-    const FrameDev& f = tab[blockIdx.z];
-    const RoundState* st = f.st;
+// Bounding boxes of round r's 64-point tiles: block bx of nbx for frame f.
+__device__ __forceinline__ void tile_box_block(const FrameDev& f, int r, int bx, int nbx) {
     const RoundRec rr = round_rec(f, r);
     if (!rr.active) return;
     const int M = rr.M;
     const int ntiles = (M + 63) >> 6;
     const int lane = threadIdx.x & 63;
     const float4* __restrict__ pts = f.list[r & 1];
-    const int wave_stride = gridDim.x * (kBlock / 64) * kBoxTilesPerWave;
-    for (int t0 = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * kBoxTilesPerWave; t0 < ntiles; t0 += wave_stride) {
+    const int wave_stride = nbx * (kBlock / 64) * kBoxTilesPerWave;
+    for (int t0 = (bx * (kBlock / 64) + (threadIdx.x >> 6)) * kBoxTilesPerWave; t0 < ntiles; t0 += wave_stride) {
         // all of this wave's tiles in flight at once; lanes past the end repeat the last point
         float4 p[kBoxTilesPerWave];
 #pragma unroll
@@ -949,6 +1025,22 @@ __global__ __launch_bounds__(kBlock) void k_tile_box(const FrameDev* __restrict_
             }
         }
     }
+}
+
+// The start of round r: hypotheses (blocks [0, hyp_blocks), an XCD-aware 1-D
+// mapping of (frame, block) pairs) and, when box_blocks > 0, the tile boxes
+// of the culled scorer (box_blocks blocks per frame after them).  Both read
+// only what the previous round's removal left.
+__global__ __launch_bounds__(kBlock) void k_round_start(const FrameDev* __restrict__ tab, int r, int bpf, int nf,
+                                                         int hyp_blocks, int box_blocks) {
+    if ((int)blockIdx.x < hyp_blocks) {
+        int frame, bx;
+        if (xcd_frame_block(bpf, nf, hyp_blocks, frame, bx)) hypgen_block(tab[frame], r, bx);
+        return;
+    }
+    const int b = (int)blockIdx.x - hyp_blocks;
+    const int frame = b / box_blocks;
+    tile_box_block(tab[frame], r, b - frame * box_blocks, box_blocks);
 }
 
 // Inlier counts with tile culling.  A block holds 64 hypotheses, one per lane.
@@ -998,12 +1090,8 @@ __device__ __forceinline__ uint32_t cull_tile(const float4* box, const float4* h
     return cnt + (uint32_t)w;
 }
 
-__global__ __launch_bounds__(kBlock) void k_score_cull(const FrameDev* __restrict__ tab, int r) {
-    const FrameDev& f = tab[blockIdx.z];
+__device__ __forceinline__ void score_cull_block(const FrameDev& f, int r, int M) {
     const RoundState* st = f.st;
-    const RoundRec rr = round_rec(f, r);
-    if (!rr.active) return;
-    const int M = rr.M;
     const int h0 = blockIdx.y * 64;
     const int hyps = __builtin_amdgcn_readfirstlane(f.hyps);
     if (h0 >= hyps) return;
@@ -1029,6 +1117,13 @@ __global__ __launch_bounds__(kBlock) void k_score_cull(const FrameDev* __restric
     for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += tstride)
         cnt += cull_tile(box, s_h, tile, M, pts, hl, hv, ax, ay, az, tlo, thi, t);
     if (hv && cnt) atomicAdd(&f.counts[h0 + lane], (int)cnt);
+}
+
+__global__ __launch_bounds__(kBlock) void k_score_cull(const FrameDev* __restrict__ tab, int r) {
+    const FrameDev& f = tab[blockIdx.z];
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active) return;
+    score_cull_block(f, r, rr.M);
 }
 
 // ------------------------------------------------------------------ matrix-core scoring
@@ -1057,12 +1152,8 @@ __device__ __forceinline__ short f32_to_bf16_rne(float x) {
 }
 
 template <int PREC, int G>  // G: hypothesis groups of 16 per wave
-__global__ __launch_bounds__(kBlock) void k_score_mfma(const FrameDev* __restrict__ tab, int r) {
-    const FrameDev& f = tab[blockIdx.z];
+__device__ __forceinline__ void score_mfma_block(const FrameDev& f, int r, int M) {
     const RoundState* st = f.st;
-    const RoundRec rr = round_rec(f, r);
-    if (!rr.active) return;
-    const int M = rr.M;
     const int h0 = blockIdx.y * (16 * G);
     if (h0 >= f.hyps || M <= 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1202,57 +1293,20 @@ __global__ __launch_bounds__(kBlock) void k_score_mfma(const FrameDev* __restric
     }
 }
 
+template <int PREC, int G>
+__global__ __launch_bounds__(kBlock) void k_score_mfma(const FrameDev* __restrict__ tab, int r) {
+    const FrameDev& f = tab[blockIdx.z];
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active) return;
+    score_mfma_block<PREC, G>(f, r, rr.M);
+}
+
 // ------------------------------------------------------------------ refit
 // Selection (Alg. 2 "best model", read as: most inliers, ties to the lowest
 // index) is recomputed by every block from the counts; then the FP64 moments
 // (n, sum q, sum q q^T with q = p - p0 of j*) of j*'s inliers are summed per
 // fixed chunk of the point list, in a fixed order.
 constexpr int kChunkSteps = kRefitChunk / kBlock;  // points per thread of a refit / removal chunk
-
-// j* = the valid hypothesis with the most inliers, the lowest index among
-// equal counts; -1 if no hypothesis is valid.  Every block computes it.
-constexpr int kSelPerThread = 4;
-__device__ __forceinline__ int select_jstar(const FrameDev& f, int* sh) {
-    const int H = f.hyps;
-    const gf32_cptr hw = (gf32_cptr)f.hyp;  // d of hypothesis j at 4 j + 3 (NaN: invalid)
-    const gi32_cptr cn = (gi32_cptr)f.counts;
-    int bc = -1, bj = 0x7FFFFFFF;
-    for (int j0 = threadIdx.x; j0 < H; j0 += kBlock * kSelPerThread) {
-        float d[kSelPerThread];
-        int cnt[kSelPerThread];
-#pragma unroll
-        for (int q = 0; q < kSelPerThread; ++q) {
-            const int jj = min(j0 + q * kBlock, H - 1);
-            d[q] = hw[4 * jj + 3];
-            cnt[q] = cn[jj];
-        }
-#pragma unroll
-        for (int q = 0; q < kSelPerThread; ++q) {
-            const int j = j0 + q * kBlock;
-            if (j < H && d[q] == d[q] && (cnt[q] > bc || (cnt[q] == bc && j < bj))) {
-                bc = cnt[q];
-                bj = j;
-            }
-        }
-    }
-    const int wc = wave_ext<true>(bc);
-    const int wj = wave_ext<false>(bc == wc ? bj : 0x7FFFFFFF);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-        sh[w] = wc;
-        sh[4 + w] = wj;
-    }
-    __syncthreads();
-    int best = sh[0], js = sh[4];
-    for (int i = 1; i < 4; ++i)
-        if (sh[i] > best || (sh[i] == best && sh[4 + i] < js)) {
-            best = sh[i];
-            js = sh[4 + i];
-        }
-    return best < 0 ? -1 : js;
-}
-
 
 // Symmetric 3x3 eigenproblem by cyclic Jacobi rotations in the tau form
 // (a'_rp = a_rp - s (a_rq + tau a_rp), tau = s / (1 + c)); columns of v are
@@ -1288,42 +1342,110 @@ __device__ void jacobi3(double a[3][3], double v[3][3]) {
     }
 }
 
+// The longest of the three pairwise cross products of the rows of A - l I
+// (for l an eigenvalue, the rows span a plane whose normal is its
+// eigenvector); returns its squared length.
+__device__ __forceinline__ double row_cross(const double a[3][3], double l, double n[3]) {
+    const double r[3][3] = {{a[0][0] - l, a[0][1], a[0][2]}, {a[0][1], a[1][1] - l, a[1][2]},
+                            {a[0][2], a[1][2], a[2][2] - l}};
+    const int pu[3] = {0, 0, 1}, pw[3] = {1, 2, 2};
+    double best = -1.0;
+    for (int k = 0; k < 3; ++k) {
+        const double* u = r[pu[k]];
+        const double* w = r[pw[k]];
+        const double x = u[1] * w[2] - u[2] * w[1];
+        const double y = u[2] * w[0] - u[0] * w[2];
+        const double z = u[0] * w[1] - u[1] * w[0];
+        const double q = x * x + y * y + z * z;
+        if (q > best) {
+            best = q;
+            n[0] = x; n[1] = y; n[2] = z;
+        }
+    }
+    return best;
+}
+
+// Eigenvector of the smallest eigenvalue l3 of a symmetric positive
+// semi-definite 3x3 matrix A (a scatter matrix), unnormalised.  l3 is first
+// approached as the smallest root of det(A - l I) = -l^3 + t2 l^2 - t1 l + t0
+// (t2 = trace, t1 = sum of the principal 2x2 minors, t0 = det A): on [0, l3]
+// that cubic decreases and is convex, so Newton steps from l = 0 climb to l3
+// from below without overshoot; they stop when a step no longer increases l.
+// t0 cancels badly when l3 is small, so the eigenvector from the rows of
+// A - l I (row_cross) is refined twice by the Rayleigh quotient l = n.A n /
+// n.n, whose error is quadratic in the eigenvector's; the result is as
+// accurate as a backward-stable solver's (about u l1 / (l2 - l3)).  A
+// handful of FP64 divisions instead of the dozens of rotations of Jacobi's
+// method.  Returns false when l3 is not separated from l2 (the longest cross
+// product is negligible), leaving the case to Jacobi.
+__device__ bool smallest_eigvec(const double a[3][3], double n[3]) {
+    const double t2 = a[0][0] + a[1][1] + a[2][2];
+    const double c00 = a[1][1] * a[2][2] - a[1][2] * a[1][2];
+    const double c01 = a[0][2] * a[1][2] - a[0][1] * a[2][2];
+    const double c02 = a[0][1] * a[1][2] - a[1][1] * a[0][2];
+    const double t1 = c00 + (a[0][0] * a[2][2] - a[0][2] * a[0][2]) + (a[0][0] * a[1][1] - a[0][1] * a[0][1]);
+    const double t0 = a[0][0] * c00 + a[0][1] * c01 + a[0][2] * c02;
+    double l = 0.0;
+    for (int it = 0; it < 32; ++it) {
+        const double p = ((t2 - l) * l - t1) * l + t0;
+        const double dp = (2.0 * t2 - 3.0 * l) * l - t1;
+        if (!(dp < 0.0)) break;
+        const double ln = l - p / dp;
+        if (!(ln > l)) break;
+        l = ln;
+    }
+    double best = row_cross(a, l, n);
+    for (int pass = 0; pass < 2; ++pass) {
+        const double x = n[0], y = n[1], z = n[2];
+        const double ax = a[0][0] * x + a[0][1] * y + a[0][2] * z;
+        const double ay = a[0][1] * x + a[1][1] * y + a[1][2] * z;
+        const double az = a[0][2] * x + a[1][2] * y + a[2][2] * z;
+        l = (x * ax + y * ay + z * az) / (x * x + y * y + z * z);
+        best = row_cross(a, l, n);
+    }
+    // |cross| ~ l1 (l2 - l3): a gap below 1e-12 of the trace goes to Jacobi
+    const double g = 1e-24 * t2 * t2 * t2 * t2;
+    return best > g && best < INFINITY;
+}
+
 // Reduce the chunk moments in a fixed order (thread t sums chunks t, t+256,
-// ... in order, then a fixed tree over threads), so every block obtains the
-// same bits.  Then the least-squares plane: centroid c = shift + S/n,
+// ... in order, then a butterfly over each wave's lanes and the four waves in
+// order), so every block obtains the same bits.  Then the least-squares plane: centroid c = shift + S/n,
 // scatter C = Q - S S^T / n, normal = eigenvector of the smallest eigenvalue,
 // d = -n.c, flipped so that d >= 0.  All threads call; thread 0 solves.
 __device__ void solve_refit(const FrameDev& f, int M, double sx, double sy, double sz, double* plane, double* centroid,
                             double* nmom, double* sh) {
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
+    const gf64_cptr part = (gf64_cptr)f.partials;
     double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int c = threadIdx.x; c < nch; c += kBlock)
 #pragma unroll
-        for (int k = 0; k < 10; ++k) m[k] += f.partials[(size_t)c * 10 + k];
+        for (int k = 0; k < 10; ++k) m[k] += part[(size_t)c * 10 + k];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) sh[k * kBlock + threadIdx.x] = m[k];
+    for (int k = 0; k < 10; ++k) m[k] = wave_sum_d(m[k]);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) sh[(threadIdx.x >> 6) * 10 + k] = m[k];
     __syncthreads();
-    for (int w = kBlock / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-#pragma unroll
-            for (int k = 0; k < 10; ++k) sh[k * kBlock + threadIdx.x] += sh[k * kBlock + threadIdx.x + w];
-        __syncthreads();
-    }
     if (threadIdx.x != 0) return;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) m[k] = sh[k * kBlock];
+    for (int k = 0; k < 10; ++k) m[k] = ((sh[k] + sh[10 + k]) + sh[20 + k]) + sh[30 + k];
     const double n = m[0];
     const double mx = m[1] / n, my = m[2] / n, mz = m[3] / n;
     double a[3][3];
     a[0][0] = m[4] - m[1] * mx; a[0][1] = m[5] - m[1] * my; a[0][2] = m[6] - m[1] * mz;
     a[1][1] = m[7] - m[2] * my; a[1][2] = m[8] - m[2] * mz; a[2][2] = m[9] - m[3] * mz;
     a[1][0] = a[0][1]; a[2][0] = a[0][2]; a[2][1] = a[1][2];
-    double v[3][3];
-    jacobi3(a, v);
-    int kmin = 0;
-    if (a[1][1] < a[kmin][kmin]) kmin = 1;
-    if (a[2][2] < a[kmin][kmin]) kmin = 2;
-    double nx = v[0][kmin], ny = v[1][kmin], nz = v[2][kmin];
+    double nv[3];
+    if (!smallest_eigvec(a, nv)) {
+        double v[3][3];
+        jacobi3(a, v);
+        int kmin = 0;
+        if (a[1][1] < a[kmin][kmin]) kmin = 1;
+        if (a[2][2] < a[kmin][kmin]) kmin = 2;
+        nv[0] = v[0][kmin]; nv[1] = v[1][kmin]; nv[2] = v[2][kmin];
+    }
+    double nx = nv[0], ny = nv[1], nz = nv[2];
     const double nn = sqrt(nx * nx + ny * ny + nz * nz);
     nx /= nn; ny /= nn; nz /= nn;
     const double cx = sx + mx, cy = sy + my, cz = sz + mz;
@@ -1403,69 +1525,51 @@ __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __rest
     }
 }
 
-// One block per frame: the refit plane from the moments pass's partials,
-// once (the kernel boundary orders the partials of every block before it).
-__global__ __launch_bounds__(kBlock) void k_refit_solve(const FrameDev* __restrict__ tab, int r) {
-    __shared__ double s_plane[4], s_cent[3], s_n;
-    __shared__ double s_red[10 * kBlock];
-    const FrameDev& f = tab[blockIdx.z];
-    const RoundRec rr = round_rec(f, r);
-    if (!rr.active || rr.stop) return;
-    const float4 p0 = ld_global4(f.hyp_p0, rr.jstar);  // the moments' origin
-    solve_refit(f, rr.M, p0.x, p0.y, p0.z, s_plane, s_cent, &s_n, s_red);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        RoundState* st = f.st;
-        for (int k = 0; k < 4; ++k) st->plane[k] = s_plane[k];
-        for (int k = 0; k < 3; ++k) st->centroid[k] = s_cent[k];
-        st->s_count = (int)s_n;
-    }
-}
-
-// |F| per chunk, for the removal.  SOLVE: each block first solves the refit
-// plane itself (solve_refit, the same reduction order as k_refit_solve, so the
-// same plane bit for bit) and block 0 stores it.  Used when the grid fits in one
-// residency wave (a few frames), where the redundant solves run side by side and
-// the separate solve launch would only add its latency.
-template <bool SOLVE>
+// |F| per chunk for the removal, F = the refit plane's inliers.  Every block
+// first solves the refit plane itself (solve_refit: the same reduction order
+// in every block, so the same plane bit for bit) while the points of its
+// first chunk are already on their way; block 0 stores the plane, the
+// centroid and |S|.  The grid gives each frame only a few blocks per CU, so
+// the redundant solves run side by side, once per block.
 __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restrict__ tab, int r) {
     __shared__ int sh[4];
     __shared__ double s_plane[4], s_cent[3], s_n;
-    __shared__ double s_red[SOLVE ? 10 * kBlock : 1];
+    __shared__ double s_red[4 * 10];
     const FrameDev& f = tab[blockIdx.z];
     const RoundRec rr = round_rec(f, r);
     if (!rr.active || rr.stop) return;
     const int M = rr.M;
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
     if ((int)blockIdx.x >= nch) return;
-    SplitPlane q;
-    if constexpr (SOLVE) {
-        const float4 p0 = ld_global4(f.hyp_p0, rr.jstar);  // the moments' origin
-        solve_refit(f, M, p0.x, p0.y, p0.z, s_plane, s_cent, &s_n, s_red);
-        __syncthreads();
-        q = split_plane(s_plane);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            RoundState* st = f.st;
-            for (int k = 0; k < 4; ++k) st->plane[k] = s_plane[k];
-            for (int k = 0; k < 3; ++k) st->centroid[k] = s_cent[k];
-            st->s_count = (int)s_n;
-        }
-    } else {
-        q = split_plane(f.st->plane);  // stored by k_refit_solve
-    }
     const float t = f.thresh;
     const float4* __restrict__ pts = f.list[r & 1];
-    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        int cnt = 0;
-        const int e = min(M, (c + 1) * kRefitChunk);
-        float4 pp[kChunkSteps];
+    int c = blockIdx.x;
+    float4 pp[kChunkSteps];
+    int e = min(M, (c + 1) * kRefitChunk);
 #pragma unroll
-        for (int s = 0; s < kChunkSteps; ++s) pp[s] = ld_global4(pts, min(c * kRefitChunk + s * kBlock + (int)threadIdx.x, e - 1));
+    for (int s = 0; s < kChunkSteps; ++s) pp[s] = ld_global4(pts, min(c * kRefitChunk + s * kBlock + (int)threadIdx.x, e - 1));
+    const float4 p0 = ld_global4(f.hyp_p0, rr.jstar);  // the moments' origin
+    solve_refit(f, M, p0.x, p0.y, p0.z, s_plane, s_cent, &s_n, s_red);
+    __syncthreads();
+    const SplitPlane q = split_plane(s_plane);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        RoundState* st = f.st;
+        for (int k = 0; k < 4; ++k) st->plane[k] = s_plane[k];
+        for (int k = 0; k < 3; ++k) st->centroid[k] = s_cent[k];
+        st->s_count = (int)s_n;
+    }
+    while (true) {
+        int cnt = 0;
 #pragma unroll
         for (int s = 0; s < kChunkSteps; ++s)
             cnt += (c * kRefitChunk + s * kBlock + (int)threadIdx.x < e && fabsf(refit_res(q, pp[s].x, pp[s].y, pp[s].z)) < t) ? 1 : 0;
         cnt = block_sum(cnt, sh);
         if (threadIdx.x == 0) f.chunk_cnt[c] = cnt;
+        c += gridDim.x;
+        if (c >= nch) break;
+        e = min(M, (c + 1) * kRefitChunk);
+#pragma unroll
+        for (int s = 0; s < kChunkSteps; ++s) pp[s] = ld_global4(pts, min(c * kRefitChunk + s * kBlock + (int)threadIdx.x, e - 1));
     }
 }
 
@@ -1698,24 +1802,28 @@ hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, int maxW, 
 }
 
 template <int HB>
-static void score_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target, hipStream_t s) {
+static void score_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target,
+                         hipStream_t s) {
     const int groups = (max_hyps + HB - 1) / HB;
     const int per_frame_cap = clampi(16384 / (nf > 0 ? nf : 1), 8, 4096);
     const int bx = clampi((max_pts + target - 1) / target, 1, clampi(per_frame_cap / groups, 1, 1024));
     hipLaunchKernelGGL((k_score<HB>), dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
 }
 
-// Culled scoring: the tile boxes of round r's list, then 64 hypotheses per block.
+// Culled scoring, 64 hypotheses per block (the tile boxes are made at the round's start).
 static void score_cull_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target,
                               hipStream_t s) {
-    const int tiles = (max_pts + 63) / 64;
-    const int per_block = (kBlock / 64) * kBoxTilesPerWave;
-    hipLaunchKernelGGL(k_tile_box, dim3(clampi((tiles + per_block - 1) / per_block, 1, 65535), 1, nf), dim3(kBlock), 0,
-                       s, tab, r);
     const int groups = (max_hyps + 63) / 64;
     const int per_frame_cap = clampi(16384 / (nf > 0 ? nf : 1), 8, 4096);
     const int bx = clampi((max_pts + target - 1) / target, 1, clampi(per_frame_cap / groups, 1, 1024));
     hipLaunchKernelGGL(k_score_cull, dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
+}
+
+// Tile-box blocks per frame for round lists of up to max_pts points.
+static int box_blocks(int max_pts) {
+    const int tiles = (max_pts + 63) / 64;
+    const int per_block = (kBlock / 64) * kBoxTilesPerWave;
+    return clampi((tiles + per_block - 1) / per_block, 1, 65535);
 }
 
 template <int PREC>
@@ -1728,10 +1836,13 @@ static void score_mfma_launch(const FrameDev* tab, int nf, int r, int max_pts, i
     hipLaunchKernelGGL((k_score_mfma<PREC, G>), dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
 }
 
+static bool culled(int precision, const Tuning& tu) { return precision == PP_SCORE_FP32 && tu.score_hb >= 3; }
+
 static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int precision,
                            const Tuning& tu, hipStream_t s) {
     const int target = chunk_value(tu.score_chunk);
-    if (precision == PP_SCORE_MFMA_F32) return score_mfma_launch<PP_SCORE_MFMA_F32>(tab, nf, r, max_pts, max_hyps, target, s);
+    if (precision == PP_SCORE_MFMA_F32)
+        return score_mfma_launch<PP_SCORE_MFMA_F32>(tab, nf, r, max_pts, max_hyps, target, s);
     if (precision == PP_SCORE_BF16) return score_mfma_launch<PP_SCORE_BF16>(tab, nf, r, max_pts, max_hyps, target, s);
     if (precision == PP_SCORE_FP16) return score_mfma_launch<PP_SCORE_FP16>(tab, nf, r, max_pts, max_hyps, target, s);
     switch (tu.score_hb) {
@@ -1742,28 +1853,29 @@ static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int 
     }
 }
 
-// Counting grids of at most this many blocks solve the refit plane in every
-// block (one residency wave: 7 such blocks fit per CU); larger ones solve it
-// once per frame in k_refit_solve.
-constexpr long kFusedSolveBlocks = 1024;
+// Blocks of the final pass over all frames (8 per CU): more would repeat the
+// plane solve in more block waves.
+constexpr int kFinalBlocks = 2048;
 
+// One RANSAC round for every frame of the table: hypotheses (+ tile boxes),
+// scoring, selection and moments, the refit plane and its inliers per chunk,
+// the removal.
 hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_hyps, int precision,
                         const Tuning& tu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const int bpf = (max_hyps + kHypPerBlock - 1) / kHypPerBlock;
     const int hyp_blocks = (bpf * nf + kXcds - 1) / kXcds * kXcds;
-    hipLaunchKernelGGL(k_hypgen, dim3(hyp_blocks), dim3(kBlock), 0, s, tab, r, bpf, nf);
+    const int nbox = culled(precision, tu) ? box_blocks(max_px) : 0;
+    hipLaunchKernelGGL(k_round_start, dim3(hyp_blocks + nbox * nf), dim3(kBlock), 0, s, tab, r, bpf, nf, hyp_blocks,
+                       nbox);
     if (ev0) (void)hipEventRecord(ev0, s);
     score_dispatch(tab, nf, r, max_px, max_hyps, precision, tu, s);
     if (ev1) (void)hipEventRecord(ev1, s);
     const int nch = (max_px + kRefitChunk - 1) / kRefitChunk;
     const int gx = clampi(nch, 1, 1024);
     hipLaunchKernelGGL(k_refit_moments, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
-    if ((long)nf * gx <= kFusedSolveBlocks) {
-        hipLaunchKernelGGL(k_refit_final<true>, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
-    } else {
-        hipLaunchKernelGGL(k_refit_solve, dim3(1, 1, nf), dim3(kBlock), 0, s, tab, r);
-        hipLaunchKernelGGL(k_refit_final<false>, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
-    }
+    // a few blocks per CU in all: each solves the plane once, then counts several chunks
+    const int gf = clampi(std::min(nch, kFinalBlocks / std::max(nf, 1)), 1, 1024);
+    hipLaunchKernelGGL(k_refit_final, dim3(gf, 1, nf), dim3(kBlock), 0, s, tab, r);
     hipLaunchKernelGGL(k_apply, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
     return hipGetLastError();
 }
@@ -1774,6 +1886,10 @@ hipError_t launch_hyp_from_triples(const FrameDev* tab, const int32_t* triples, 
 }
 
 hipError_t launch_score_only(const FrameDev* tab, int max_px, int n, int precision, const Tuning& tu, hipStream_t s) {
+    if (culled(precision, tu)) {
+        const int nbox = box_blocks(max_px);
+        hipLaunchKernelGGL(k_round_start, dim3(nbox), dim3(kBlock), 0, s, tab, 0, 1, 1, 0, nbox);
+    }
     score_dispatch(tab, 1, 0, max_px, n, precision, tu, s);
     return hipGetLastError();
 }
