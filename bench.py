@@ -52,13 +52,14 @@ def residuals_of(n_planes, inliers, m0, max_planes, hyps):
 
 
 def score_kernel_name(precision, tuning):
-    if precision != "fp32":
-        return f"k_score_mfma ({precision} inlier scoring)"
     hb = int(tuning.get("score_hb", 0)) if tuning else 0
-    if hb == 4:
-        return ("k_score_cull (inlier scoring with 64-point tile culling: most tiles are decided per "
-                "hypothesis from their bounding box, made at the round's start)")
-    return f"k_score<{(8, 16, 32)[max(hb, 1) - 1]}> (inlier scoring)"
+    if precision == "fp32" and hb <= 3:
+        return f"k_score<{(8, 16, 32)[max(hb, 1) - 1]}> (inlier scoring, every point)"
+    q = {5: 2, 6: 4}.get(hb, 1)
+    form = {"fp32": "vector ALUs", "mfma_f32": "FP32 matrix cores", "bf16": "BF16 matrix cores",
+            "fp16": "FP16 matrix cores"}[precision]
+    return (f"k_score_tiles<{precision}, {q}> (inlier scoring with 64-point tile culling: most tiles are decided "
+            f"per hypothesis from their bounding box, made at the round's start; undecided ones on the {form})")
 
 
 def source_hash():

@@ -96,14 +96,18 @@ typedef struct { int32_t iters; float lambda; float kappa_mm; int32_t edge_stop;
  * canonical FP32 residual fmaf(nx,x, fmaf(ny,y, fmaf(nz,z,d))) does, so all
  * forms return identical counts, planes and labels:
  *  PP_SCORE_FP32      the canonical formula on the vector ALUs;
- *  PP_SCORE_MFMA_F32  the contraction on FP32 matrix cores; residuals within
+ *  the matrix-core forms evaluate on the matrix cores the points of the
+ *  64-point tiles whose bounding box leaves a hypothesis undecided (when a
+ *  tile has at least 40 such hypotheses; fewer go to the vector ALUs):
+ *  PP_SCORE_MFMA_F32  the contraction in FP32; residuals within
  *                     max(recheck_band_m, 16 * 2^-24 * (max|p|_1 + |d|)) of t
  *                     are recomputed canonically;
- *  PP_SCORE_BF16/FP16 tile-centred points and normals in BF16/FP16 on the
- *                     matrix cores with FP32 accumulation; residuals within
- *                     recheck_band_m of t, and every point whose bound on the
- *                     low-precision error exceeds it, are recomputed
- *                     canonically (recheck_band_m = 0.002 is the 2 mm form). */
+ *  PP_SCORE_BF16/FP16 points centred on their tile's box and the normals in
+ *                     BF16/FP16, FP32 accumulation; residuals within
+ *                     max(recheck_band_m, a bound on the low-precision
+ *                     error, about 1e-2 / 1e-3 of the tile's extent along n)
+ *                     of t are recomputed canonically (recheck_band_m =
+ *                     0.002 is the 2 mm form, 0 the tightest). */
 enum { PP_SCORE_FP32 = 0, PP_SCORE_MFMA_F32 = 1, PP_SCORE_BF16 = 2, PP_SCORE_FP16 = 3 };
 
 /* Alg. 2 "RANSAC parameters".  Hypotheses draw from Philox4x64-10 keyed by
@@ -386,12 +390,13 @@ pp_status pp_batch_run_eager(pp_ctx* ctx, int32_t n_frames, const pp_frame_job* 
  * diffuse_tile: the diffusion kernel's tile shape (1-4: LDS tiles of 64x16,
  * 128x16, 64x32 and 128x32 pixels; 5, 6: register-resident columns, one
  * wave per 64 - 2T columns and 8 or 16 rows), diffuse_t: iterations fused
- * per pass (temporal blocking depth), score_hb: the FP32 scorer's
- * hypotheses per block (1: 8, 2: 16, 3: 32 on the vector ALUs; 4: 64 with
- * tile culling, each 64-point tile's bounding box first decides for every
- * hypothesis whether all, none or only some of its points can be inliers),
- * score_chunk: points per scoring work item.  Every choice gives identical
- * results. */
+ * per pass (temporal blocking depth), score_hb: the scorer's hypotheses per
+ * block (1: 8, 2: 16, 3: 32, every point on the vector ALUs, FP32 form only;
+ * 4: 64, 5: 128, 6: 256 with tile culling: each 64-point tile's bounding box
+ * first decides for every hypothesis whether all, none or only some of its
+ * points can be inliers; the matrix-core forms always cull, at 64 when 1-3
+ * is set), score_chunk: points per scoring work item.  Every choice gives
+ * identical results. */
 typedef struct {
     int32_t diffuse_tile;
     int32_t diffuse_t;

@@ -17,7 +17,7 @@ from typing import Dict, Optional, Sequence
 
 TILES = (1, 2, 3, 4, 5, 6)           # LDS 64x16, 128x16, 64x32, 128x32; register columns of 8, 16 rows
 DEPTHS = (1, 2, 3, 4, 5, 8, 10)      # iterations per diffusion pass
-HB = (1, 2, 3, 4)                    # 8, 16, 32 hypotheses per VALU scoring block; 64 with tile culling
+HB = (1, 2, 3, 4, 5, 6)              # 8, 16, 32 hypotheses per VALU scoring block; 64, 128, 256 with tile culling
 CHUNKS = (1, 2, 3, 4)                # 1024 ... 8192 points per scoring block
 
 
@@ -89,7 +89,7 @@ def tune(frames: Sequence, ctx=None, reps: int = 2, path: Optional[str] = None, 
             diff[(tile, T)] = _time_stage(pp, frames, ctx, "diffusion", reps)
     tile, T = min(diff, key=diff.get)
     score = {}
-    hbs = HB if frames[0].ransac.precision == pp.PP_SCORE_FP32 else (base["score_hb"],)
+    hbs = HB if frames[0].ransac.precision == pp.PP_SCORE_FP32 else (4, 5, 6)
     for hb in hbs:
         for ch in CHUNKS:
             ctx.set_tuning(diffuse_tile=tile, diffuse_t=T, score_hb=hb, score_chunk=ch)

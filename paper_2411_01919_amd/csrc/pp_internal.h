@@ -88,13 +88,13 @@ struct FrameDev {
 struct Tuning {
     int diffuse_tile;  // LDS tiles 64x16, 128x16, 64x32, 128x32; register-resident waves of TY = 8, 16 rows
     int diffuse_t;     // iterations per pass
-    int score_hb;      // index into {8, 16, 32, 64 with tile culling}
+    int score_hb;      // index into {8, 16, 32, then 64, 128, 256 with tile culling (1, 2, 4 per lane)}
     int score_chunk;   // index into {1024, 2048, 4096, 8192}
 };
 
 constexpr int kNumTiles = 6;
 constexpr int kMaxT = 10;
-constexpr int kNumHB = 4;
+constexpr int kNumHB = 6;
 constexpr int kNumChunk = 4;
 int hb_value(int idx);
 int chunk_value(int idx);

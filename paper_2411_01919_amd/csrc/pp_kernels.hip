@@ -9,9 +9,10 @@
 //   k_list_scatter   the round-0 scoring list in 8x8-block order
 //   k_round_start    3-point hypotheses from Philox4x64-10 (Alg. 2) and the
 //                    bounding boxes of the round's 64-point tiles
-//   k_score_cull     inlier counts, point-to-plane distance < t (Eq. 3, Alg. 2):
+//   k_score_tiles    inlier counts, point-to-plane distance < t (Eq. 3, Alg. 2):
 //                    tiles decided from their boxes, the rest point by point
-//                    (k_score: every point)
+//                    on the vector ALUs or the matrix cores (k_score: every
+//                    point)
 //   k_refit_*        selection of j*, FP64 moments of its inliers, the
 //                    least-squares plane (Jacobi, solved in every block of the
 //                    final pass) and its inliers per chunk
@@ -1043,39 +1044,30 @@ __global__ __launch_bounds__(kBlock) void k_round_start(const FrameDev* __restri
     tile_box_block(tab[frame], r, b - frame * box_blocks, box_blocks);
 }
 
-// Inlier counts with tile culling.  A block holds 64 hypotheses, one per lane.
-// For each 64-point tile, every lane bounds its hypothesis' residual over the
+// Inlier counts over 64-point tiles (Eq. 3, Alg. 2): the tile boxes decide
+// most (tile, hypothesis) pairs; the rest are counted point by point.
+//
+// A block holds 64 Q hypotheses, Q per lane; its four waves take tiles in
+// turn.  For each tile every lane bounds its hypotheses' residuals over the
 // tile's box: |n.c + d| -/+ (|nx| ex + |ny| ey + |nz| ez).  With a margin of
-// 16 u (P1 + |d|) (u = 2^-24, P1 = max |p|_1 of the frame), which exceeds
-// the FP32 rounding of the bound and of the canonical residual, a tile lies
+// 16 u (P1 + |d|) (u = 2^-24, P1 = max |p|_1 of the frame), which exceeds the
+// FP32 rounding of the bound and of the canonical residual, a tile lies
 // wholly outside (no inliers) or wholly inside (all its points are inliers)
-// exactly as the canonical formula decides; only the hypotheses left
-// straddling are evaluated point by point (one point per lane), and their
-// counts are the canonical ones.
-// One tile of k_score_cull for this lane's hypothesis: the box test, then,
-// only if some hypothesis of the block straddles, the tile's points (one per
-// lane; the index is clamped and lanes past the end are masked out of every
-// ballot) against each straddling hypothesis, lowest first; returns this
-// lane's count.
-__device__ __forceinline__ uint32_t cull_tile(const float4* box, const float4* hyp_lds, int tile, int M,
-                                              const float4* pts, float4 hl, bool hv, float ax, float ay, float az,
-                                              float tlo, float thi, float t) {
-    const float4 c = ld_global4(box, 2 * tile), e = ld_global4(box, 2 * tile + 1);
-    const float a = fabsf(fmaf(hl.x, c.x, fmaf(hl.y, c.y, fmaf(hl.z, c.z, hl.w))));
-    const float ext = fmaf(ax, e.x, fmaf(ay, e.y, az * e.z));
-    const bool in = hv && a + ext < tlo;
-    const bool out = !hv || a - ext >= thi;
-    uint32_t cnt = in ? (uint32_t)__float_as_int(c.w) : 0u;
-    unsigned long long S = __ballot(!in && !out);
-    if (!S) return cnt;
-    // lanes past the end hold a NaN point, which no hypothesis takes as an inlier
-    const bool live = tile * 64 + (int)(threadIdx.x & 63) < M;
-    float3 p = ld_global_xyz(pts, min(tile * 64 + (int)(threadIdx.x & 63), M - 1));
-    const float qnan = __int_as_float(0x7fc00000);
-    if (!live) p = make_float3(qnan, qnan, qnan);
-    asm volatile("" : "+v"(p.x), "+v"(p.y), "+v"(p.z));  // keeps the select out of the loop below
-    // each straddling hypothesis occurs once per tile: its count is written
-    // straight into its lane of w (v_writelane, lane select in M0)
+// exactly as the canonical formula decides.  The hypotheses left straddling
+// the tile are evaluated on its points, so every count is the canonical one:
+//  - a few of them (or every one, for PP_SCORE_FP32): one at a time with the
+//    canonical formula, the tile's points one per lane (straddle_loop);
+//  - otherwise on the matrix cores, 16 at a time (mfma_groups).
+constexpr int kMfmaMinStraddlers = 40;  // fewer straddlers of a tile go through straddle_loop
+
+// One tile's straddling hypotheses S (bit k: slot k of hyp_lds) against the
+// tile's points (one per lane; lanes past the list's end hold a NaN point,
+// which no hypothesis takes as an inlier), lowest first.  Each straddler
+// occurs once per tile: its count is written straight into its lane of the
+// result (v_writelane, lane select in M0).  S != 0.  (Reading the next
+// plane ahead added more copies than it hid latency: enough waves share a
+// SIMD to cover the LDS read.)
+__device__ __forceinline__ int straddle_loop(unsigned long long S, const float4* hyp_lds, float3 p, float t) {
     int w = 0;
     do {
         const int k = __builtin_ctzll(S);
@@ -1087,218 +1079,298 @@ __device__ __forceinline__ uint32_t cull_tile(const float4* box, const float4* h
         const int m = __popcll(__ballot(fabsf(canon_res(h, p.x, p.y, p.z)) < t));
         asm("v_writelane_b32 %0, %2, %1" : "+v"(w) : "{m0}"(k), "s"(m));
     } while (S);
-    return cnt + (uint32_t)w;
+    return w;
 }
 
-__device__ __forceinline__ void score_cull_block(const FrameDev& f, int r, int M) {
-    const RoundState* st = f.st;
-    const int h0 = blockIdx.y * 64;
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+
+// Low-precision matrix operands: 8 elements per lane (K = 32).
+template <int PREC> struct LpVec { typedef bf16x8_t type; typedef __bf16 elem; };
+template <> struct LpVec<PP_SCORE_FP16> { typedef f16x8_t type; typedef _Float16 elem; };
+
+// FP16 operands carry q scaled by 2^6 (exact), so that coordinates down to
+// about 1e-6 m stay normal FP16 numbers; residuals and thresholds scale alike.
+template <int PREC> constexpr float lp_scale() { return PREC == PP_SCORE_FP16 ? 64.f : 1.f; }
+
+// A value v in the low precision as hi + lo, both rounded to nearest
+// (v - hi is exact in FP32), so that hi + lo is v to about u_lp^2.
+template <int PREC>
+__device__ __forceinline__ void lp_split(float v, typename LpVec<PREC>::elem& hi, typename LpVec<PREC>::elem& lo) {
+    typedef typename LpVec<PREC>::elem lp_t;
+    hi = (lp_t)v;
+    lo = (lp_t)(v - (float)hi);
+}
+
+// The K elements of a low-precision operand row, in split form: lanes 0-15
+// carry elements 0-7 and lanes 16-31 element 8 (K positions 0-8 of 32).
+// Points: (qx_h, qy_h, qz_h, qx_l, qy_l, qz_l, qx_h, qy_h | qz_h);
+// normals: (nx_h, ny_h, nz_h, nx_h, ny_h, nz_h, nx_l, ny_l | nz_l): the
+// contraction is q_h.n_h + q_l.n_h + q_h.n_l, i.e. (q_h + q_l).(n_h + n_l)
+// without q_l.n_l.
+template <int PREC>
+__device__ __forceinline__ void lp_point_row(float qx, float qy, float qz, typename LpVec<PREC>::type& row,
+                                             typename LpVec<PREC>::elem& row8) {
+    typename LpVec<PREC>::elem xh, xl, yh, yl, zh, zl;
+    lp_split<PREC>(qx, xh, xl);
+    lp_split<PREC>(qy, yh, yl);
+    lp_split<PREC>(qz, zh, zl);
+    row = typename LpVec<PREC>::type{xh, yh, zh, xl, yl, zl, xh, yh};
+    row8 = zh;
+}
+template <int PREC>
+__device__ __forceinline__ void lp_normal_row(float nx, float ny, float nz, typename LpVec<PREC>::type& row,
+                                              typename LpVec<PREC>::elem& row8) {
+    typename LpVec<PREC>::elem xh, xl, yh, yl, zh, zl;
+    lp_split<PREC>(nx, xh, xl);
+    lp_split<PREC>(ny, yh, yl);
+    lp_split<PREC>(nz, zh, zl);
+    row = typename LpVec<PREC>::type{xh, yh, zh, xh, yh, zh, xl, yl};
+    row8 = zl;
+}
+
+// The straddlers of one tile on the matrix cores, 16 hypotheses a group.
+// The queue qs holds their slots in s_h; sp holds the tile's 64 points
+// (NaN coordinates past the list's end).  v_mfma_f32_16x16x*: 16 points
+// along M (A rows), the group's 16 hypotheses along N (B columns); lane l
+// holds D[4 (l/16) + v][l % 16] of each 16-point block b, so after the
+// tile's four blocks every lane has 16 residuals of one hypothesis.
+//   PP_SCORE_MFMA_F32: A = (x, y, z, 1), B = (nx, ny, nz, d) (16x16x4 f32);
+//     D and the canonical residual differ by rounding only: at most
+//     16 u (P1 + |d|) (u = 2^-24; P1 bounds |p|_1 over the tile's points).
+//   PP_SCORE_BF16 / FP16 (16x16x32): A = q = p - c (c: the tile box's
+//     centre) and B = n in the split form of lp_point_row / lp_normal_row
+//     (unit roundoff u_lp = 2^-8 / 2^-11, staged in LDS: spa per point,
+//     shb per hypothesis), C = a = n.c + d in FP32; the products are exact
+//     and accumulate in FP32.  With |q_k| <= e_k and E = sum |n_k| e_k, D
+//     differs from the canonical residual by at most (3 u_lp^2 + 12 u) E +
+//     48 u (P1 + |d|), plus 6.2e-5 (e_x + e_y + e_z + 3 / 2^6) should the
+//     matrix cores flush FP16 subnormals.
+// A residual whose |D| lies farther than the band from t decides as the
+// canonical one does; one inside the band (within max(recheck_band_m, the
+// bound) of t) is recomputed canonically.  Counts go to LDS (ds_add).
+template <int PREC>
+__device__ __forceinline__ void mfma_groups(int ns, const int* __restrict__ qs, const float4* __restrict__ sp,
+                                            const typename LpVec<PREC>::type* __restrict__ spa,
+                                            const typename LpVec<PREC>::elem* __restrict__ spa8,
+                                            const float4* __restrict__ s_h,
+                                            const typename LpVec<PREC>::type* __restrict__ shb,
+                                            const typename LpVec<PREC>::elem* __restrict__ shb8, int* s_cnt,
+                                            float4 c, float4 e, float t, float P1, float band_min) {
+    typedef typename LpVec<PREC>::type lpv_t;
+    typedef typename LpVec<PREC>::elem lp_t;
+    const int lane = threadIdx.x & 63, col = lane & 15, grp = lane >> 4;
+    const float u = 5.9604645e-8f;
+    const float qnan = __int_as_float(0x7fc00000);
+    constexpr bool F32 = PREC == PP_SCORE_MFMA_F32;
+    constexpr float S = lp_scale<PREC>();
+    const lp_t z = (lp_t)0.f;
+    const lpv_t zv = {z, z, z, z, z, z, z, z};
+    // A operands of the tile's four 16-point blocks
+    float a32[4];
+    lpv_t alp[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        if constexpr (F32) {
+            a32[b] = reinterpret_cast<const float*>(sp + 16 * b + col)[grp];
+        } else {
+            alp[b] = zv;
+            if (grp == 0) alp[b] = spa[16 * b + col];
+            else if (grp == 1) alp[b][0] = spa8[16 * b + col];
+        }
+    }
+    const float ulp = PREC == PP_SCORE_BF16 ? 0.00390625f : 0.00048828125f;
+    const float coef = 3.f * ulp * ulp + 12.f * u;
+    const float flush = PREC == PP_SCORE_FP16 ? 6.2e-5f * (e.x + e.y + e.z + 3.f / 64.f) : 0.f;
+    for (int g = 0; g * 16 < ns; ++g) {
+        const int k = g * 16 + col;
+        const int slot = k < ns ? qs[k] : -1;
+        const float4 h = slot >= 0 ? s_h[slot] : make_float4(0.f, 0.f, 0.f, qnan);
+        float band = F32 ? 16.f * u * (P1 + fabsf(h.w))
+                         : fmaf(coef, fmaf(fabsf(h.x), e.x, fmaf(fabsf(h.y), e.y, fabsf(h.z) * e.z)),
+                                48.f * u * (P1 + fabsf(h.w))) + flush;
+        band = fmaxf(band, band_min);
+        const float tlo = (t - band) * S, thi = (t + band) * S;
+        f32x4_t D[4];
+        if constexpr (F32) {
+            // component grp of the column's plane, read straight from LDS
+            const float bop = slot >= 0 ? reinterpret_cast<const float*>(s_h + slot)[grp] : qnan;
+            const f32x4_t zf = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int b = 0; b < 4; ++b) D[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[b], bop, zf, 0, 0, 0);
+        } else {
+            lpv_t bv = zv;
+            if (slot >= 0) {
+                if (grp == 0) bv = shb[slot];
+                else if (grp == 1) bv[0] = shb8[slot];
+            }
+            const float a = fmaf(h.x, c.x, fmaf(h.y, c.y, fmaf(h.z, c.z, h.w))) * S;
+            const f32x4_t cc = {a, a, a, a};
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if constexpr (PREC == PP_SCORE_BF16)
+                    D[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alp[b], bv, cc, 0, 0, 0);
+                else
+                    D[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(alp[b], bv, cc, 0, 0, 0);
+            }
+        }
+        // definite inliers counted; residuals inside the band only flag the wave
+        int cnt = 0;
+        unsigned long long amb = 0ull;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float x = fabsf(D[b][v]);
+                const bool sure = x < tlo;
+                cnt += sure ? 1 : 0;
+                amb |= __ballot(x < thi) & ~__ballot(sure);
+            }
+        if (__builtin_expect(amb != 0ull, 0)) {  // the canonical residual decides inside the band
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float x = fabsf(D[b][v]);
+                    if (x >= tlo && x < thi) {
+                        const float4 p = sp[16 * b + 4 * grp + v];
+                        cnt += fabsf(canon_res(h, p.x, p.y, p.z)) < t ? 1 : 0;
+                    }
+                }
+        }
+        // the four lanes of a column add into its hypothesis' count
+        if (slot >= 0 && cnt != 0) atomicAdd(&s_cnt[slot], cnt);
+    }
+}
+
+template <int PREC, int Q>
+__global__ __launch_bounds__(kBlock) void k_score_tiles(const FrameDev* __restrict__ tab, int r) {
+    constexpr int NH = 64 * Q;
+    constexpr bool MF = PREC != PP_SCORE_FP32;
+    __shared__ float4 s_h[NH];
+    __shared__ int s_cnt[NH];
+    constexpr bool LP = PREC == PP_SCORE_BF16 || PREC == PP_SCORE_FP16;
+    typedef typename LpVec<PREC>::type lpv_t;
+    typedef typename LpVec<PREC>::elem lp_t;
+    __shared__ int s_q[MF ? kBlock / 64 : 1][MF ? NH : 1];        // per wave: slots of the tile's straddlers
+    __shared__ float4 s_p[MF ? kBlock / 64 : 1][MF ? 64 : 1];    // per wave: the tile's points
+    __shared__ lpv_t s_pa[LP ? kBlock / 64 : 1][LP ? 64 : 1];    // per wave: split low-precision rows of q
+    __shared__ lp_t s_pa8[LP ? kBlock / 64 : 1][LP ? 64 : 1];
+    __shared__ lpv_t s_hb[LP ? NH : 1];                            // split low-precision rows of the normals
+    __shared__ lp_t s_hb8[LP ? NH : 1];
+    const FrameDev& f = tab[blockIdx.z];
+    const RoundRec rr = round_rec(f, r);
+    if (!rr.active) return;
+    const int M = rr.M;
     const int hyps = __builtin_amdgcn_readfirstlane(f.hyps);
+    const int h0 = blockIdx.y * NH;
     if (h0 >= hyps) return;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const float qnan = __int_as_float(0x7fc00000);
-    const int nh = min(64, hyps - h0);
-    const float4* hyp = f.hyp + h0;
-    __shared__ float4 s_h[64];
-    if (threadIdx.x < 64) s_h[threadIdx.x] = lane < nh ? ld_global4(hyp, lane) : make_float4(0.f, 0.f, 0.f, qnan);
+    for (int j = threadIdx.x; j < NH; j += kBlock) {
+        const float4 h = h0 + j < hyps ? ld_global4(f.hyp, h0 + j) : make_float4(0.f, 0.f, 0.f, qnan);
+        s_h[j] = h;
+        s_cnt[j] = 0;
+        if constexpr (LP) lp_normal_row<PREC>(h.x, h.y, h.z, s_hb[j], s_hb8[j]);
+    }
     __syncthreads();
-    const float4 hl = s_h[lane];
-    const bool hv = hl.w == hl.w;
     const float t = f.thresh;
-    const float band = 16.f * 5.9604645e-8f * (__uint_as_float(st->p1max_bits) + fabsf(hl.w));
-    const float thi = t + band, tlo = t - band;
-    const float ax = fabsf(hl.x), ay = fabsf(hl.y), az = fabsf(hl.z);
+    const float P1 = __uint_as_float(f.st->p1max_bits);
+    const float u = 5.9604645e-8f;
+    float4 hl[Q];
+    bool hv[Q];
+    float ax[Q], ay[Q], az[Q], tlo[Q], thi[Q];
+    uint32_t cnt[Q];
+    int w[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        hl[q] = s_h[q * 64 + lane];
+        hv[q] = hl[q].w == hl[q].w;
+        const float band = 16.f * u * (P1 + fabsf(hl[q].w));
+        tlo[q] = t - band;
+        thi[q] = t + band;
+        ax[q] = fabsf(hl[q].x);
+        ay[q] = fabsf(hl[q].y);
+        az[q] = fabsf(hl[q].z);
+        cnt[q] = 0u;
+        w[q] = 0;
+    }
     const float4* pts = f.list[r & 1];
     const float4* box = f.tbox;
     const int ntiles = (M + 63) >> 6;
+    // each wave's next tile (box and this lane's point) is loaded one iteration ahead
     const int tstride = gridDim.x * 4;
-    uint32_t cnt = 0u;
-    for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += tstride)
-        cnt += cull_tile(box, s_h, tile, M, pts, hl, hv, ax, ay, az, tlo, thi, t);
-    if (hv && cnt) atomicAdd(&f.counts[h0 + lane], (int)cnt);
-}
-
-__global__ __launch_bounds__(kBlock) void k_score_cull(const FrameDev* __restrict__ tab, int r) {
-    const FrameDev& f = tab[blockIdx.z];
-    const RoundRec rr = round_rec(f, r);
-    if (!rr.active) return;
-    score_cull_block(f, r, rr.M);
-}
-
-// ------------------------------------------------------------------ matrix-core scoring
-// The same counts as k_score, with the contraction n.p + d on the matrix
-// cores.  D = A B (+ C) on v_mfma_f32_16x16x*: 16 points along M (A rows), 16
-// hypotheses along N (B columns); lane l holds D[4*(l/16) + v][l % 16], so
-// every lane counts for one hypothesis.  Each residual whose matrix-core
-// value lies within `band` of t is recomputed with the canonical FP32
-// formula, so every form returns exactly the canonical counts:
-//   PREC 1 (FP32, 16x16x4): A = (x, y, z, 1), B = (nx, ny, nz, d); the two
-//     evaluations differ by rounding only: band_j = 16 u (P1 + |d_j|),
-//     u = 2^-24, P1 = max |p|_1 of the frame.
-//   PREC 2 / 3 (BF16 / FP16, 16x16x16): points centred on the tile's first
-//     point c, A = q = p - c, B = n in the low precision (unit roundoff
-//     u_lp = 2^-8 / 2^-11), C = n.c + d in FP32.  The residual error is at
-//     most (2 u_lp + u_lp^2 + 4u) |q|_1 + 32 u P1; a row (point) whose bound
-//     exceeds the caller's band is rechecked against all its hypotheses.
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-typedef short s16x4_t __attribute__((ext_vector_type(4)));
-typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ short f32_to_bf16_rne(float x) {
-    uint32_t b = __float_as_uint(x);
-    b += 0x7FFFu + ((b >> 16) & 1u);
-    return (short)(b >> 16);
-}
-
-template <int PREC, int G>  // G: hypothesis groups of 16 per wave
-__device__ __forceinline__ void score_mfma_block(const FrameDev& f, int r, int M) {
-    const RoundState* st = f.st;
-    const int h0 = blockIdx.y * (16 * G);
-    if (h0 >= f.hyps || M <= 0) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int col = lane & 15, grp = lane >> 4;
-    const float t = f.thresh;
-    const float u = 5.9604645e-8f;
-    const float P1 = __uint_as_float(st->p1max_bits);
-    const float4* __restrict__ pts = f.list[r & 1];
-    const float* __restrict__ ptsf = reinterpret_cast<const float*>(pts);
-    const float qnan = __int_as_float(0x7fc00000);
-    const float4 nanh = make_float4(0.f, 0.f, 0.f, qnan);
-
-    // this lane's hypotheses (column col of each group) and their bands
-    float4 hf[G];
-    float tlo[G], thi[G];
-    float bop[G];     // FP32 B operand: component grp of the hypothesis in column col
-    s16x4_t bbf[G];   // BF16 B operand (lanes 0..15 carry n, others 0)
-    f16x4_t bh[G];    // FP16 B operand
-    int cnt[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const int j = h0 + g * 16 + col;
-        hf[g] = j < f.hyps ? f.hyp[j] : nanh;
-        const float band = PREC == PP_SCORE_MFMA_F32 ? fmaxf(f.band, 16.f * u * (P1 + fabsf(hf[g].w))) : f.band;
-        tlo[g] = t - band;
-        thi[g] = t + band;
-        bop[g] = grp == 0 ? hf[g].x : grp == 1 ? hf[g].y : grp == 2 ? hf[g].z : hf[g].w;
-        s16x4_t zb = {0, 0, 0, 0};
-        f16x4_t zh = {(_Float16)0.f, (_Float16)0.f, (_Float16)0.f, (_Float16)0.f};
-        if (grp == 0) {
-            zb[0] = f32_to_bf16_rne(hf[g].x); zb[1] = f32_to_bf16_rne(hf[g].y); zb[2] = f32_to_bf16_rne(hf[g].z);
-            zh[0] = (_Float16)hf[g].x; zh[1] = (_Float16)hf[g].y; zh[2] = (_Float16)hf[g].z;
-        }
-        bbf[g] = zb;
-        bh[g] = zh;
-        cnt[g] = 0;
-    }
-    const float ulp_lp = PREC == PP_SCORE_BF16 ? 0.00390625f : 0.00048828125f;
-    const float row_coef = 2.f * ulp_lp + ulp_lp * ulp_lp + 4.f * u;
-    const float row_fixed = 32.f * u * P1;
-
-    const int ntiles = (M + 15) >> 4;
-    const int wstride = gridDim.x * 4;
-    // operands of the next tile are loaded one iteration ahead (software pipelining)
     int tile = blockIdx.x * 4 + wave;
-    float v_next = 0.f;
-    float4 p_next = make_float4(0.f, 0.f, 0.f, 0.f), c_next = p_next;
+    float4 c_next = make_float4(0.f, 0.f, 0.f, 0.f), e_next = c_next;
+    float3 p_next = make_float3(0.f, 0.f, 0.f);
     if (tile < ntiles) {
-        const int i = (tile << 4) + col;
-        const int ic = i < M ? i : M - 1;  // loads stay in range; rows past M become NaN
-        if (PREC == PP_SCORE_MFMA_F32) v_next = ptsf[4 * ic + grp];
-        else { p_next = pts[ic]; c_next = pts[tile << 4]; }
+        c_next = ld_global4(box, 2 * tile);
+        e_next = ld_global4(box, 2 * tile + 1);
+        p_next = ld_global_xyz(pts, min(tile * 64 + lane, M - 1));
     }
-    for (; tile < ntiles; tile += wstride) {
-        const int base = tile << 4;
-        const int i = base + col;
-        const float v = v_next;
-        const float4 p = p_next, c = c_next;
-        if (tile + wstride < ntiles) {
-            const int i2 = ((tile + wstride) << 4) + col;
-            const int ic2 = i2 < M ? i2 : M - 1;
-            if (PREC == PP_SCORE_MFMA_F32) v_next = ptsf[4 * ic2 + grp];
-            else { p_next = pts[ic2]; c_next = pts[(tile + wstride) << 4]; }
+    for (; tile < ntiles; tile += tstride) {
+        const float4 c = c_next, e = e_next;
+        float3 p = p_next;
+        if (tile + tstride < ntiles) {
+            c_next = ld_global4(box, 2 * (tile + tstride));
+            e_next = ld_global4(box, 2 * (tile + tstride) + 1);
+            p_next = ld_global_xyz(pts, min((tile + tstride) * 64 + lane, M - 1));
         }
-        f32x4_t D[G];
-        uint32_t unsafe = 0;  // rows whose low-precision error bound exceeds the band
-        if (PREC == PP_SCORE_MFMA_F32) {
-            const float a = i < M ? (grp == 3 ? 1.0f : v) : qnan;
-            const f32x4_t z = {0.f, 0.f, 0.f, 0.f};
+        unsigned long long S[Q];
+        int ns = 0;
 #pragma unroll
-            for (int g = 0; g < G; ++g) D[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bop[g], z, 0, 0, 0);
-        } else {
-            // c: the tile's first point (anchor); p: this lane's point
-            const float qx = i < M ? p.x - c.x : qnan, qy = p.y - c.y, qz = p.z - c.z;
-            const bool row_unsafe = i < M && !(row_coef * (fabsf(qx) + fabsf(qy) + fabsf(qz)) + row_fixed < f.band);
-            unsafe = (uint32_t)(__ballot(grp == 0 && row_unsafe) & 0xFFFFull);
-            s16x4_t abf = {0, 0, 0, 0};
-            f16x4_t ah = {(_Float16)0.f, (_Float16)0.f, (_Float16)0.f, (_Float16)0.f};
-            if (PREC == PP_SCORE_BF16) {
-                if (grp == 0) { abf[0] = f32_to_bf16_rne(qx); abf[1] = f32_to_bf16_rne(qy); abf[2] = f32_to_bf16_rne(qz); }
-            } else {
-                if (grp == 0) { ah[0] = (_Float16)qx; ah[1] = (_Float16)qy; ah[2] = (_Float16)qz; }
-            }
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const float bias = fmaf(hf[g].x, c.x, fmaf(hf[g].y, c.y, fmaf(hf[g].z, c.z, hf[g].w)));
-                const f32x4_t cc = {bias, bias, bias, bias};
-                if (PREC == PP_SCORE_BF16)
-                    D[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(abf, bbf[g], cc, 0, 0, 0);
-                else
-                    D[g] = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh[g], cc, 0, 0, 0);
-            }
+        for (int q = 0; q < Q; ++q) {
+            const float a = fabsf(fmaf(hl[q].x, c.x, fmaf(hl[q].y, c.y, fmaf(hl[q].z, c.z, hl[q].w))));
+            const float ext = fmaf(ax[q], e.x, fmaf(ay[q], e.y, az[q] * e.z));
+            const bool in = hv[q] && a + ext < tlo[q];
+            const bool out = !hv[q] || a - ext >= thi[q];
+            cnt[q] += in ? (uint32_t)__float_as_int(c.w) : 0u;
+            S[q] = __ballot(!in && !out);
+            ns += __popcll(S[q]);
         }
-        // definite inliers: |d| < t - band; residuals with t - band <= |d| < t + band only raise a flag
-        uint64_t bandm = 0;  // lane mask, kept in scalar registers
+        if (ns == 0) continue;
+        if (tile * 64 + lane >= M) p = make_float3(qnan, qnan, qnan);
+        if (!MF || ns < kMfmaMinStraddlers) {
+            asm volatile("" : "+v"(p.x), "+v"(p.y), "+v"(p.z));  // keeps the select out of the loops below
 #pragma unroll
-        for (int g = 0; g < G; ++g)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const float a = fabsf(D[g][v]);
-                const bool lo = a < tlo[g];
-                cnt[g] += lo ? 1 : 0;
-                bandm |= __ballot(a < thi[g]) & ~__ballot(lo);
+            for (int q = 0; q < Q; ++q)
+                if (S[q]) w[q] += straddle_loop(S[q], s_h + q * 64, p, t);
+            continue;
+        }
+        if constexpr (MF) {
+            // the tile's points and the straddlers' slots (in slot order); one
+            // wave's LDS accesses complete in order, so no barrier is needed
+            s_p[wave][lane] = make_float4(p.x, p.y, p.z, 1.f);
+            if constexpr (LP) {
+                constexpr float S = lp_scale<PREC>();
+                lp_point_row<PREC>((p.x - c.x) * S, (p.y - c.y) * S, (p.z - c.z) * S, s_pa[wave][lane],
+                                   s_pa8[wave][lane]);
             }
-        if (bandm != 0ull || unsafe != 0) {
-            // rare: recompute flagged residuals with the canonical formula
+            int base = 0;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int pi = base + 4 * grp + v;
-                if (pi >= M) continue;
-                const bool row_bad = (unsafe >> (4 * grp + v)) & 1u;
-                bool any = row_bad;
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const float a = fabsf(D[g][v]);
-                    any = any || (a >= tlo[g] && a < thi[g]);
-                }
-                if (!any) continue;
-                const float4 p = pts[pi];
-#pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const float a = fabsf(D[g][v]);
-                    const bool counted = a < tlo[g];
-                    if (row_bad || (!counted && a < thi[g]))
-                        cnt[g] += (fabsf(canon_res(hf[g], p.x, p.y, p.z)) < t ? 1 : 0) - (counted ? 1 : 0);
-                }
+            for (int q = 0; q < Q; ++q) {
+                if ((S[q] >> lane) & 1ull) s_q[wave][base + __popcll(S[q] & lanemask_lt())] = q * 64 + lane;
+                base += __popcll(S[q]);
             }
+            // the tile's points have |p|_1 <= |c|_1 + |e|_1: the bands' bound on |p|_1 (widened by 2^-20
+            // for the rounding of the sum), tighter than the frame's
+            const float P1t = fminf(P1, (fabsf(c.x) + fabsf(c.y) + fabsf(c.z) + (e.x + e.y + e.z)) * 1.00000095f);
+            mfma_groups<PREC>(ns, s_q[wave], s_p[wave], s_pa[LP ? wave : 0], s_pa8[LP ? wave : 0], s_h, s_hb, s_hb8,
+                              s_cnt, c, e, t, P1t, f.band);
         }
     }
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        int c = cnt[g];
-        c += __shfl_xor(c, 16);
-        c += __shfl_xor(c, 32);
-        const int j = h0 + g * 16 + col;
-        if (grp == 0 && c != 0 && j < f.hyps) atomicAdd(&f.counts[j], c);
+    for (int q = 0; q < Q; ++q) {
+        const int v = (int)cnt[q] + w[q];
+        if (v) atomicAdd(&s_cnt[q * 64 + lane], v);
     }
-}
-
-template <int PREC, int G>
-__global__ __launch_bounds__(kBlock) void k_score_mfma(const FrameDev* __restrict__ tab, int r) {
-    const FrameDev& f = tab[blockIdx.z];
-    const RoundRec rr = round_rec(f, r);
-    if (!rr.active) return;
-    score_mfma_block<PREC, G>(f, r, rr.M);
+    __syncthreads();
+    for (int j = threadIdx.x; j < NH; j += kBlock) {
+        const int v = s_cnt[j];
+        if (v && h0 + j < hyps) atomicAdd(&f.counts[h0 + j], v);
+    }
 }
 
 // ------------------------------------------------------------------ refit
@@ -1682,7 +1754,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
 }
 
 // ------------------------------------------------------------------ launchers
-static const int kHB[kNumHB] = {8, 16, 32, 64};  // 64: the culled scorer
+static const int kHB[kNumHB] = {8, 16, 32, 64, 128, 256};  // 64 Q: the tile-culled scorer, Q per lane
 static const int kChunk[kNumChunk] = {1024, 2048, 4096, 8192};
 
 int hb_value(int i) { return kHB[i]; }
@@ -1810,14 +1882,23 @@ static void score_launch(const FrameDev* tab, int nf, int r, int max_pts, int ma
     hipLaunchKernelGGL((k_score<HB>), dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
 }
 
-// Culled scoring, 64 hypotheses per block (the tile boxes are made at the round's start).
-static void score_cull_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target,
-                              hipStream_t s) {
-    const int groups = (max_hyps + 63) / 64;
+// Tile-culled scoring (k_score_tiles), 64 Q hypotheses per block; the tile
+// boxes are made at the round's start.
+template <int PREC>
+static void score_tiles_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target, int q,
+                               hipStream_t s) {
+    const int groups = (max_hyps + 64 * q - 1) / (64 * q);
     const int per_frame_cap = clampi(16384 / (nf > 0 ? nf : 1), 8, 4096);
     const int bx = clampi((max_pts + target - 1) / target, 1, clampi(per_frame_cap / groups, 1, 1024));
-    hipLaunchKernelGGL(k_score_cull, dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
+    const dim3 grid(bx, groups, nf);
+    if (q == 1) hipLaunchKernelGGL((k_score_tiles<PREC, 1>), grid, dim3(kBlock), 0, s, tab, r);
+    else if (q == 2) hipLaunchKernelGGL((k_score_tiles<PREC, 2>), grid, dim3(kBlock), 0, s, tab, r);
+    else hipLaunchKernelGGL((k_score_tiles<PREC, 4>), grid, dim3(kBlock), 0, s, tab, r);
 }
+
+// Tile-box culling: every matrix-core form, and the FP32 form at the culled tunings.
+static bool culled(int precision, const Tuning& tu) { return precision != PP_SCORE_FP32 || tu.score_hb >= 3; }
+static int tiles_q(const Tuning& tu) { return tu.score_hb <= 3 ? 1 : (tu.score_hb == 4 ? 2 : 4); }
 
 // Tile-box blocks per frame for round lists of up to max_pts points.
 static int box_blocks(int max_pts) {
@@ -1826,30 +1907,23 @@ static int box_blocks(int max_pts) {
     return clampi((tiles + per_block - 1) / per_block, 1, 65535);
 }
 
-template <int PREC>
-static void score_mfma_launch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int target,
-                              hipStream_t s) {
-    constexpr int G = PREC == PP_SCORE_MFMA_F32 ? 8 : 4;
-    const int groups = (max_hyps + 16 * G - 1) / (16 * G);
-    const int per_frame_cap = clampi(16384 / (nf > 0 ? nf : 1), 8, 4096);
-    const int bx = clampi((max_pts + target - 1) / target, 1, clampi(per_frame_cap / groups, 1, 1024));
-    hipLaunchKernelGGL((k_score_mfma<PREC, G>), dim3(bx, groups, nf), dim3(kBlock), 0, s, tab, r);
-}
-
-static bool culled(int precision, const Tuning& tu) { return precision == PP_SCORE_FP32 && tu.score_hb >= 3; }
-
 static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int precision,
                            const Tuning& tu, hipStream_t s) {
     const int target = chunk_value(tu.score_chunk);
-    if (precision == PP_SCORE_MFMA_F32)
-        return score_mfma_launch<PP_SCORE_MFMA_F32>(tab, nf, r, max_pts, max_hyps, target, s);
-    if (precision == PP_SCORE_BF16) return score_mfma_launch<PP_SCORE_BF16>(tab, nf, r, max_pts, max_hyps, target, s);
-    if (precision == PP_SCORE_FP16) return score_mfma_launch<PP_SCORE_FP16>(tab, nf, r, max_pts, max_hyps, target, s);
-    switch (tu.score_hb) {
-        case 0: score_launch<8>(tab, nf, r, max_pts, max_hyps, target, s); break;
-        case 1: score_launch<16>(tab, nf, r, max_pts, max_hyps, target, s); break;
-        case 2: score_launch<32>(tab, nf, r, max_pts, max_hyps, target, s); break;
-        default: score_cull_launch(tab, nf, r, max_pts, max_hyps, target, s); break;
+    if (!culled(precision, tu)) {
+        switch (tu.score_hb) {
+            case 0: score_launch<8>(tab, nf, r, max_pts, max_hyps, target, s); break;
+            case 1: score_launch<16>(tab, nf, r, max_pts, max_hyps, target, s); break;
+            default: score_launch<32>(tab, nf, r, max_pts, max_hyps, target, s); break;
+        }
+        return;
+    }
+    const int q = tiles_q(tu);
+    switch (precision) {
+        case PP_SCORE_MFMA_F32: score_tiles_launch<PP_SCORE_MFMA_F32>(tab, nf, r, max_pts, max_hyps, target, q, s); break;
+        case PP_SCORE_BF16: score_tiles_launch<PP_SCORE_BF16>(tab, nf, r, max_pts, max_hyps, target, q, s); break;
+        case PP_SCORE_FP16: score_tiles_launch<PP_SCORE_FP16>(tab, nf, r, max_pts, max_hyps, target, q, s); break;
+        default: score_tiles_launch<PP_SCORE_FP32>(tab, nf, r, max_pts, max_hyps, target, q, s); break;
     }
 }
 

@@ -435,7 +435,7 @@ def test_scoring_tunings_give_identical_planes(pp):
     dc, rc = cfg_params(2, W, H, 2)
     ref = None
     ctx = pp.Context(0)
-    for hb in (1, 2, 3, 4):
+    for hb in (1, 2, 3, 4, 5, 6):
         for ch in (1, 4):
             ctx.set_tuning(score_hb=hb, score_chunk=ch)
             fo = pp.make_outputs(to_dev(f.depth), (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc)
@@ -459,18 +459,19 @@ def test_culled_scorer_counts_equal_the_plain_scorer(pp, cid, k, size, hyps):
     dc, rc = cfg_params(cid, W, H, k, hyps=hyps)
     log(f"culled scorer cfg={cid} k={k} {W}x{H} hyps={hyps}")
     runs = []
-    for hb in (1, 4):
+    for hb in (1, 4, 5, 6):  # every point; tiles with 1, 2, 4 hypotheses per lane
         ctx = pp.Context(0)
         ctx.set_tuning(score_hb=hb)
         runs.append(run_plain(f, dc, rc, ctx=ctx))
         ctx.close()
-    a, b = runs
-    assert a["n_planes"] == b["n_planes"] and np.array_equal(a["labels"], b["labels"])
-    for key in ("counts", "triples", "round_info"):
-        assert np.array_equal(a["dbg"][key], b["dbg"][key]), key
-    assert np.array_equal(a["dbg"]["hyps"], b["dbg"]["hyps"], equal_nan=True)
-    for pa, pb in zip(a["planes"], b["planes"]):
-        assert np.array_equal(pa["n"], pb["n"]) and pa["d"] == pb["d"] and pa["inliers"] == pb["inliers"]
+    a = runs[0]
+    for b in runs[1:]:
+        assert a["n_planes"] == b["n_planes"] and np.array_equal(a["labels"], b["labels"])
+        for key in ("counts", "triples", "round_info"):
+            assert np.array_equal(a["dbg"][key], b["dbg"][key]), key
+        assert np.array_equal(a["dbg"]["hyps"], b["dbg"]["hyps"], equal_nan=True)
+        for pa, pb in zip(a["planes"], b["planes"]):
+            assert np.array_equal(pa["n"], pb["n"]) and pa["d"] == pb["d"] and pa["inliers"] == pb["inliers"]
     log(f"  {a['n_planes']} planes, counts of {int((a['dbg']['round_info'][:, 0] > 0).sum())} rounds equal")
 
 
@@ -518,17 +519,23 @@ def test_invalid_arguments_are_rejected_before_launch(pp):
 
 
 # ------------------------------------------------------------------ precision forms
-@pytest.mark.parametrize("cid,k", [(1, 0), (2, 1), (3, 1)])
-def test_matrix_core_forms_equal_the_fp32_path_bitwise(pp, cid, k):
-    """FP32-MFMA, BF16 and FP16 scoring (with the recheck band) return the
-    canonical FP32 counts, hence identical planes and labels."""
-    f = scenes.make_frame(cid, k)
+@pytest.mark.parametrize("cid,k,size,hb", [(1, 0, None, 4), (2, 1, None, 4), (3, 1, None, 5), (2, 2, None, 6),
+                                            (4, 0, (1280, 720), 5)])
+def test_matrix_core_forms_equal_the_fp32_path_bitwise(pp, cid, k, size, hb):
+    """FP32-MFMA, BF16 and FP16 scoring (with the recheck band, or the
+    derived bound alone) return the canonical FP32 counts of every round,
+    hence identical planes and labels, at 1, 2 and 4 hypotheses per lane."""
+    f = scenes.make_frame(cid, k, size=size)
     H, W = f.depth.shape
     runs = {}
     for prec, band in [(pp.PP_SCORE_FP32, 0.0), (pp.PP_SCORE_MFMA_F32, 0.0), (pp.PP_SCORE_BF16, 0.002),
-                       (pp.PP_SCORE_FP16, 0.002), (pp.PP_SCORE_BF16, 1e-4), (pp.PP_SCORE_FP16, 0.0)]:
+                       (pp.PP_SCORE_FP16, 0.002), (pp.PP_SCORE_BF16, 1e-4), (pp.PP_SCORE_FP16, 0.0),
+                       (pp.PP_SCORE_BF16, 0.0)]:
         dc, rc = cfg_params(cid, W, H, k, precision=prec, recheck_band_m=band)
-        runs[(prec, band)] = run_plain(f, dc, rc)
+        ctx = pp.Context(0)
+        ctx.set_tuning(score_hb=hb if prec != pp.PP_SCORE_FP32 else 1)
+        runs[(prec, band)] = run_plain(f, dc, rc, ctx=ctx)
+        ctx.close()
     ref = runs[(pp.PP_SCORE_FP32, 0.0)]
     for key, g in runs.items():
         assert g["n_planes"] == ref["n_planes"], key
