@@ -285,70 +285,96 @@ def diffusion_bytes_per_px(iters, T):
     return 2 * P + 4 * (P - 1) + 4 * P
 
 
-def precision_bench(pp, reps=3):
-    """The precision form on two homogeneous batches of 256 frames (1280x720
-    and 848x480 straight-stair frames, 4096 hypotheses): scoring on the vector
-    ALUs, FP32 matrix cores, BF16 and FP16 matrix cores with the 2 mm
-    recheck; outputs must be bitwise identical across forms.  Also the HBM
-    rate of diffusion and normals at a size far above the 256 MB cache.
-    Each batch replicates 8 generated frames 32 times (frame ids differ)."""
+def normals_bytes_per_px(valid_frac):
+    """Algorithmic HBM bytes per pixel of back-projection + normals (float
+    depth 4 B in; points 12, normals 12 and flags 1 B out) and of the valid
+    list (flags 1 B in, 4 B per valid pixel out)."""
+    return 4 + 12 + 12 + 1 + 1 + 4 * valid_frac
+
+
+def hbm_fractions(stage_ms, n_px, iters, T, valid_frac):
+    """Achieved HBM rates of diffusion (a1) and of back-projection, normals and
+    valid list (a2-a4) from their per-step stage times and algorithmic bytes."""
+    out = {}
+    for name, bpp, ms in (("diffusion", diffusion_bytes_per_px(iters, T), stage_ms["diffusion"]),
+                          ("normals_and_valid_list", normals_bytes_per_px(valid_frac), stage_ms["normals"])):
+        gbs = bpp * n_px / (ms * 1e-3) / 1e9
+        out[name] = {"bytes_per_px": round(bpp, 2), "ms_per_step": round(ms, 4), "gb_per_s": round(gbs, 1),
+                     "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 3)}
+    out["target_frac"] = 0.6
+    out["target_met"] = all(v["frac_of_8tbs"] >= 0.6 for k, v in out.items() if isinstance(v, dict))
+    out["note"] = ("diffusion fuses T iterations per pass in registers and is bound by its arithmetic (two exp per "
+                   "pixel and iteration), not by HBM; the normals stage time also covers the 8x8-ordered scoring list "
+                   "build, whose bytes are not counted here")
+    return out
+
+
+def precision_bench(pp, tuning, n_frames=256, size=(1280, 720), reps=2):
+    """The precision form at one size far above the 256 MB cache: a batch of
+    256 straight-stair frames (8 generated, replicated with distinct frame
+    ids), 4096 hypotheses, scored on the vector ALUs (FP32), and on the matrix
+    cores in BF16 and FP16 (recheck band derived from the operands' error
+    bound, and the 2 mm form) and FP32; every form's outputs must be bitwise
+    the FP32 ones.  The diffusion knobs are the main leg's; the scoring block
+    shape is the faster of 128 and 256 hypotheses per block for each form.
+    Also the HBM rates of diffusion and normals at that size."""
     import torch
 
     import scenes
-    from paper_2411_01919_amd import autotune
-    ctx = pp.default_context(0)
     cfg = scenes.CONFIGS[4]
-    out = {}
-    for (W, H) in ((1280, 720), (848, 480)):
-        base = [scenes.make_frame(4, k, size=(W, H)) for k in range(8)]
-        frames = []
-        for i in range(256):
-            f = base[i % 8]
-            d = torch.from_numpy(f.depth.view(np.int16)).to("cuda:0")
-            dc = pp.DiffuseConfig(cfg.diffuse_iters, cfg.lam, cfg.kappa_mm)
-            rc = pp.RansacConfig(cfg.max_planes, cfg.hyps, cfg.min_inliers(W, H), cfg.thresh_m, cfg.ransac_seed, i)
-            frames.append(pp.make_outputs(d, (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc))
-        tun = autotune.tune(frames, ctx=ctx)
-        ctx.set_stage_timing(True)
-        rec = {"tuning": {k: tun[k] for k in ("diffuse_tile", "diffuse_t", "score_hb", "score_chunk")}}
-        ref = None
-        for name, prec, band in (("fp32_valu", pp.PP_SCORE_FP32, 0.0), ("fp32_mfma", pp.PP_SCORE_MFMA_F32, 0.0),
-                                 ("bf16_mfma", pp.PP_SCORE_BF16, 0.002), ("fp16_mfma", pp.PP_SCORE_FP16, 0.002)):
-            for fo in frames:
-                fo.ransac.precision, fo.ransac.recheck_band_m = prec, band
-            best = None
+    W, H = size
+    base = [scenes.make_frame(4, k, size=(W, H)) for k in range(8)]
+    ctx = pp.Context(0)
+    frames = []
+    for i in range(n_frames):
+        f = base[i % 8]
+        d = torch.from_numpy(f.depth.view(np.int16)).to("cuda:0")
+        dc = pp.DiffuseConfig(cfg.diffuse_iters, cfg.lam, cfg.kappa_mm)
+        rc = pp.RansacConfig(cfg.max_planes, cfg.hyps, cfg.min_inliers(W, H), cfg.thresh_m, cfg.ransac_seed, i)
+        frames.append(pp.make_outputs(d, (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc))
+    ctx.set_stage_timing(True)
+    rec = {"workload": f"{n_frames} x {W}x{H} straight staircase, 20 diffusion iterations, up to 12 planes x "
+                       f"{cfg.hyps} hypotheses", "forms": {}}
+    ref = None
+    fp32_ms = None
+    for name, prec, band in (("fp32_valu", pp.PP_SCORE_FP32, 0.0), ("bf16_mfma", pp.PP_SCORE_BF16, 0.0),
+                             ("fp16_mfma", pp.PP_SCORE_FP16, 0.0), ("fp32_mfma", pp.PP_SCORE_MFMA_F32, 0.0),
+                             ("bf16_mfma_2mm", pp.PP_SCORE_BF16, 0.002)):
+        for fo in frames:
+            fo.ransac.precision, fo.ransac.recheck_band_m = prec, band
+        best = None
+        for hb in (5, 6):
+            ctx.set_tuning(tuning["diffuse_tile"], tuning["diffuse_t"], hb, tuning["score_chunk"])
             for r in range(reps + 1):
                 a = time.perf_counter()
                 pp.batch_run(frames, graph=False, ctx=ctx)
                 torch.cuda.synchronize()
                 wall = time.perf_counter() - a
                 br = ctx.stage_breakdown()
-                if r and (best is None or wall < best[0]):
-                    best = (wall, br)
-            snap = [(int(fo.n_planes.cpu().item()), fo.planes.cpu().numpy().tobytes(), fo.labels.cpu().numpy())
-                    for fo in frames[:16]]
-            if ref is None:
-                ref = snap
-            same = all(a[0] == b[0] and a[1] == b[1] and np.array_equal(a[2], b[2]) for a, b in zip(snap, ref))
-            wall, br = best
-            rec[name] = {"frames_per_s": round(256 / wall, 2), "scoring_ms": round(br["scoring"], 3),
-                         "identical_to_fp32": bool(same)}
-            log(f"precision {W}x{H} {name}: {rec[name]}")
-        px = 256 * W * H
-        br = ctx.stage_breakdown()
-        T = ctx.get_tuning()["diffuse_t"]
-        dbytes = diffusion_bytes_per_px(cfg.diffuse_iters, T) * px
-        nbytes = 50 * px  # normals 4 in + 25 out, valid list 1 in + 20 out per pixel (upper bound)
-        rec["diffusion_hbm"] = {"gb_per_s": round(dbytes / (br["diffusion"] * 1e-3) / 1e9, 1),
-                                "frac_of_8tbs": round(dbytes / (br["diffusion"] * 1e-3) / 8e12, 3),
-                                "bytes_per_px": diffusion_bytes_per_px(cfg.diffuse_iters, T), "ms": round(br["diffusion"], 3)}
-        rec["normals_hbm"] = {"gb_per_s": round(nbytes / (br["normals"] * 1e-3) / 1e9, 1),
-                              "frac_of_8tbs": round(nbytes / (br["normals"] * 1e-3) / 8e12, 3), "ms": round(br["normals"], 3)}
-        ctx.set_stage_timing(False)
-        out[f"{W}x{H}x256"] = rec
-        del frames
-        torch.cuda.empty_cache()
-    return out
+                if r and (best is None or br["scoring"] < best[1]["scoring"]):
+                    best = (wall, br, hb)
+        snap = [(int(fo.n_planes.cpu().item()), fo.planes.cpu().numpy().tobytes(), fo.labels.cpu().numpy())
+                for fo in frames[:16]]
+        if ref is None:
+            ref = snap
+        same = all(a[0] == b[0] and a[1] == b[1] and np.array_equal(a[2], b[2]) for a, b in zip(snap, ref))
+        wall, br, hb = best
+        if fp32_ms is None:
+            fp32_ms = br["scoring"]
+        rec["forms"][name] = {"frames_per_s": round(n_frames / wall, 2), "scoring_ms": round(br["scoring"], 3),
+                              "scoring_vs_fp32_valu": round(br["scoring"] / fp32_ms, 3), "score_hb": hb,
+                              "recheck_band_m": band, "identical_to_fp32": bool(same)}
+        log(f"precision {W}x{H} {name}: {rec['forms'][name]}")
+        if name == "fp32_valu":
+            T = tuning["diffuse_t"]
+            valid_frac = float(np.mean([(f.depth > 0).mean() for f in base]))
+            rec["hbm"] = hbm_fractions(br, n_frames * W * H, cfg.diffuse_iters, T, valid_frac)
+            rec["stage_ms"] = {k: round(v, 3) for k, v in br.items()}
+    ctx.set_stage_timing(False)
+    ctx.close()
+    del frames
+    torch.cuda.empty_cache()
+    return rec
 
 
 def ragged_bench(pp, steps=20, warmup=3, n_frames=64):
@@ -468,7 +494,8 @@ def main():
     ap.add_argument("--served-sweep-seconds", type=float, default=5.0, help="seconds per rate multiplier")
     ap.add_argument("--served-lanes", type=int, default=4, help="concurrent batches (streams) of the server, 1 to 4")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--c4", action="store_true", help="add the precision-form leg (two batches of 256 large frames)")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the precision-form leg (256 frames of 1280x720, FP32 / BF16 / FP16 scoring)")
     ap.add_argument("--tuning", type=str, default="", help="tile,T,hb,chunk (1-based knobs) instead of autotuning")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mfma_f32", "bf16", "fp16"],
                     help="scoring form of the batched and plain legs (all give identical results)")
@@ -577,6 +604,17 @@ def main():
         planes_tot += n
     score_ms_step = score_ms / args.steps
     achieved = res_step * FLOPS_PER_RESIDUAL / (score_ms_step * 1e-3) / 1e12
+    # residuals the scorer actually evaluated (the tile boxes decide the other pairs), from its
+    # introspection counters on the same frames through the per-frame path (same kernels, same decisions)
+    evaluated = decided = 0
+    if args.precision == "fp32" and int(tuning.get("score_hb", 0)) >= 4:
+        for fo in outs:
+            dbg = pp.ransac_planes_debug(fo.points, fo.valid, fo.ransac, ctx=ctx)[3]
+            sc = dbg["scored"].cpu().numpy()
+            decided += int(sc[0])
+            evaluated += int(sc[1])
+    hbm = hbm_fractions({k: v / args.steps for k, v in stage_ms.items()}, args.batch * W * H, cfg.diffuse_iters,
+                        int(tuning["diffuse_t"]), float(np.mean([(f.depth > 0).mean() for f in frames])))
     khash = source_hash()
     traffic = load_traffic(khash)
 
@@ -624,9 +662,9 @@ def main():
         log(f"served: {served}")
 
     precision = None
-    if args.c4:
-        log("precision-form leg")
-        precision = precision_bench(pp)
+    if not args.no_precision:
+        log("precision-form leg: 256 frames of 1280x720")
+        precision = precision_bench(pp, tuning)
 
     chain = None
     if not args.no_chain:
@@ -674,11 +712,21 @@ def main():
         "roofline": {"bound": "alu", "kernel": score_kernel_name(args.precision, tuning),
                      "achieved": round(achieved, 3), "peak": round(FP32_VECTOR_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
                      "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": traffic,
+                     "kind": "effective: the method's residuals over the kernel time; the tile boxes decide most "
+                             "(tile, hypothesis) pairs without evaluating their residuals",
                      "ceiling_without_packed_fp32": round(VALU_FMA_TFLOPS, 1),
                      "flops": "the method's residuals, |R_r| x H per round, 6 flop each (3 FMA)",
                      "residuals_per_step": res_step, "launches_per_step": score_launches // max(1, args.steps),
                      "avg_launch_ms": round(score_ms / max(1, score_launches), 4),
+                     "evaluated_residuals_per_step": evaluated or None,
+                     "box_decided_pairs_per_step": decided or None,
+                     "evaluated_fraction": round(evaluated / res_step, 4) if evaluated else None,
+                     "evaluated_tflops": round(evaluated * FLOPS_PER_RESIDUAL / (score_ms_step * 1e-3) / 1e12, 3)
+                     if evaluated else None,
+                     "evaluated_frac_of_fma_ceiling": round(evaluated * FLOPS_PER_RESIDUAL / (score_ms_step * 1e-3)
+                                                            / 1e12 / VALU_FMA_TFLOPS, 4) if evaluated else None,
                      "kernel_source_hash": khash},
+        "hbm": hbm,
         "cpu_baseline": base,
         "paper_context": "> 30 Hz per frame (whole pipeline incl. Canny/contours, per-polygon RANSAC) on an "
                          "i9-13900HX + RTX 4060 laptop GPU; not this workload",

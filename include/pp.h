@@ -141,7 +141,11 @@ typedef struct {
  * when sampling gave up), round_info [max_planes][4] = (j*, |S|, |F|, status:
  * 0 plane emitted, 1 no valid hypothesis, 2 |F| < min_inliers, -1 not run),
  * masks [max_planes][height*width] (bit0: inlier of j*, bit1: in F),
- * valid_list [height*width] (pixel offsets y*pitch+x) and n_valid [1]. */
+ * valid_list [height*width] (pixel offsets y*pitch+x) and n_valid [1];
+ * scored [2], caller-zeroed, added to by the tile-culled scorers over all
+ * rounds: [0] (64-point tile, hypothesis) pairs decided by the tile's
+ * bounding box, [1] residuals evaluated point by point (64 per undecided
+ * pair). */
 typedef struct {
     int32_t* counts;
     float* hyps;
@@ -150,6 +154,7 @@ typedef struct {
     uint8_t* masks;
     int32_t* valid_list;
     int32_t* n_valid;
+    unsigned long long* scored;
 } pp_ransac_debug;
 
 /* ---------------------------------------------------------------- context */

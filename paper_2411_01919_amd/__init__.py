@@ -263,7 +263,8 @@ def ransac_planes_noalloc(points, valid, cfg: RansacConfig, planes, n_planes, la
 
 def ransac_planes_debug(points, valid, cfg: RansacConfig, ctx: Optional[Context] = None, stream=None):
     """ransac_planes plus per-round introspection (hypotheses, triples,
-    counts, round info, S/F masks, valid list)."""
+    counts, round info, S/F masks, valid list, the tile scorer's decided
+    pairs and evaluated residuals)."""
     torch = _torch()
     _, H, W = points.shape
     dev = points.device
@@ -277,9 +278,10 @@ def ransac_planes_debug(points, valid, cfg: RansacConfig, ctx: Optional[Context]
         masks=torch.zeros((R, H * W), dtype=torch.uint8, device=dev),
         valid_list=torch.zeros((H * W,), dtype=torch.int32, device=dev),
         n_valid=torch.zeros((1,), dtype=torch.int32, device=dev),
+        scored=torch.zeros((2,), dtype=torch.int64, device=dev),
     )
     dbg = N.RansacDebug(*[_ptr(dbg_t[k]) for k in ("counts", "hyps", "triples", "round_info", "masks",
-                                                      "valid_list", "n_valid")])
+                                                      "valid_list", "n_valid", "scored")])
     ctx = ctx or default_context(dev.index)
     p = cfg.c()
     ctx.check(N.lib().pp_ransac_planes_dbg(ctx.h, _ptr(points), _ptr(valid), _desc(H, W), ctypes.byref(p),

@@ -45,7 +45,7 @@ class Plane(ctypes.Structure):
 
 class RansacDebug(ctypes.Structure):
     _fields_ = [("counts", c_vp), ("hyps", c_vp), ("triples", c_vp), ("round_info", c_vp), ("masks", c_vp),
-                ("valid_list", c_vp), ("n_valid", c_vp)]
+                ("valid_list", c_vp), ("n_valid", c_vp), ("scored", c_vp)]
 
 
 class RegionDebug(ctypes.Structure):

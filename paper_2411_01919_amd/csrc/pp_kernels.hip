@@ -1310,9 +1310,11 @@ __global__ __launch_bounds__(kBlock) void k_score_tiles(const FrameDev* __restri
         e_next = ld_global4(box, 2 * tile + 1);
         p_next = ld_global_xyz(pts, min(tile * 64 + lane, M - 1));
     }
+    uint32_t n_tiles = 0, n_straddle = 0;  // this wave's tiles and undecided pairs (introspection)
     for (; tile < ntiles; tile += tstride) {
         const float4 c = c_next, e = e_next;
         float3 p = p_next;
+        ++n_tiles;
         if (tile + tstride < ntiles) {
             c_next = ld_global4(box, 2 * (tile + tstride));
             e_next = ld_global4(box, 2 * (tile + tstride) + 1);
@@ -1331,6 +1333,7 @@ __global__ __launch_bounds__(kBlock) void k_score_tiles(const FrameDev* __restri
             ns += __popcll(S[q]);
         }
         if (ns == 0) continue;
+        n_straddle += ns;
         if (tile * 64 + lane >= M) p = make_float3(qnan, qnan, qnan);
         if (!MF || ns < kMfmaMinStraddlers) {
             asm volatile("" : "+v"(p.x), "+v"(p.y), "+v"(p.z));  // keeps the select out of the loops below
@@ -1365,6 +1368,11 @@ __global__ __launch_bounds__(kBlock) void k_score_tiles(const FrameDev* __restri
     for (int q = 0; q < Q; ++q) {
         const int v = (int)cnt[q] + w[q];
         if (v) atomicAdd(&s_cnt[q * 64 + lane], v);
+    }
+    if (f.dbg.scored && lane == 0 && n_tiles) {
+        const uint32_t nvalid = (uint32_t)min(NH, hyps - h0);
+        atomicAdd(f.dbg.scored, (unsigned long long)n_tiles * nvalid - n_straddle);
+        atomicAdd(f.dbg.scored + 1, 64ull * n_straddle);
     }
     __syncthreads();
     for (int j = threadIdx.x; j < NH; j += kBlock) {
