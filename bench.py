@@ -309,7 +309,7 @@ def hbm_fractions(stage_ms, n_px, iters, T, valid_frac):
     return out
 
 
-def precision_bench(pp, tuning, n_frames=256, size=(1280, 720), reps=2):
+def precision_bench(pp, tuning, n_frames=256, size=(1280, 720), reps=2, forms=None):
     """The precision form at one size far above the 256 MB cache: a batch of
     256 straight-stair frames (8 generated, replicated with distinct frame
     ids), 4096 hypotheses, scored on the vector ALUs (FP32), and on the matrix
@@ -340,6 +340,8 @@ def precision_bench(pp, tuning, n_frames=256, size=(1280, 720), reps=2):
     for name, prec, band in (("fp32_valu", pp.PP_SCORE_FP32, 0.0), ("bf16_mfma", pp.PP_SCORE_BF16, 0.0),
                              ("fp16_mfma", pp.PP_SCORE_FP16, 0.0), ("fp32_mfma", pp.PP_SCORE_MFMA_F32, 0.0),
                              ("bf16_mfma_2mm", pp.PP_SCORE_BF16, 0.002)):
+        if forms and name not in forms:
+            continue
         for fo in frames:
             fo.ransac.precision, fo.ransac.recheck_band_m = prec, band
         best = None
@@ -496,6 +498,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the precision-form leg (256 frames of 1280x720, FP32 / BF16 / FP16 scoring)")
+    ap.add_argument("--precision-forms", type=str, default="",
+                    help="comma list of the precision leg's forms to run (fp32_valu first), default all")
     ap.add_argument("--tuning", type=str, default="", help="tile,T,hb,chunk (1-based knobs) instead of autotuning")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "mfma_f32", "bf16", "fp16"],
                     help="scoring form of the batched and plain legs (all give identical results)")
@@ -664,7 +668,7 @@ def main():
     precision = None
     if not args.no_precision:
         log("precision-form leg: 256 frames of 1280x720")
-        precision = precision_bench(pp, tuning)
+        precision = precision_bench(pp, tuning, forms=[x for x in args.precision_forms.split(",") if x])
 
     chain = None
     if not args.no_chain:

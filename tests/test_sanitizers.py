@@ -75,7 +75,7 @@ def test_scheduler_under_tsan(tmp_path):
            os.path.join(ROOT, "tests", "native", "server_tsan.cpp"), "-o", str(exe), "-lpthread"]
     subprocess.check_call(cmd, cwd=tmp_path)
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1:second_deadlock_stack=1")
-    r = subprocess.run([str(exe)], env=env, capture_output=True, text=True, timeout=300)
+    r = subprocess.run([str(exe)], env=env, capture_output=True, text=True, timeout=900)
     out = r.stdout + r.stderr
     assert "ThreadSanitizer" not in out, out[-4000:]
     assert r.returncode == 0 and "server_tsan ok" in out, out[-4000:]
