@@ -174,17 +174,18 @@ bool intrinsics_ok(const pp_intrinsics& K) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t delta, L, list, taken, hyp, hyp_p0, triples, counts, partials, chunk_cnt, chunk_cnt_q, tbox, st, total;
+    size_t delta, L, list, taken, hyp, hyp_p0, triples, counts, partials, chunk_cnt, chunk_cnt_q, tbox, chunk_run, st, total;
 };
 
 Layout slot_layout(size_t px, int hyps) {
     Layout l;
-    const size_t nch_refit = (px + ppk::kRefitChunk - 1) / ppk::kRefitChunk;
+    const size_t cap = ppk::list_capacity(px);
+    const size_t nch_refit = (cap + ppk::kRefitChunk - 1) / ppk::kRefitChunk;
     const size_t nch_valid = (px + ppk::kValidChunk - 1) / ppk::kValidChunk;
     size_t o = 0;
     l.delta = o; o += align256(2 * px * sizeof(float));
     l.L = o; o += align256(px * sizeof(int32_t));
-    l.list = o; o += align256(2 * px * sizeof(float4));
+    l.list = o; o += align256(2 * cap * sizeof(float4));
     l.taken = o; o += align256((px + 3) / 4 * 4);
     l.hyp = o; o += align256((size_t)hyps * sizeof(float4));
     l.hyp_p0 = o; o += align256((size_t)hyps * sizeof(float4));
@@ -194,7 +195,8 @@ Layout slot_layout(size_t px, int hyps) {
     l.chunk_cnt = o; o += align256(std::max(nch_refit, nch_valid) * sizeof(int32_t));
     // the padded 8x8-block scan of a frame of px pixels (each side >= 3) covers at most 3.4 px + 70 positions
     l.chunk_cnt_q = o; o += align256(((4 * px + 4096) / ppk::kValidChunk + 1) * sizeof(int32_t));
-    l.tbox = o; o += align256((px + 63) / 64 * 2 * sizeof(float4));
+    l.tbox = o; o += align256(cap / 64 * 2 * sizeof(float4));
+    l.chunk_run = o; o += align256(nch_refit * sizeof(int32_t));
     l.st = o; o += align256(sizeof(RoundState));
     l.total = o;
     return l;
@@ -236,7 +238,7 @@ void bind_layout(char* b, size_t px_cap, int hyp_cap, FrameDev& f) {
     f.delta[1] = f.delta[0] + px_cap;
     f.L = reinterpret_cast<int32_t*>(b + l.L);
     f.list[0] = reinterpret_cast<float4*>(b + l.list);
-    f.list[1] = f.list[0] + px_cap;
+    f.list[1] = f.list[0] + ppk::list_capacity(px_cap);
     f.taken = reinterpret_cast<uint8_t*>(b + l.taken);
     f.hyp = reinterpret_cast<float4*>(b + l.hyp);
     f.hyp_p0 = reinterpret_cast<float4*>(b + l.hyp_p0);
@@ -246,6 +248,7 @@ void bind_layout(char* b, size_t px_cap, int hyp_cap, FrameDev& f) {
     f.chunk_cnt = reinterpret_cast<int32_t*>(b + l.chunk_cnt);
     f.chunk_cnt_q = reinterpret_cast<int32_t*>(b + l.chunk_cnt_q);
     f.tbox = reinterpret_cast<float4*>(b + l.tbox);
+    f.chunk_run = reinterpret_cast<int32_t*>(b + l.chunk_run);
     f.st = reinterpret_cast<RoundState*>(b + l.st);
 }
 

@@ -21,24 +21,27 @@ constexpr int kScanBlock = 8;     // the scoring list walks the image in 8x8-pix
 // Per-frame RANSAC state in device memory.  Fields indexed by the round r are
 // written only by an earlier kernel than the ones that read them, so no
 // kernel reads a field another block of the same launch may be writing.
-// One round's flags, read together by a single 16-byte scalar load.
+// One round's flags, read together by a single 32-byte scalar load.
 struct RoundRec {
     int32_t active;  // round r runs iff active
     int32_t M;       // |R_r|: unassigned points entering round r
     int32_t stop;    // round r found no valid hypothesis
     int32_t jstar;
+    int32_t Mlen;    // length of round r's point list: R_r in order, each chunk's run padded with NaN points
+                     // to a multiple of 64 (every 64-point tile lies inside one chunk's run)
+    int32_t pad[3];
 };
 
 struct RoundState {
     int32_t M0;                        // |L|: depth-valid pixels
     uint32_t p1max_bits;               // max |x|+|y|+|z| over the frame's points (float bits)
     int32_t s_count;
-    int32_t pad;
+    int32_t pad[5];
     RoundRec round[kMaxRounds + 1];
     double plane[4];                   // refit plane of the current round
     double centroid[3];
 };
-static_assert(offsetof(RoundState, M0) == 0 && offsetof(RoundState, round) % 16 == 0, "RoundState layout");
+static_assert(offsetof(RoundState, M0) == 0 && offsetof(RoundState, round) % 32 == 0, "RoundState layout");
 
 // Everything a kernel needs about one frame.  Kernels read a table of these
 // from device memory and take the frame index from blockIdx.z.
@@ -69,7 +72,7 @@ struct FrameDev {
     // library scratch
     float* delta[2];         // [H][W] diffusion ping-pong (delta = I - I0)
     int32_t* L;              // [W*H] valid list (pixel offsets y*pitch+x)
-    float4* list[2];         // [W*H] remaining points (x, y, z, valid-list position bits)
+    float4* list[2];         // [list capacity] remaining points (x, y, z, valid-list position bits), NaN padding
     uint8_t* taken;          // [W*H rounded up to 4] 1 iff the point at valid-list position k is assigned
     float4* hyp;             // [hyps] (n, d); d = NaN when invalid
     float4* hyp_p0;          // [hyps] the first point of each hypothesis' triple (the refit's moment origin)
@@ -78,8 +81,9 @@ struct FrameDev {
     double* partials;        // [refit chunks][10]
     int32_t* chunk_cnt;      // [max(valid chunks, refit chunks)]
     int32_t* chunk_cnt_q;    // [block-order chunks] depth-valid pixels per 1024 positions of the 8x8-block scan
-    float4* tbox;            // [ceil(W*H/64)][2] per 64-point tile of the current list: centre (w: point
-                             // count bits) and half extents of its bounding box
+    float4* tbox;            // [list tiles][2] per 64-point tile of the current list: centre (w: count of
+                             // its points that are not padding) and half extents of their bounding box
+    int32_t* chunk_run;      // [refit chunks] padded length of each chunk's run of survivors
     RoundState* st;
     // introspection (may be null)
     pp_ransac_debug dbg;
@@ -109,6 +113,7 @@ hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, int maxW, 
 hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_hyps, int precision,
                         const Tuning& tu, hipStream_t s, hipEvent_t score_start = nullptr,
                         hipEvent_t score_end = nullptr);
+size_t list_capacity(size_t px);
 hipError_t launch_hyp_from_triples(const FrameDev* tab, const int32_t* triples, int n, hipStream_t s);
 hipError_t launch_score_only(const FrameDev* tab, int max_px, int n, int precision, const Tuning& tu,
                              hipStream_t s);

@@ -6,17 +6,18 @@
 //                    (one wave per column strip); k_diffuse: the same on LDS tiles
 //   k_normals        back-projection (Alg. 2) + Sobel normal image (Eq. 2)
 //   k_valid_*,       row-major list of depth-valid pixels (Alg. 2 point set) and
-//   k_list_scatter   the round-0 scoring list in 8x8-block order
-//   k_round_start    3-point hypotheses from Philox4x64-10 (Alg. 2) and the
-//                    bounding boxes of the round's 64-point tiles
+//   k_list_scatter   the round-0 scoring list in 8x8-block order with the
+//                    bounding boxes of its 64-point tiles
+//   k_round_start    3-point hypotheses from Philox4x64-10 (Alg. 2)
 //   k_score_tiles    inlier counts, point-to-plane distance < t (Eq. 3, Alg. 2):
 //                    tiles decided from their boxes, the rest point by point
 //                    on the vector ALUs or the matrix cores (k_score: every
 //                    point)
 //   k_refit_*        selection of j*, FP64 moments of its inliers, the
-//                    least-squares plane (Jacobi, solved in every block of the
-//                    final pass) and its inliers per chunk
-//   k_apply          remove / label the refit plane's inliers, next round
+//                    least-squares plane (solved in every block of the final
+//                    pass) and its inliers per chunk
+//   k_apply          remove / label the refit plane's inliers; the next
+//                    round's list with the boxes of its tiles
 //
 // Every kernel takes a device table of FrameDev and reads its frame from
 // blockIdx.z (k_round_start: from a 1-D grid, XCD-aware for the hypotheses),
@@ -46,10 +47,10 @@ __device__ __forceinline__ bool hyp_valid(const float4 h) { return h.w == h.w; }
 // Round r's flags by one scalar load.  No kernel writes the record it reads
 // this way (each round's record is written by the kernels before it).
 __device__ __forceinline__ RoundRec round_rec(const FrameDev& f, int r) {
-    typedef int v4i_t __attribute__((ext_vector_type(4)));
-    typedef const __attribute__((address_space(4))) v4i_t* ci4_ptr;
-    const v4i_t v = ((ci4_ptr)(f.st->round + r))[0];
-    return RoundRec{v.x, v.y, v.z, v.w};
+    typedef int v8i_t __attribute__((ext_vector_type(8)));
+    typedef const __attribute__((address_space(4))) v8i_t* ci8_ptr;
+    const v8i_t v = ((ci8_ptr)(f.st->round + r))[0];
+    return RoundRec{v[0], v[1], v[2], v[3], v[4], {v[5], v[6], v[7]}};
 }
 
 // exp(-(x/kappa)^2) as 2^-a with the hardware exponential (v_exp_f32, about
@@ -687,12 +688,116 @@ __device__ __forceinline__ float3 load_point_g(const FrameDev& f, int off) {
     return make_float3(p[off], p[plane + off], p[2 * plane + off]);
 }
 
+// Floats as integers of the same order (the sign-magnitude bits of negative
+// values flipped), so that min / max over a wave are integer DPP min / max.
+__device__ __forceinline__ int ordered_bits(float v) {
+    const int b = __float_as_int(v);
+    return b ^ ((b >> 31) & 0x7FFFFFFF);
+}
+__device__ __forceinline__ float from_ordered_bits(int b) { return __int_as_float(b ^ ((b >> 31) & 0x7FFFFFFF)); }
+
+// min / max over the wave with DPP lane permutes (no LDS): pairs, quads, rows
+// of 16 by rotation, then the row broadcasts; lane 63 ends with the result.
+template <bool MAX>
+__device__ __forceinline__ int wave_extreme_to_lane63(int v) {
+    v = dpp_ext<MAX, 0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_ext<MAX, 0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_ext<MAX, 0x124>(v);  // row_ror:4
+    v = dpp_ext<MAX, 0x128>(v);  // row_ror:8
+    v = dpp_ext<MAX, 0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_ext<MAX, 0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+__device__ __forceinline__ int align64(int n) { return (n + 63) & ~63; }
+
+// The padding entry of a point list: NaN coordinates, which no residual test
+// passes, so padding is never an inlier, never kept, and never in a box.
+__device__ __forceinline__ float4 pad_point() {
+    const float qnan = __int_as_float(0x7fc00000);
+    return make_float4(qnan, qnan, qnan, __int_as_float(-1));
+}
+
+// min / max over each row of 16 lanes (quad permutes and row rotations):
+// every lane of the row ends with the row's result.
+template <bool MAX>
+__device__ __forceinline__ int row_extreme(int v) {
+    v = dpp_ext<MAX, 0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_ext<MAX, 0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_ext<MAX, 0x124>(v);  // row_ror:4
+    v = dpp_ext<MAX, 0x128>(v);  // row_ror:8
+    return v;
+}
+__device__ __forceinline__ int row_sum(int v) {
+    v = dpp_add<0xB1>(v);
+    v = dpp_add<0x4E>(v);
+    v = dpp_add<0x124>(v);
+    v = dpp_add<0x128>(v);
+    return v;
+}
+
+// Bounding boxes of ntiles consecutive 64-point tiles of a list held at src
+// (LDS or global memory the block has written), over their points that are
+// not padding: box[2 t] = centre (w: their count as integer bits), box[2 t +
+// 1] = half extents.  The calling wave takes tiles in groups of 4 (group g,
+// g + step, ...): a 16-lane row per tile, 4 consecutive points per lane,
+// reduced first in the lane (float min / max, which pass over NaN), then
+// across the row as order-preserving integers (each permute folds into its
+// v_min_i32_dpp / v_max_i32_dpp).
+__device__ __forceinline__ void tile_boxes(const float4* src, int ntiles, float4* box, int g, int step) {
+    const int lane = threadIdx.x & 63, row = lane >> 4, i = lane & 15;
+    for (; g * 4 < ntiles; g += step) {
+        const int tile = g * 4 + row;
+        float4 q[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q[j] = tile < ntiles ? src[tile * 64 + 4 * i + j] : pad_point();
+        float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
+        int n = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            lx = fminf(lx, q[j].x); ly = fminf(ly, q[j].y); lz = fminf(lz, q[j].z);
+            hx = fmaxf(hx, q[j].x); hy = fmaxf(hy, q[j].y); hz = fmaxf(hz, q[j].z);
+            n += q[j].x == q[j].x ? 1 : 0;
+        }
+        lx = from_ordered_bits(row_extreme<false>(ordered_bits(lx)));
+        ly = from_ordered_bits(row_extreme<false>(ordered_bits(ly)));
+        lz = from_ordered_bits(row_extreme<false>(ordered_bits(lz)));
+        hx = from_ordered_bits(row_extreme<true>(ordered_bits(hx)));
+        hy = from_ordered_bits(row_extreme<true>(ordered_bits(hy)));
+        hz = from_ordered_bits(row_extreme<true>(ordered_bits(hz)));
+        n = row_sum(n);
+        if (i == 15 && tile < ntiles) {
+            const float cx = 0.5f * (lx + hx), cy = 0.5f * (ly + hy), cz = 0.5f * (lz + hz);
+            // the rounded differences may fall short of the true ones by an ulp: widen by 2^-20
+            const float w = 1.0f + 9.5367432e-7f;
+            const float ex = fmaxf(hx - cx, cx - lx) * w, ey = fmaxf(hy - cy, cy - ly) * w,
+                        ez = fmaxf(hz - cz, cz - lz) * w;
+            box[2 * tile] = make_float4(cx, cy, cz, __int_as_float(n));
+            box[2 * tile + 1] = make_float4(ex, ey, ez, 0.f);
+        }
+    }
+}
+
+// Writes a chunk's run of n points, staged in LDS in list order, to the
+// list at position start (a multiple of 64), padded to a multiple of 64, and
+// the boxes of its tiles; the block's four waves take the tiles in turn.
+__device__ __forceinline__ void store_run(float4* stage, int n, float4* out, float4* tbox, int start) {
+    const int wave = threadIdx.x >> 6;
+    const int padded = align64(n);
+    for (int i = n + (int)threadIdx.x; i < padded; i += kBlock) stage[i] = pad_point();
+    __syncthreads();
+    for (int i = threadIdx.x; i < padded; i += kBlock) out[start + i] = stage[i];
+    tile_boxes(stage, padded >> 6, tbox + 2 * (start >> 6), wave, kBlock / 64);
+}
+
 // The first RANSAC round's scoring list: the depth-valid points in 8x8-block scan order,
 // each tagged with its valid-list position (w), by ordered compaction over
-// chunks of 1024 scan positions.
+// chunks of 1024 scan positions; each chunk's run is padded to a multiple of
+// 64 points, and the tile boxes of the run are made here.
 __global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restrict__ tab) {
     constexpr int S = kValidChunk / kBlock;
     __shared__ int sh[4 * S];
+    __shared__ float4 stage[kValidChunk];
     const FrameDev& f = tab[blockIdx.z];
     const int nq = scan_positions(f);
     const int nchq = (nq + kValidChunk - 1) / kValidChunk;
@@ -701,12 +806,14 @@ __global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restr
     const gu8_cptr vg = (gu8_cptr)f.valid;
     const gf32_cptr pg = (gf32_cptr)f.pts;
     const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt_q;
-    // valid pixels before scan chunk c, carried from this block's previous chunk
+    // list position of scan chunk c's run (the padded runs of the chunks
+    // before it), carried from this block's previous chunk
     int run = 0;
     for (int c = blockIdx.x; c < nchq; c += gridDim.x) {
         {
             int add = 0;
-            for (int i = c - (c == (int)blockIdx.x ? c : (int)gridDim.x) + threadIdx.x; i < c; i += kBlock) add += ccnt[i];
+            for (int i = c - (c == (int)blockIdx.x ? c : (int)gridDim.x) + threadIdx.x; i < c; i += kBlock)
+                add += align64(ccnt[i]);
             run += block_sum(add, sh);
         }
         int off[S], lp[S];
@@ -735,7 +842,10 @@ __global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restr
         block_rank_steps<S>(v, sh, rank, tot);
 #pragma unroll
         for (int k = 0; k < S; ++k)
-            if (v[k]) f.list[0][run + rank[k]] = make_float4(px[k], py[k], pz[k], __int_as_float(lp[k]));
+            if (v[k]) stage[rank[k]] = make_float4(px[k], py[k], pz[k], __int_as_float(lp[k]));
+        store_run(stage, tot, f.list[0], f.tbox, run);
+        if (c == nchq - 1 && threadIdx.x == 0) f.st->round[0].Mlen = run + align64(tot);
+        __syncthreads();  // the stage is reused by the next chunk
     }
 }
 
@@ -944,7 +1054,7 @@ __global__ __launch_bounds__(kBlock) void k_score(const FrameDev* __restrict__ t
     const FrameDev& f = tab[blockIdx.z];
     const RoundRec rr = round_rec(f, r);
     if (!rr.active) return;
-    score_block<HB>(f, r, rr.M);
+    score_block<HB>(f, r, rr.Mlen);
 }
 
 // ------------------------------------------------------------------ culled scoring
@@ -966,82 +1076,13 @@ __device__ __forceinline__ float3 ld_global_xyz(const float4* p, int i) {
     return make_float3(v.x, v.y, v.z);
 }
 
-// Floats as integers of the same order (the sign-magnitude bits of negative
-// values flipped), so that min / max over a wave are integer DPP min / max.
-__device__ __forceinline__ int ordered_bits(float v) {
-    const int b = __float_as_int(v);
-    return b ^ ((b >> 31) & 0x7FFFFFFF);
-}
-__device__ __forceinline__ float from_ordered_bits(int b) { return __int_as_float(b ^ ((b >> 31) & 0x7FFFFFFF)); }
 
-// min / max over the wave with DPP lane permutes (no LDS): pairs, quads, rows
-// of 16 by rotation, then the row broadcasts; lane 63 ends with the result.
-template <bool MAX>
-__device__ __forceinline__ int wave_extreme_to_lane63(int v) {
-    v = dpp_ext<MAX, 0xB1>(v);   // quad_perm [1,0,3,2]
-    v = dpp_ext<MAX, 0x4E>(v);   // quad_perm [2,3,0,1]
-    v = dpp_ext<MAX, 0x124>(v);  // row_ror:4
-    v = dpp_ext<MAX, 0x128>(v);  // row_ror:8
-    v = dpp_ext<MAX, 0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    v = dpp_ext<MAX, 0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-    return v;
-}
-
-constexpr int kBoxTilesPerWave = 4;
-
-// Bounding boxes of round r's 64-point tiles: block bx of nbx for frame f.
-__device__ __forceinline__ void tile_box_block(const FrameDev& f, int r, int bx, int nbx) {
-    const RoundRec rr = round_rec(f, r);
-    if (!rr.active) return;
-    const int M = rr.M;
-    const int ntiles = (M + 63) >> 6;
-    const int lane = threadIdx.x & 63;
-    const float4* __restrict__ pts = f.list[r & 1];
-    const int wave_stride = nbx * (kBlock / 64) * kBoxTilesPerWave;
-    for (int t0 = (bx * (kBlock / 64) + (threadIdx.x >> 6)) * kBoxTilesPerWave; t0 < ntiles; t0 += wave_stride) {
-        // all of this wave's tiles in flight at once; lanes past the end repeat the last point
-        float4 p[kBoxTilesPerWave];
-#pragma unroll
-        for (int q = 0; q < kBoxTilesPerWave; ++q) p[q] = ld_global4(pts, min((t0 + q) * 64 + lane, M - 1));
-#pragma unroll
-        for (int q = 0; q < kBoxTilesPerWave; ++q) {
-            const int tile = t0 + q;
-            if (tile >= ntiles) break;
-            const int bx = ordered_bits(p[q].x), by = ordered_bits(p[q].y), bz = ordered_bits(p[q].z);
-            const float lx = from_ordered_bits(wave_extreme_to_lane63<false>(bx));
-            const float hx = from_ordered_bits(wave_extreme_to_lane63<true>(bx));
-            const float ly = from_ordered_bits(wave_extreme_to_lane63<false>(by));
-            const float hy = from_ordered_bits(wave_extreme_to_lane63<true>(by));
-            const float lz = from_ordered_bits(wave_extreme_to_lane63<false>(bz));
-            const float hz = from_ordered_bits(wave_extreme_to_lane63<true>(bz));
-            if (lane == 63) {
-                const float cx = 0.5f * (lx + hx), cy = 0.5f * (ly + hy), cz = 0.5f * (lz + hz);
-                // the rounded differences may fall short of the true ones by an ulp: widen by 2^-20
-                const float w = 1.0f + 9.5367432e-7f;
-                const float ex = fmaxf(hx - cx, cx - lx) * w, ey = fmaxf(hy - cy, cy - ly) * w,
-                            ez = fmaxf(hz - cz, cz - lz) * w;
-                const int n = min(64, M - tile * 64);
-                f.tbox[2 * tile] = make_float4(cx, cy, cz, __int_as_float(n));
-                f.tbox[2 * tile + 1] = make_float4(ex, ey, ez, 0.f);
-            }
-        }
-    }
-}
-
-// The start of round r: hypotheses (blocks [0, hyp_blocks), an XCD-aware 1-D
-// mapping of (frame, block) pairs) and, when box_blocks > 0, the tile boxes
-// of the culled scorer (box_blocks blocks per frame after them).  Both read
-// only what the previous round's removal left.
-__global__ __launch_bounds__(kBlock) void k_round_start(const FrameDev* __restrict__ tab, int r, int bpf, int nf,
-                                                         int hyp_blocks, int box_blocks) {
-    if ((int)blockIdx.x < hyp_blocks) {
-        int frame, bx;
-        if (xcd_frame_block(bpf, nf, hyp_blocks, frame, bx)) hypgen_block(tab[frame], r, bx);
-        return;
-    }
-    const int b = (int)blockIdx.x - hyp_blocks;
-    const int frame = b / box_blocks;
-    tile_box_block(tab[frame], r, b - frame * box_blocks, box_blocks);
+// The start of round r: the hypotheses, over an XCD-aware 1-D mapping of
+// (frame, block) pairs.  They read only what the previous round's removal
+// left (the tile boxes of the round's list were made with the list).
+__global__ __launch_bounds__(kBlock) void k_round_start(const FrameDev* __restrict__ tab, int r, int bpf, int nf) {
+    int frame, bx;
+    if (xcd_frame_block(bpf, nf, (int)gridDim.x, frame, bx)) hypgen_block(tab[frame], r, bx);
 }
 
 // Inlier counts over 64-point tiles (Eq. 3, Alg. 2): the tile boxes decide
@@ -1262,7 +1303,7 @@ __global__ __launch_bounds__(kBlock) void k_score_tiles(const FrameDev* __restri
     const FrameDev& f = tab[blockIdx.z];
     const RoundRec rr = round_rec(f, r);
     if (!rr.active) return;
-    const int M = rr.M;
+    const int M = rr.Mlen;  // a multiple of 64; padding points are NaN
     const int hyps = __builtin_amdgcn_readfirstlane(f.hyps);
     const int h0 = blockIdx.y * NH;
     if (h0 >= hyps) return;
@@ -1334,7 +1375,6 @@ __global__ __launch_bounds__(kBlock) void k_score_tiles(const FrameDev* __restri
         }
         if (ns == 0) continue;
         n_straddle += ns;
-        if (tile * 64 + lane >= M) p = make_float3(qnan, qnan, qnan);
         if (!MF || ns < kMfmaMinStraddlers) {
             asm volatile("" : "+v"(p.x), "+v"(p.y), "+v"(p.z));  // keeps the select out of the loops below
 #pragma unroll
@@ -1545,7 +1585,7 @@ __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __rest
     RoundState* st = f.st;
     const RoundRec rr = round_rec(f, r);
     if (!rr.active) return;
-    const int M = rr.M;
+    const int M = rr.Mlen;
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
     if ((int)blockIdx.x >= nch) return;
     if (blockIdx.x == 0 && f.dbg.counts)
@@ -1605,20 +1645,22 @@ __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __rest
     }
 }
 
-// |F| per chunk for the removal, F = the refit plane's inliers.  Every block
-// first solves the refit plane itself (solve_refit: the same reduction order
-// in every block, so the same plane bit for bit) while the points of its
-// first chunk are already on their way; block 0 stores the plane, the
-// centroid and |S|.  The grid gives each frame only a few blocks per CU, so
-// the redundant solves run side by side, once per block.
+// ------------------------------------------------------------------ removal
+// |F| per chunk for the removal, F = the refit plane's inliers, and the
+// padded length of the chunk's run of survivors in the next round's list.
+// Every block first solves the refit plane itself (solve_refit: the same
+// reduction order in every block, so the same plane bit for bit) while the
+// points of its first chunk are already on their way; block 0 stores the
+// plane, the centroid and |S|.  The grid gives each frame only a few blocks
+// per CU, so the redundant solves run side by side, once per block.
 __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restrict__ tab, int r) {
-    __shared__ int sh[4];
+    __shared__ int sh[8];
     __shared__ double s_plane[4], s_cent[3], s_n;
     __shared__ double s_red[4 * 10];
     const FrameDev& f = tab[blockIdx.z];
     const RoundRec rr = round_rec(f, r);
     if (!rr.active || rr.stop) return;
-    const int M = rr.M;
+    const int M = rr.Mlen;
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
     if ((int)blockIdx.x >= nch) return;
     const float t = f.thresh;
@@ -1639,12 +1681,19 @@ __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restri
         st->s_count = (int)s_n;
     }
     while (true) {
-        int cnt = 0;
+        int nF = 0, keep = 0;
 #pragma unroll
-        for (int s = 0; s < kChunkSteps; ++s)
-            cnt += (c * kRefitChunk + s * kBlock + (int)threadIdx.x < e && fabsf(refit_res(q, pp[s].x, pp[s].y, pp[s].z)) < t) ? 1 : 0;
-        cnt = block_sum(cnt, sh);
-        if (threadIdx.x == 0) f.chunk_cnt[c] = cnt;
+        for (int s = 0; s < kChunkSteps; ++s) {
+            const bool in = c * kRefitChunk + s * kBlock + (int)threadIdx.x < e;
+            const bool f_in = in && fabsf(refit_res(q, pp[s].x, pp[s].y, pp[s].z)) < t;  // padding (NaN) never is
+            nF += f_in ? 1 : 0;
+            keep += (in && !f_in && pp[s].x == pp[s].x) ? 1 : 0;
+        }
+        block_sum2(nF, keep, sh);
+        if (threadIdx.x == 0) {
+            f.chunk_cnt[c] = nF;
+            f.chunk_run[c] = align64(keep);
+        }
         c += gridDim.x;
         if (c >= nch) break;
         e = min(M, (c + 1) * kRefitChunk);
@@ -1653,50 +1702,58 @@ __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restri
     }
 }
 
-
-// F = the refit plane's inliers among R_r.  If |F| >= min_inliers: label F
-// with r, write the plane record, and compact the survivors (in order) into
-// the next round's list; otherwise the frame stops without emitting.
+// F = the refit plane's inliers among R_r (reading R18 of Alg. 2's model
+// update).  If |F| >= min_inliers: label F with r, mark it assigned, write
+// the plane record, and write each chunk's survivors, in order, as one run
+// padded to a multiple of 64 into the next round's list (at the sum of the
+// earlier chunks' runs), then the bounding boxes of the run's tiles (read
+// back from the cache); otherwise the frame stops without emitting.
 __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ tab, int r) {
     __shared__ int sh[8];
+    __shared__ int s_cnt[kChunkSteps][kBlock / 64];
     const FrameDev& f = tab[blockIdx.z];
     RoundState* st = f.st;
     const RoundRec rr = round_rec(f, r);
     if (!rr.active || rr.stop) return;
-    const int M = rr.M;
+    const int M = rr.Mlen;
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
     if ((int)blockIdx.x >= nch) return;
-    // |F| and the inliers of the chunks before this block's first one, in one pass
+    // |F| and the runs of the chunks before this block's first one, in one pass
     const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt;
+    const gi32_cptr crun = (gi32_cptr)f.chunk_run;
     int ftot = 0, pre = 0;
     for (int c = threadIdx.x; c < nch; c += kBlock) {
-        const int v = ccnt[c];
-        ftot += v;
-        pre += c < (int)blockIdx.x ? v : 0;
+        ftot += ccnt[c];
+        pre += c < (int)blockIdx.x ? crun[c] : 0;
     }
     block_sum2(ftot, pre, sh);
     const bool emit = ftot >= f.min_inliers;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const int next = M - (emit ? ftot : 0);
-        if (emit) {
-            pp_plane pl;
-            for (int k = 0; k < 3; ++k) pl.n[k] = st->plane[k];
-            pl.d = st->plane[3];
-            for (int k = 0; k < 3; ++k) pl.centroid[k] = st->centroid[k];
-            pl.inliers = ftot;
-            pl.hyp_index = rr.jstar;
-            f.planes[r] = pl;
-            f.n_planes[0] = r + 1;
-        }
-        st->round[r + 1].M = next;
-        st->round[r + 1].active = (emit && next >= 3 && r + 1 < f.max_planes) ? 1 : 0;
-        if (f.dbg.round_info) {
-            int32_t* ri = f.dbg.round_info + 4 * r;
-            ri[0] = rr.jstar; ri[1] = st->s_count; ri[2] = ftot; ri[3] = emit ? 0 : 2;
+    if (blockIdx.x == 0) {
+        int rtot = 0;
+        for (int c = threadIdx.x; c < nch; c += kBlock) rtot += crun[c];
+        rtot = block_sum(rtot, sh);
+        if (threadIdx.x == 0) {
+            const int next = rr.M - (emit ? ftot : 0);
+            if (emit) {
+                pp_plane pl;
+                for (int k = 0; k < 3; ++k) pl.n[k] = st->plane[k];
+                pl.d = st->plane[3];
+                for (int k = 0; k < 3; ++k) pl.centroid[k] = st->centroid[k];
+                pl.inliers = ftot;
+                pl.hyp_index = rr.jstar;
+                f.planes[r] = pl;
+                f.n_planes[0] = r + 1;
+            }
+            st->round[r + 1].M = next;
+            st->round[r + 1].Mlen = rtot;
+            st->round[r + 1].active = (emit && next >= 3 && r + 1 < f.max_planes) ? 1 : 0;
+            if (f.dbg.round_info) {
+                int32_t* ri = f.dbg.round_info + 4 * r;
+                ri[0] = rr.jstar; ri[1] = st->s_count; ri[2] = ftot; ri[3] = emit ? 0 : 2;
+            }
         }
     }
     if (!emit) return;
-    __shared__ int s_cnt[kChunkSteps][kBlock / 64];
     const SplitPlane q = split_plane(st->plane);
     const float t = f.thresh;
     const float4* __restrict__ pts = f.list[r & 1];
@@ -1704,35 +1761,32 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
     const gi32_cptr Lg = (gi32_cptr)f.L;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        if (c != (int)blockIdx.x) {  // later chunks of this block: add the chunks since its previous one
+        if (c != (int)blockIdx.x) {  // later chunks of this block: add the runs since its previous one
             int add = 0;
-            for (int i = c - (int)gridDim.x + threadIdx.x; i < c; i += kBlock) add += ccnt[i];
+            for (int i = c - (int)gridDim.x + threadIdx.x; i < c; i += kBlock) add += crun[i];
             pre += block_sum(add, sh);
         }
-        // survivors before chunk c: every chunk before it is full
-        const int before = c * kRefitChunk - pre;
+        const int start = pre;
         const int e = min(M, (c + 1) * kRefitChunk);
         // every point of this thread in flight at once: point c*chunk + s*256 + tid of step s
         float4 p[kChunkSteps];
 #pragma unroll
-        for (int s = 0; s < kChunkSteps; ++s) {
-            const int i = c * kRefitChunk + s * kBlock + threadIdx.x;
-            p[s] = ld_global4(pts, min(i, e - 1));
-        }
+        for (int s = 0; s < kChunkSteps; ++s) p[s] = ld_global4(pts, min(c * kRefitChunk + s * kBlock + (int)threadIdx.x, e - 1));
         bool inF[kChunkSteps];
-        int off[kChunkSteps];
-#pragma unroll
-        for (int s = 0; s < kChunkSteps; ++s) {
-            const int i = c * kRefitChunk + s * kBlock + threadIdx.x;
-            inF[s] = i < e && fabsf(refit_res(q, p[s].x, p[s].y, p[s].z)) < t;
-        }
-        // the pixels of the inliers, all looked up before any store
-#pragma unroll
-        for (int s = 0; s < kChunkSteps; ++s) off[s] = Lg[inF[s] ? __float_as_int(p[s].w) : 0];
         unsigned long long keepm[kChunkSteps];
 #pragma unroll
         for (int s = 0; s < kChunkSteps; ++s) {
-            const int i = c * kRefitChunk + s * kBlock + threadIdx.x;
+            const bool in = c * kRefitChunk + s * kBlock + (int)threadIdx.x < e;
+            inF[s] = in && fabsf(refit_res(q, p[s].x, p[s].y, p[s].z)) < t;
+            keepm[s] = __ballot(in && !inF[s] && p[s].x == p[s].x);
+            if (lane == 0) s_cnt[s][wave] = __popcll(keepm[s]);
+        }
+        // the pixels of the inliers, all looked up before any store
+        int off[kChunkSteps];
+#pragma unroll
+        for (int s = 0; s < kChunkSteps; ++s) off[s] = Lg[inF[s] ? __float_as_int(p[s].w) : 0];
+#pragma unroll
+        for (int s = 0; s < kChunkSteps; ++s)
             if (inF[s]) {
                 f.labels[off[s]] = (int8_t)r;
                 f.taken[__float_as_int(p[s].w)] = 1;
@@ -1741,12 +1795,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
                     f.dbg.masks[(size_t)r * f.W * f.H + (size_t)y * f.W + x] |= 2;
                 }
             }
-            keepm[s] = __ballot(i < e && !inF[s]);
-            if (lane == 0) s_cnt[s][wave] = __popcll(keepm[s]);
-        }
-        __syncthreads();
-        // survivors keep their order: step-major, then wave, then lane
-        int base = before;
+        __syncthreads();  // s_cnt
+        // survivors keep their order: step-major, then wave, then lane; then the padding
+        int base = start;
 #pragma unroll
         for (int s = 0; s < kChunkSteps; ++s) {
             int mine = base;
@@ -1757,6 +1808,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
             }
             if ((keepm[s] >> lane) & 1ull) out[mine + __popcll(keepm[s] & lanemask_lt())] = p[s];
         }
+        const int end = align64(base);
+        for (int i = base + (int)threadIdx.x; i < end; i += kBlock) out[i] = pad_point();
+        __syncthreads();  // the run is in memory for the whole block
+        tile_boxes(out + start, (end - start) >> 6, f.tbox + 2 * (start >> 6), wave, kBlock / 64);
         __syncthreads();  // s_cnt is reused by the next chunk
     }
 }
@@ -1908,13 +1963,6 @@ static void score_tiles_launch(const FrameDev* tab, int nf, int r, int max_pts, 
 static bool culled(int precision, const Tuning& tu) { return precision != PP_SCORE_FP32 || tu.score_hb >= 3; }
 static int tiles_q(const Tuning& tu) { return tu.score_hb <= 3 ? 1 : (tu.score_hb == 4 ? 2 : 4); }
 
-// Tile-box blocks per frame for round lists of up to max_pts points.
-static int box_blocks(int max_pts) {
-    const int tiles = (max_pts + 63) / 64;
-    const int per_block = (kBlock / 64) * kBoxTilesPerWave;
-    return clampi((tiles + per_block - 1) / per_block, 1, 65535);
-}
-
 static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int max_hyps, int precision,
                            const Tuning& tu, hipStream_t s) {
     const int target = chunk_value(tu.score_chunk);
@@ -1935,24 +1983,32 @@ static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int 
     }
 }
 
+// Longest point list of a frame of px pixels: the depth-valid pixels with each
+// 1024-position chunk of the 8x8-block scan padded to a multiple of 64 (later
+// rounds' lists are never longer than the first).
+size_t list_capacity(size_t px) {
+    // the padded scan of a frame of px pixels (each side >= 3) covers at most 8/3 px + 56 positions
+    const size_t chunks = (3 * px + 4096) / kValidChunk + 1;
+    return (px + 63) / 64 * 64 + 64 * chunks;
+}
+
 // Blocks of the final pass over all frames (8 per CU): more would repeat the
 // plane solve in more block waves.
 constexpr int kFinalBlocks = 2048;
 
-// One RANSAC round for every frame of the table: hypotheses (+ tile boxes),
-// scoring, selection and moments, the refit plane and its inliers per chunk,
-// the removal.
+// One RANSAC round for every frame of the table: hypotheses, scoring,
+// selection and moments, the refit plane and its inliers per chunk, the
+// removal with the next round's list and tile boxes.
 hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_hyps, int precision,
                         const Tuning& tu, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const int bpf = (max_hyps + kHypPerBlock - 1) / kHypPerBlock;
     const int hyp_blocks = (bpf * nf + kXcds - 1) / kXcds * kXcds;
-    const int nbox = culled(precision, tu) ? box_blocks(max_px) : 0;
-    hipLaunchKernelGGL(k_round_start, dim3(hyp_blocks + nbox * nf), dim3(kBlock), 0, s, tab, r, bpf, nf, hyp_blocks,
-                       nbox);
+    hipLaunchKernelGGL(k_round_start, dim3(hyp_blocks), dim3(kBlock), 0, s, tab, r, bpf, nf);
     if (ev0) (void)hipEventRecord(ev0, s);
-    score_dispatch(tab, nf, r, max_px, max_hyps, precision, tu, s);
+    const int max_pts = (int)list_capacity((size_t)max_px);
+    score_dispatch(tab, nf, r, max_pts, max_hyps, precision, tu, s);
     if (ev1) (void)hipEventRecord(ev1, s);
-    const int nch = (max_px + kRefitChunk - 1) / kRefitChunk;
+    const int nch = (max_pts + kRefitChunk - 1) / kRefitChunk;
     const int gx = clampi(nch, 1, 1024);
     hipLaunchKernelGGL(k_refit_moments, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
     // a few blocks per CU in all: each solves the plane once, then counts several chunks
@@ -1968,11 +2024,7 @@ hipError_t launch_hyp_from_triples(const FrameDev* tab, const int32_t* triples, 
 }
 
 hipError_t launch_score_only(const FrameDev* tab, int max_px, int n, int precision, const Tuning& tu, hipStream_t s) {
-    if (culled(precision, tu)) {
-        const int nbox = box_blocks(max_px);
-        hipLaunchKernelGGL(k_round_start, dim3(nbox), dim3(kBlock), 0, s, tab, 0, 1, 1, 0, nbox);
-    }
-    score_dispatch(tab, 1, 0, max_px, n, precision, tu, s);
+    score_dispatch(tab, 1, 0, (int)list_capacity((size_t)max_px), n, precision, tu, s);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ def test_source_hash_ignores_comments_and_white_space_only(tmp_path, monkeypatch
     monkeypatch.setattr(bench, "ROOT", _tree(tmp_path / "a", "// a new comment\n" + src.replace("\n", "\n\n  ")
                                              + "\n/* block\n comment */\n"))
     assert bench.source_hash() == base
-    monkeypatch.setattr(bench, "ROOT", _tree(tmp_path / "b", src.replace("kBoxTilesPerWave = 4", "kBoxTilesPerWave = 2")))
+    monkeypatch.setattr(bench, "ROOT", _tree(tmp_path / "b", src.replace("kFinalBlocks = 2048", "kFinalBlocks = 1024")))
     assert bench.source_hash() != base
 
 
