@@ -218,7 +218,7 @@ pp_status pp_ransac_planes(pp_ctx* ctx, const float* points_dev, const uint8_t* 
  * results for the same arguments) with no context and no allocation.  Its
  * scratch is a device array of PP_NOALLOC_SCRATCH_BYTES that the library
  * holds on every GPU it runs on until the process ends; a frame needing more
- * (about 51.7 bytes per pixel plus 48 per hypothesis: 1280x1024 at 8192
+ * (about 45.6 bytes per pixel plus 48 per hypothesis: 1280x1024 at 8192
  * hypotheses fits, 1920x1080 does not) returns PP_E_INVAL before any work.
  * Runs on the calling thread's current HIP device with the default tuning,
  * asynchronously on hip_stream; arguments as pp_ransac_planes (no region
@@ -228,7 +228,7 @@ pp_status pp_ransac_planes(pp_ctx* ctx, const float* points_dev, const uint8_t* 
  * for bad arguments, PP_E_HIP for a failed launch (nothing to poison);
  * pp_last_error(NULL) on the calling thread gives the text.  The first call
  * on a device looks the array up (hipGetSymbolAddress). */
-#define PP_NOALLOC_SCRATCH_BYTES ((size_t)80 << 20)
+#define PP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 pp_status pp_ransac_planes_noalloc(const float* points_dev, const uint8_t* valid_dev, pp_frame_desc desc,
                                    const pp_ransac_params* params, pp_plane* planes_dev, int32_t* n_planes_dev,
                                    int8_t* labels_dev, void* hip_stream);

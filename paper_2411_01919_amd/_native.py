@@ -168,7 +168,7 @@ def lib():
 
 
 # bytes of device scratch pp_ransac_planes_noalloc holds per GPU (PP_NOALLOC_SCRATCH_BYTES)
-NOALLOC_SCRATCH_BYTES = 80 << 20
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def status_string(s: int) -> str:

@@ -174,28 +174,27 @@ bool intrinsics_ok(const pp_intrinsics& K) {
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t delta, L, list, taken, hyp, hyp_p0, triples, counts, partials, chunk_cnt, chunk_cnt_q, tbox, chunk_run, st, total;
+    size_t delta, L, list, taken, hyp, hyp_p0, triples, counts, partials, chunk_cnt, tbox, chunk_run, st, total;
 };
 
+// px: the slot's pixel capacity, at least the scan positions of every frame it
+// holds (ppk::scan_pixels), which is also its point lists' capacity.
 Layout slot_layout(size_t px, int hyps) {
     Layout l;
-    const size_t cap = ppk::list_capacity(px);
-    const size_t nch_refit = (cap + ppk::kRefitChunk - 1) / ppk::kRefitChunk;
+    const size_t nch_refit = (px + ppk::kRefitChunk - 1) / ppk::kRefitChunk;
     const size_t nch_valid = (px + ppk::kValidChunk - 1) / ppk::kValidChunk;
     size_t o = 0;
     l.delta = o; o += align256(2 * px * sizeof(float));
     l.L = o; o += align256(px * sizeof(int32_t));
-    l.list = o; o += align256(2 * cap * sizeof(float4));
-    l.taken = o; o += align256((px + 3) / 4 * 4);
+    l.list = o; o += align256(2 * px * sizeof(float4));
+    l.taken = o; o += align256(px);
     l.hyp = o; o += align256((size_t)hyps * sizeof(float4));
     l.hyp_p0 = o; o += align256((size_t)hyps * sizeof(float4));
     l.triples = o; o += align256((size_t)hyps * 3 * sizeof(int32_t));
     l.counts = o; o += align256((size_t)hyps * sizeof(int32_t));
     l.partials = o; o += align256(nch_refit * 10 * sizeof(double));
     l.chunk_cnt = o; o += align256(std::max(nch_refit, nch_valid) * sizeof(int32_t));
-    // the padded 8x8-block scan of a frame of px pixels (each side >= 3) covers at most 3.4 px + 70 positions
-    l.chunk_cnt_q = o; o += align256(((4 * px + 4096) / ppk::kValidChunk + 1) * sizeof(int32_t));
-    l.tbox = o; o += align256(cap / 64 * 2 * sizeof(float4));
+    l.tbox = o; o += align256((px + 63) / 64 * 2 * sizeof(float4));
     l.chunk_run = o; o += align256(nch_refit * sizeof(int32_t));
     l.st = o; o += align256(sizeof(RoundState));
     l.total = o;
@@ -238,7 +237,7 @@ void bind_layout(char* b, size_t px_cap, int hyp_cap, FrameDev& f) {
     f.delta[1] = f.delta[0] + px_cap;
     f.L = reinterpret_cast<int32_t*>(b + l.L);
     f.list[0] = reinterpret_cast<float4*>(b + l.list);
-    f.list[1] = f.list[0] + ppk::list_capacity(px_cap);
+    f.list[1] = f.list[0] + px_cap;
     f.taken = reinterpret_cast<uint8_t*>(b + l.taken);
     f.hyp = reinterpret_cast<float4*>(b + l.hyp);
     f.hyp_p0 = reinterpret_cast<float4*>(b + l.hyp_p0);
@@ -246,7 +245,6 @@ void bind_layout(char* b, size_t px_cap, int hyp_cap, FrameDev& f) {
     f.counts = reinterpret_cast<int32_t*>(b + l.counts);
     f.partials = reinterpret_cast<double*>(b + l.partials);
     f.chunk_cnt = reinterpret_cast<int32_t*>(b + l.chunk_cnt);
-    f.chunk_cnt_q = reinterpret_cast<int32_t*>(b + l.chunk_cnt_q);
     f.tbox = reinterpret_cast<float4*>(b + l.tbox);
     f.chunk_run = reinterpret_cast<int32_t*>(b + l.chunk_run);
     f.st = reinterpret_cast<RoundState*>(b + l.st);
@@ -493,7 +491,7 @@ pp_status pp_diffuse(pp_ctx* c, const uint16_t* depth_dev, float* out_mm_dev, pp
         return fail(c, PP_E_INVAL, "pp_diffuse: bad argument");
     if ((s = set_device(c)) != PP_OK) return s;
     const size_t px = (size_t)desc.width * desc.height;
-    if ((s = ensure_slot(c, 0, px, 1)) != PP_OK) return s;
+    if ((s = ensure_slot(c, 0, ppk::scan_pixels(desc.width, desc.height), 1)) != PP_OK) return s;
     FrameDev f{};
     bind_slot(c, 0, f);
     fill_geometry(f, desc);
@@ -533,7 +531,7 @@ static pp_status ransac_common(pp_ctx* c, const float* points_dev, const uint8_t
     pp_status s;
     if ((s = set_device(c)) != PP_OK) return s;
     const size_t px = (size_t)desc.width * desc.height;
-    if ((s = ensure_slot(c, 0, px, p->hyps_per_plane)) != PP_OK) return s;
+    if ((s = ensure_slot(c, 0, ppk::scan_pixels(desc.width, desc.height), p->hyps_per_plane)) != PP_OK) return s;
     FrameDev f{};
     bind_slot(c, 0, f);
     fill_geometry(f, desc);
@@ -552,7 +550,7 @@ static pp_status ransac_common(pp_ctx* c, const float* points_dev, const uint8_t
     if ((s = put_plain(c, f, st)) != PP_OK) return s;
     HIPCHK(c, ppk::launch_valid_list(c->plain_tab, 1, (int)px, desc.width, desc.height, st));
     for (int r = 0; r < p->max_planes; ++r)
-        HIPCHK(c, ppk::launch_round(c->plain_tab, 1, r, (int)px, p->hyps_per_plane, p->precision, c->tuning, st,
+        HIPCHK(c, ppk::launch_round(c->plain_tab, 1, r, (int)ppk::scan_pixels(desc.width, desc.height), p->hyps_per_plane, p->precision, c->tuning, st,
                                     c->timing ? c->score_ev[r][0] : nullptr, c->timing ? c->score_ev[r][1] : nullptr));
     if (c->timing) c->timed_rounds = p->max_planes;
     return mark_stream(c, st);
@@ -705,7 +703,7 @@ pp_status pp_debug_score_triples(pp_ctx* c, const float* points_dev, const uint8
         return fail(c, PP_E_INVAL, "pp_debug_score_triples: bad argument");
     if ((s = set_device(c)) != PP_OK) return s;
     const size_t px = (size_t)desc.width * desc.height;
-    if ((s = ensure_slot(c, 0, px, 1)) != PP_OK) return s;
+    if ((s = ensure_slot(c, 0, ppk::scan_pixels(desc.width, desc.height), 1)) != PP_OK) return s;
     FrameDev f{};
     bind_slot(c, 0, f);
     fill_geometry(f, desc);
@@ -738,7 +736,7 @@ pp_status pp_debug_score_triples(pp_ctx* c, const float* points_dev, const uint8
     hipLaunchKernelGGL(k_force_active, dim3(1), dim3(1), 0, st, c->plain_tab);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, ppk::launch_hyp_from_triples(c->plain_tab, triples_dev, n, st));
-    HIPCHK(c, ppk::launch_score_only(c->plain_tab, (int)px, n, precision, c->tuning, st));
+    HIPCHK(c, ppk::launch_score_only(c->plain_tab, (int)ppk::scan_pixels(desc.width, desc.height), n, precision, c->tuning, st));
     return mark_stream(c, st);
 }
 
@@ -753,7 +751,7 @@ bool job_ok(const pp_frame_job& j) {
 }
 
 struct BatchPlan {
-    int nf = 0, maxW = 0, maxH = 0, max_px = 0, max_hyps = 0, max_rounds = 0, precision = 0;
+    int nf = 0, maxW = 0, maxH = 0, max_px = 0, max_scan = 0, max_hyps = 0, max_rounds = 0, precision = 0;
     std::vector<int> order;                        // table position -> job index
     std::vector<std::pair<int, int>> iter_groups;  // (first table position, count): equal iterations and scheme
     std::vector<int> group_iters, group_scheme;
@@ -775,6 +773,7 @@ BatchPlan plan_batch(const pp_frame_job* jobs, int n, const ppk::Tuning& tu) {
         b.maxW = std::max(b.maxW, j.desc.width);
         b.maxH = std::max(b.maxH, j.desc.height);
         b.max_px = std::max(b.max_px, j.desc.width * j.desc.height);
+        b.max_scan = std::max(b.max_scan, (int)ppk::scan_pixels(j.desc.width, j.desc.height));
         b.max_hyps = std::max(b.max_hyps, j.ransac.hyps_per_plane);
         b.max_rounds = std::max(b.max_rounds, j.ransac.max_planes);
         if (i == 0 || j.diffuse.iters != jobs[b.order[i - 1]].diffuse.iters ||
@@ -786,8 +785,8 @@ BatchPlan plan_batch(const pp_frame_job* jobs, int n, const ppk::Tuning& tu) {
         b.iter_groups.back().second++;
     }
     char buf[256];
-    snprintf(buf, sizeof buf, "n%d W%d H%d px%d h%d r%d p%d t%d.%d.%d.%d", n, b.maxW, b.maxH, b.max_px, b.max_hyps,
-             b.max_rounds, b.precision, tu.diffuse_tile, tu.diffuse_t, tu.score_hb, tu.score_chunk);
+    snprintf(buf, sizeof buf, "n%d W%d H%d px%d q%d h%d r%d p%d t%d.%d.%d.%d", n, b.maxW, b.maxH, b.max_px, b.max_scan,
+             b.max_hyps, b.max_rounds, b.precision, tu.diffuse_tile, tu.diffuse_t, tu.score_hb, tu.score_chunk);
     b.key = buf;
     for (size_t g = 0; g < b.iter_groups.size(); ++g) {
         snprintf(buf, sizeof buf, " g%d:%d:%d:%d", b.iter_groups[g].first, b.iter_groups[g].second, b.group_iters[g],
@@ -808,7 +807,7 @@ pp_status enqueue_batch(pp_ctx* c, const BatchPlan& b, hipStream_t st, bool capt
     HIPCHK(c, ppk::launch_valid_list(c->batch_tab, b.nf, b.max_px, b.maxW, b.maxH, st));
     if (timed) HIPCHK(c, hipEventRecord(c->stage_ev[2], st));
     for (int r = 0; r < b.max_rounds; ++r)
-        HIPCHK(c, ppk::launch_round(c->batch_tab, b.nf, r, b.max_px, b.max_hyps, b.precision, c->tuning, st,
+        HIPCHK(c, ppk::launch_round(c->batch_tab, b.nf, r, b.max_scan, b.max_hyps, b.precision, c->tuning, st,
                                     timed ? c->score_ev[r][0] : nullptr, timed ? c->score_ev[r][1] : nullptr));
     if (timed) {
         HIPCHK(c, hipEventRecord(c->stage_ev[3], st));
@@ -822,7 +821,7 @@ pp_status upload_batch_table(pp_ctx* c, const pp_frame_job* jobs, const BatchPla
     pp_status s;
     for (int i = 0; i < b.nf; ++i) {
         const pp_frame_job& j = jobs[b.order[i]];
-        if ((s = ensure_slot(c, 1 + i, (size_t)j.desc.width * j.desc.height, j.ransac.hyps_per_plane)) != PP_OK) return s;
+        if ((s = ensure_slot(c, 1 + i, ppk::scan_pixels(j.desc.width, j.desc.height), j.ransac.hyps_per_plane)) != PP_OK) return s;
     }
     if (b.nf > c->batch_tab_cap) {
         if (c->batch_tab) {
@@ -891,7 +890,7 @@ pp_status batch_run(pp_ctx* c, int32_t n, const pp_frame_job* jobs, void* stream
                 HIPCHK(c, hipFree(sl.base));
             }
             sl.base = ext_scratch[b.order[i]];
-            sl.px_cap = (size_t)j.desc.width * j.desc.height;
+            sl.px_cap = ppk::scan_pixels(j.desc.width, j.desc.height);
             sl.hyp_cap = j.ransac.hyps_per_plane;
             sl.bytes = slot_layout(sl.px_cap, sl.hyp_cap).total;
             sl.external = true;
@@ -957,7 +956,7 @@ pp_status pp_batch_run_eager(pp_ctx* c, int32_t n, const pp_frame_job* jobs, voi
 namespace ppk {
 
 size_t frame_scratch_bytes(int width, int height, int hyps) {
-    return slot_layout((size_t)width * height, hyps).total;
+    return slot_layout(ppk::scan_pixels(width, height), hyps).total;
 }
 
 pp_status batch_run_external(pp_ctx* c, int n, const pp_frame_job* jobs, void* const* scratch, hipStream_t s,
@@ -1003,7 +1002,7 @@ pp_status noalloc_scratch(int dev, void** out) {
 
 // Bytes of `scratch` one frame takes: the frame table entry, then its slot.
 size_t noalloc_bytes(const pp_frame_desc& d, int hyps) {
-    return align256(sizeof(FrameDev)) + slot_layout((size_t)d.width * d.height, hyps).total;
+    return align256(sizeof(FrameDev)) + slot_layout(ppk::scan_pixels(d.width, d.height), hyps).total;
 }
 
 }  // namespace
@@ -1035,7 +1034,7 @@ pp_status pp_ransac_planes_noalloc(const float* points_dev, const uint8_t* valid
     FrameDev* tab = static_cast<FrameDev*>(base);
     const size_t px = (size_t)desc.width * desc.height;
     FrameDev f{};
-    bind_layout(static_cast<char*>(base) + align256(sizeof(FrameDev)), px, p->hyps_per_plane, f);
+    bind_layout(static_cast<char*>(base) + align256(sizeof(FrameDev)), ppk::scan_pixels(desc.width, desc.height), p->hyps_per_plane, f);
     fill_geometry(f, desc);
     fill_ransac(f, *p);
     f.pts = const_cast<float*>(points_dev);
@@ -1051,7 +1050,7 @@ pp_status pp_ransac_planes_noalloc(const float* points_dev, const uint8_t* valid
     e = hipGetLastError();
     if (e == hipSuccess) e = ppk::launch_valid_list(tab, 1, (int)px, desc.width, desc.height, st);
     for (int r = 0; e == hipSuccess && r < p->max_planes; ++r)
-        e = ppk::launch_round(tab, 1, r, (int)px, p->hyps_per_plane, p->precision, kDefaultTuning, st);
+        e = ppk::launch_round(tab, 1, r, (int)ppk::scan_pixels(desc.width, desc.height), p->hyps_per_plane, p->precision, kDefaultTuning, st);
     if (e != hipSuccess) return fail(nullptr, PP_E_HIP, std::string("pp_ransac_planes_noalloc: ") + hipGetErrorString(e));
     return PP_OK;
 }

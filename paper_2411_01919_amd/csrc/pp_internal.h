@@ -72,15 +72,14 @@ struct FrameDev {
     // library scratch
     float* delta[2];         // [H][W] diffusion ping-pong (delta = I - I0)
     int32_t* L;              // [W*H] valid list (pixel offsets y*pitch+x)
-    float4* list[2];         // [list capacity] remaining points (x, y, z, valid-list position bits), NaN padding
-    uint8_t* taken;          // [W*H rounded up to 4] 1 iff the point at valid-list position k is assigned
+    float4* list[2];         // [scan positions] remaining points (x, y, z, valid-list position bits), NaN padding
+    uint8_t* taken;          // [W*H] 1 iff the point at valid-list position k is assigned
     float4* hyp;             // [hyps] (n, d); d = NaN when invalid
     float4* hyp_p0;          // [hyps] the first point of each hypothesis' triple (the refit's moment origin)
     int32_t* triples;        // [hyps][3]
     int32_t* counts;         // [hyps]
     double* partials;        // [refit chunks][10]
     int32_t* chunk_cnt;      // [max(valid chunks, refit chunks)]
-    int32_t* chunk_cnt_q;    // [block-order chunks] depth-valid pixels per 1024 positions of the 8x8-block scan
     float4* tbox;            // [list tiles][2] per 64-point tile of the current list: centre (w: count of
                              // its points that are not padding) and half extents of their bounding box
     int32_t* chunk_run;      // [refit chunks] padded length of each chunk's run of survivors
@@ -113,7 +112,10 @@ hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, int maxW, 
 hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_hyps, int precision,
                         const Tuning& tu, hipStream_t s, hipEvent_t score_start = nullptr,
                         hipEvent_t score_end = nullptr);
-size_t list_capacity(size_t px);
+// Positions of the 8x8-block scan of a W x H frame (whole blocks): the length
+// of its round-0 point list, which no later round's list exceeds, and at
+// least W H.  Frame scratch is sized by it.
+inline size_t scan_pixels(int W, int H) { return (size_t)((W + 7) / 8) * (size_t)((H + 7) / 8) * 64; }
 hipError_t launch_hyp_from_triples(const FrameDev* tab, const int32_t* triples, int n, hipStream_t s);
 hipError_t launch_score_only(const FrameDev* tab, int max_px, int n, int precision, const Tuning& tu,
                              hipStream_t s);

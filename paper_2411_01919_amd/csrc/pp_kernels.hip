@@ -5,9 +5,10 @@
 //                    per pass, FP32 on delta = I - I0, the iterate in registers
 //                    (one wave per column strip); k_diffuse: the same on LDS tiles
 //   k_normals        back-projection (Alg. 2) + Sobel normal image (Eq. 2)
-//   k_valid_*,       row-major list of depth-valid pixels (Alg. 2 point set) and
-//   k_list_scatter   the round-0 scoring list in 8x8-block order with the
-//                    bounding boxes of its 64-point tiles
+//   k_valid_*        row-major list of depth-valid pixels (Alg. 2 point set)
+//   k_list0          the round-0 scoring list: every position of the image's
+//                    8x8-block scan (NaN for no point) with the bounding boxes
+//                    of its 64-point tiles
 //   k_round_start    3-point hypotheses from Philox4x64-10 (Alg. 2)
 //   k_score_tiles    inlier counts, point-to-plane distance < t (Eq. 3, Alg. 2):
 //                    tiles decided from their boxes, the rest point by point
@@ -519,6 +520,8 @@ __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__
 // order, pixels row-major inside a block) so that 64 consecutive points are
 // close in space; the sampling list L stays row-major.  Scan position q of the
 // padded block grid maps to pixel (x, y), outside the image past the edges.
+// The round-0 list holds every scan position (a pixel without a point is a
+// NaN entry), so it needs no compaction; later rounds compact.
 __device__ __forceinline__ int scan_positions(const FrameDev& f) {
     return ((f.W + kScanBlock - 1) / kScanBlock) * ((f.H + kScanBlock - 1) / kScanBlock) * kScanBlock * kScanBlock;
 }
@@ -539,9 +542,6 @@ __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restri
     const int npx = f.W * f.H;
     const int nch = (npx + kValidChunk - 1) / kValidChunk;
     if (blockIdx.x == 0 && threadIdx.x == 0) f.st->p1max_bits = 0u;
-    const int nwords = (npx + 3) >> 2;
-    uint32_t* __restrict__ tw = reinterpret_cast<uint32_t*>(f.taken);
-    for (int w = blockIdx.x * kBlock + threadIdx.x; w < nwords; w += gridDim.x * kBlock) tw[w] = 0u;
     static_assert(kValidChunk == 4 * kBlock, "four pixels per thread and chunk");
     const gu8_cptr vg = (gu8_cptr)f.valid;
     const bool word_rows = ((f.pitch | (int)(uintptr_t)f.valid) & 3) == 0;
@@ -564,38 +564,18 @@ __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restri
         cnt = block_sum(cnt, sh);
         if (threadIdx.x == 0) f.chunk_cnt[c] = cnt;
     }
-    // the same counts over the 8x8-block scan that orders the scoring list:
-    // scan positions q0..q0+3 are 4 pixels of one row of one block
-    const int nq = scan_positions(f);
-    const int nchq = (nq + kValidChunk - 1) / kValidChunk;
-    for (int c = blockIdx.x; c < nchq; c += gridDim.x) {
-        int x = 0, y = 0;
-        const bool in = scan_pixel(f, c * kValidChunk + 4 * (int)threadIdx.x, x, y);
-        int cnt = 0;
-        if (in && word_rows && x + 3 < f.W) {
-            const uint32_t w = *(const __attribute__((address_space(1))) uint32_t*)(vg + (size_t)y * f.pitch + x);
-            cnt = __popc(w & 0x01010101u);
-        } else if (in) {
-            for (int i = 0; i < 4 && x + i < f.W; ++i) cnt += vg[(size_t)y * f.pitch + x + i] & 1;
-        }
-        cnt = block_sum(cnt, sh);
-        if (threadIdx.x == 0) f.chunk_cnt_q[c] = cnt;
-    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __restrict__ tab) {
     constexpr int S = kValidChunk / kBlock;  // steps of one chunk
     __shared__ int sh[4 * S];
-    __shared__ float shf[4];
     const FrameDev& f = tab[blockIdx.z];
     const int npx = f.W * f.H;
     const int nch = (npx + kValidChunk - 1) / kValidChunk;
-    const size_t plane = (size_t)f.H * f.pitch;
     // valid-list position of every depth-valid pixel, [H][W]; the diffusion
     // ping-pong buffer is free by now
     int32_t* __restrict__ lpos = reinterpret_cast<int32_t*>(f.delta[0]);
     const gu8_cptr vg = (gu8_cptr)f.valid;
-    const gf32_cptr pg = (gf32_cptr)f.pts;
     const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt;
     // valid pixels before chunk c, carried from this block's previous chunk
     int before = 0;
@@ -609,7 +589,6 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
         int off[S];
         bool in[S], v[S];
         uint8_t vb[S];
-        float a1[S];
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             const int p = c * kValidChunk + k * kBlock + threadIdx.x;
@@ -621,40 +600,27 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
 #pragma unroll
         for (int k = 0; k < S; ++k) vb[k] = vg[off[k]];
 #pragma unroll
-        for (int k = 0; k < S; ++k)
-            a1[k] = fabsf(pg[off[k]]) + fabsf(pg[plane + off[k]]) + fabsf(pg[2 * plane + off[k]]);
-#pragma unroll
         for (int k = 0; k < S; ++k) {
             v[k] = in[k] && (vb[k] & 1);
             if (in[k]) f.labels[off[k]] = -1;
         }
         int rank[S], tot;
         block_rank_steps<S>(v, sh, rank, tot);
-        float p1 = 0.f;
 #pragma unroll
         for (int k = 0; k < S; ++k)
             if (v[k]) {
                 const int kk = before + rank[k];
                 f.L[kk] = off[k];
+                f.taken[kk] = 0;
                 lpos[c * kValidChunk + k * kBlock + threadIdx.x] = kk;
                 if (f.dbg.valid_list) f.dbg.valid_list[kk] = off[k];
-                p1 = fmaxf(p1, a1[k]);
             }
         const int run = before + tot;
-        // frame-wide bound on |p|_1 for the recheck bands of the matrix-core scorers
-        // (non-negative floats order as their bit patterns)
-        float pm = __int_as_float(wave_ext<true>(__float_as_int(p1)));
-        __syncthreads();
-        if ((threadIdx.x & 63) == 0) shf[threadIdx.x >> 6] = pm;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            pm = fmaxf(fmaxf(shf[0], shf[1]), fmaxf(shf[2], shf[3]));
-            if (pm > 0.f) atomicMax(&f.st->p1max_bits, __float_as_uint(pm));
-        }
         if (c == nch - 1 && threadIdx.x == 0) {
             RoundState* st = f.st;
             st->M0 = run;
             st->round[0].M = run;
+            st->round[0].Mlen = scan_positions(f);
             st->round[0].active = (run >= 3 && f.max_planes >= 1) ? 1 : 0;
             for (int r = 1; r <= kMaxRounds; ++r) st->round[r].active = 0;
             f.n_planes[0] = 0;
@@ -670,11 +636,9 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
 // blocks at most.  The list L is fixed per frame, so the draws of round r do
 // not depend on how many points earlier rounds removed.
 // 16 lanes per hypothesis compute its 16 Philox blocks at once and look up
-// their 64 candidates in the per-position assignment bytes; one lane then
-// walks them in draw order, so the triple is exactly the sequential draw's
-// (the serial continuation below only runs if fewer lanes are configured).
-// The bytes are set by plain stores when a round removes its inliers (a
-// bitmap would need atomic ORs, which contend on shared words).
+// their 64 candidates in the per-position assignment bytes, which the
+// removal sets with plain byte stores (a bitmap would need atomic ORs, which
+// contend on shared words).
 constexpr int kHypLanes = 16;
 constexpr int kHypPerBlock = kBlock / kHypLanes;
 
@@ -778,44 +742,27 @@ __device__ __forceinline__ void tile_boxes(const float4* src, int ntiles, float4
     }
 }
 
-// Writes a chunk's run of n points, staged in LDS in list order, to the
-// list at position start (a multiple of 64), padded to a multiple of 64, and
-// the boxes of its tiles; the block's four waves take the tiles in turn.
-__device__ __forceinline__ void store_run(float4* stage, int n, float4* out, float4* tbox, int start) {
-    const int wave = threadIdx.x >> 6;
-    const int padded = align64(n);
-    for (int i = n + (int)threadIdx.x; i < padded; i += kBlock) stage[i] = pad_point();
-    __syncthreads();
-    for (int i = threadIdx.x; i < padded; i += kBlock) out[start + i] = stage[i];
-    tile_boxes(stage, padded >> 6, tbox + 2 * (start >> 6), wave, kBlock / 64);
-}
-
-// The first RANSAC round's scoring list: the depth-valid points in 8x8-block scan order,
-// each tagged with its valid-list position (w), by ordered compaction over
-// chunks of 1024 scan positions; each chunk's run is padded to a multiple of
-// 64 points, and the tile boxes of the run are made here.
-__global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restrict__ tab) {
+// The first RANSAC round's scoring list: position q of the 8x8-block scan
+// holds the point of its pixel (x, y, z, its valid-list position as integer bits),
+// or NaN where the pixel is outside the frame or has no depth, so the list
+// needs no compaction; the boxes of its 64-point tiles (one tile per 8x8
+// block) are made here, as is the frame-wide bound on |p|_1 that the matrix-core
+// scorers' recheck bands use.  A block takes 16 tiles (1024 positions) per
+// step, staged in LDS for the boxes.
+__global__ __launch_bounds__(kBlock) void k_list0(const FrameDev* __restrict__ tab) {
     constexpr int S = kValidChunk / kBlock;
-    __shared__ int sh[4 * S];
     __shared__ float4 stage[kValidChunk];
+    __shared__ float shf[4];
     const FrameDev& f = tab[blockIdx.z];
     const int nq = scan_positions(f);
     const int nchq = (nq + kValidChunk - 1) / kValidChunk;
     const size_t plane = (size_t)f.H * f.pitch;
-    const gi32_cptr lpos = (gi32_cptr)f.delta[0];
     const gu8_cptr vg = (gu8_cptr)f.valid;
     const gf32_cptr pg = (gf32_cptr)f.pts;
-    const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt_q;
-    // list position of scan chunk c's run (the padded runs of the chunks
-    // before it), carried from this block's previous chunk
-    int run = 0;
+    const gi32_cptr lpos = (gi32_cptr)f.delta[0];
+    float4* __restrict__ out = f.list[0];
+    float p1 = 0.f;
     for (int c = blockIdx.x; c < nchq; c += gridDim.x) {
-        {
-            int add = 0;
-            for (int i = c - (c == (int)blockIdx.x ? c : (int)gridDim.x) + threadIdx.x; i < c; i += kBlock)
-                add += align64(ccnt[i]);
-            run += block_sum(add, sh);
-        }
         int off[S], lp[S];
         bool v[S];
         uint8_t vb[S];
@@ -837,15 +784,29 @@ __global__ __launch_bounds__(kBlock) void k_list_scatter(const FrameDev* __restr
             lp[k] = lpos[lp[k]];
         }
 #pragma unroll
-        for (int k = 0; k < S; ++k) v[k] = v[k] && (vb[k] & 1);
-        int rank[S], tot;
-        block_rank_steps<S>(v, sh, rank, tot);
-#pragma unroll
-        for (int k = 0; k < S; ++k)
-            if (v[k]) stage[rank[k]] = make_float4(px[k], py[k], pz[k], __int_as_float(lp[k]));
-        store_run(stage, tot, f.list[0], f.tbox, run);
-        if (c == nchq - 1 && threadIdx.x == 0) f.st->round[0].Mlen = run + align64(tot);
+        for (int k = 0; k < S; ++k) {
+            const int i = k * kBlock + threadIdx.x;
+            float4 q = pad_point();
+            if (v[k] && (vb[k] & 1)) {
+                q = make_float4(px[k], py[k], pz[k], __int_as_float(lp[k]));
+                p1 = fmaxf(p1, fabsf(px[k]) + fabsf(py[k]) + fabsf(pz[k]));
+            }
+            if (c * kValidChunk + i < nq) out[c * kValidChunk + i] = q;
+            stage[i] = q;
+        }
+        __syncthreads();
+        const int ntiles = min(kValidChunk, nq - c * kValidChunk) >> 6;
+        tile_boxes(stage, ntiles, f.tbox + 2 * (c * kValidChunk >> 6), threadIdx.x >> 6, kBlock / 64);
         __syncthreads();  // the stage is reused by the next chunk
+    }
+    // frame-wide bound on |p|_1 for the recheck bands of the matrix-core scorers
+    // (non-negative floats order as their bit patterns)
+    float pm = __int_as_float(wave_ext<true>(__float_as_int(p1)));
+    if ((threadIdx.x & 63) == 0) shf[threadIdx.x >> 6] = pm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pm = fmaxf(fmaxf(shf[0], shf[1]), fmaxf(shf[2], shf[3]));
+        if (pm > 0.f) atomicMax(&f.st->p1max_bits, __float_as_uint(pm));
     }
 }
 
@@ -1355,12 +1316,13 @@ __global__ __launch_bounds__(kBlock) void k_score_tiles(const FrameDev* __restri
     for (; tile < ntiles; tile += tstride) {
         const float4 c = c_next, e = e_next;
         float3 p = p_next;
-        ++n_tiles;
         if (tile + tstride < ntiles) {
             c_next = ld_global4(box, 2 * (tile + tstride));
             e_next = ld_global4(box, 2 * (tile + tstride) + 1);
             p_next = ld_global_xyz(pts, min((tile + tstride) * 64 + lane, M - 1));
         }
+        if (__float_as_int(c.w) == 0) continue;  // a tile of padding only (no point of its 8x8 block)
+        ++n_tiles;
         unsigned long long S[Q];
         int ns = 0;
 #pragma unroll
@@ -1932,7 +1894,7 @@ hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, int maxW, 
     const int64_t grid = (maxW + pad - 1) / pad * pad * ((maxH + pad - 1) / pad * pad);
     const int64_t scan = grid < (int64_t)4 * max_px + 4096 ? grid : (int64_t)4 * max_px + 4096;
     const int gq = clampi((int)((scan + kValidChunk - 1) / kValidChunk), 1, 1024);
-    hipLaunchKernelGGL(k_list_scatter, dim3(gq, 1, nf), dim3(kBlock), 0, s, tab);
+    hipLaunchKernelGGL(k_list0, dim3(gq, 1, nf), dim3(kBlock), 0, s, tab);
     return hipGetLastError();
 }
 
@@ -1983,15 +1945,6 @@ static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int 
     }
 }
 
-// Longest point list of a frame of px pixels: the depth-valid pixels with each
-// 1024-position chunk of the 8x8-block scan padded to a multiple of 64 (later
-// rounds' lists are never longer than the first).
-size_t list_capacity(size_t px) {
-    // the padded scan of a frame of px pixels (each side >= 3) covers at most 8/3 px + 56 positions
-    const size_t chunks = (3 * px + 4096) / kValidChunk + 1;
-    return (px + 63) / 64 * 64 + 64 * chunks;
-}
-
 // Blocks of the final pass over all frames (8 per CU): more would repeat the
 // plane solve in more block waves.
 constexpr int kFinalBlocks = 2048;
@@ -2005,7 +1958,7 @@ hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_
     const int hyp_blocks = (bpf * nf + kXcds - 1) / kXcds * kXcds;
     hipLaunchKernelGGL(k_round_start, dim3(hyp_blocks), dim3(kBlock), 0, s, tab, r, bpf, nf);
     if (ev0) (void)hipEventRecord(ev0, s);
-    const int max_pts = (int)list_capacity((size_t)max_px);
+    const int max_pts = max_px;  // the longest list: the scan positions of the largest frame
     score_dispatch(tab, nf, r, max_pts, max_hyps, precision, tu, s);
     if (ev1) (void)hipEventRecord(ev1, s);
     const int nch = (max_pts + kRefitChunk - 1) / kRefitChunk;
@@ -2024,7 +1977,7 @@ hipError_t launch_hyp_from_triples(const FrameDev* tab, const int32_t* triples, 
 }
 
 hipError_t launch_score_only(const FrameDev* tab, int max_px, int n, int precision, const Tuning& tu, hipStream_t s) {
-    score_dispatch(tab, 1, 0, (int)list_capacity((size_t)max_px), n, precision, tu, s);
+    score_dispatch(tab, 1, 0, max_px, n, precision, tu, s);
     return hipGetLastError();
 }
 

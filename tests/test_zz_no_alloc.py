@@ -95,7 +95,7 @@ def test_noalloc_matrix_core_form_equals_the_context_path(pp):
 def test_noalloc_refuses_frames_beyond_its_scratch_and_bad_arguments(pp):
     import torch
     from paper_2411_01919_amd import _native as N
-    W, H = 2048, 2048  # about 216 MB of scratch at 51.7 bytes a pixel
+    W, H = 2048, 2048  # about 191 MB of scratch at 45.6 bytes a pixel
     pts = torch.zeros((3, H, W), dtype=torch.float32, device="cuda:0")
     valid = torch.zeros((H, W), dtype=torch.uint8, device="cuda:0")
     _, rc = cfg_params(2, W, H)
