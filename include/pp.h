@@ -460,6 +460,8 @@ typedef struct {
 pp_status pp_server_create(const pp_server_cfg* cfg, pp_server** out);
 /* Stops the scheduler, waits for batches on the device, frees everything. */
 pp_status pp_server_destroy(pp_server* s);
+/* Text of the failure that poisoned the server ("" if none); the pointer stays
+ * valid until the calling thread's next call. */
 const char* pp_server_last_error(const pp_server* s);
 /* Register camera stream stream_id (unique for the server's lifetime): frame
  * size (pitch_px == width), intrinsics and parameters.  PP_E_BUDGET if one
@@ -471,7 +473,10 @@ pp_status pp_stream_open(pp_server* s, int32_t stream_id, pp_frame_desc desc, pp
 pp_status pp_stream_close(pp_server* s, int32_t stream_id);
 /* Copy a host uint16 [height][width] frame into pinned staging and queue it;
  * never blocks.  frame_id keys the frame's hypotheses.  *ticket identifies
- * the result.  PP_E_AGAIN when the stream's staging is full. */
+ * the result.  PP_E_AGAIN when the stream's staging is full; PP_E_CLOSED if
+ * the stream is (or was meanwhile) closed; PP_E_HIP once a failure has
+ * poisoned the server (also when it happens while the frame is copied: the
+ * frame is then not queued). */
 pp_status pp_submit(pp_server* s, int32_t stream_id, const uint16_t* depth_host, uint64_t frame_id,
                     uint64_t* ticket);
 /* Wait up to timeout_us (0: don't wait) for the ticket: PP_OK with the results

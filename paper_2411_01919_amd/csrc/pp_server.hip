@@ -343,8 +343,8 @@ void scheduler(pp_server* s) {
 
 pp_status check(pp_server* s) {
     if (!s) return PP_E_INVAL;
-    if (s->poisoned) return PP_E_HIP;
-    return PP_OK;
+    std::lock_guard<std::mutex> lk(s->mu);
+    return s->poisoned ? PP_E_HIP : PP_OK;
 }
 
 }  // namespace
@@ -419,7 +419,14 @@ pp_status pp_server_destroy(pp_server* s) {
     return PP_OK;
 }
 
-const char* pp_server_last_error(const pp_server* s) { return s ? s->err.c_str() : ""; }
+const char* pp_server_last_error(const pp_server* s) {
+    // a copy per calling thread: the scheduler may replace the text meanwhile
+    thread_local std::string text;
+    if (!s) return "";
+    std::lock_guard<std::mutex> lk(const_cast<pp_server*>(s)->mu);
+    text = s->err;
+    return text.c_str();
+}
 
 pp_status pp_stream_open(pp_server* s, int32_t stream_id, pp_frame_desc desc, pp_intrinsics K,
                          const pp_diffuse_params* dp, const pp_ransac_params* rp) {
@@ -510,13 +517,12 @@ pp_status pp_stream_close(pp_server* s, int32_t stream_id) {
 
 pp_status pp_submit(pp_server* s, int32_t stream_id, const uint16_t* depth_host, uint64_t frame_id,
                     uint64_t* ticket) {
-    pp_status c = check(s);
-    if (c != PP_OK) return c;
-    if (!depth_host || !ticket) return PP_E_INVAL;
+    if (!s || !depth_host || !ticket) return PP_E_INVAL;
     int slot;
     Stream* st;
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        if (s->poisoned) return PP_E_HIP;
         auto it = s->streams.find(stream_id);
         if (it == s->streams.end()) return PP_E_INVAL;
         st = &it->second;
@@ -533,6 +539,14 @@ pp_status pp_submit(pp_server* s, int32_t stream_id, const uint16_t* depth_host,
     memcpy(st->in_stage + (size_t)slot * st->in_bytes, depth_host, (size_t)st->desc.width * st->desc.height * 2);
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        // a batch may have failed (the scheduler no longer admits anything) or
+        // the stream been closed while the frame was copied: the frame is then
+        // refused and its slot returned
+        if (s->poisoned || !st->open) {
+            st->free_slots.push_back(slot);
+            st->outstanding--;
+            return s->poisoned ? PP_E_HIP : PP_E_CLOSED;
+        }
         const uint64_t id = ((uint64_t)(uint32_t)stream_id << 40) | (++s->seq & ((1ull << 40) - 1));
         Ticket t;
         t.stream = stream_id;

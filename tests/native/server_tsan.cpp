@@ -109,12 +109,17 @@ int main() {
     CHECK(pp_server_create(&cfg, &s) == PP_OK);
     CHECK(pp_stream_open(s, 0, pp_frame_desc{W, H, W}, K, &dp, &rp) == PP_OK);
     std::vector<uint64_t> ts;
+    int failed = 0;
     for (int k = 0; k < 8; ++k) {
         uint64_t t = 0;
-        CHECK(pp_submit(s, 0, frame.data(), (uint64_t)k, &t) == PP_OK);
-        ts.push_back(t);
+        // once the injected failure has poisoned the server, submissions are refused
+        const pp_status ss = pp_submit(s, 0, frame.data(), (uint64_t)k, &t);
+        CHECK(ss == PP_OK || ss == PP_E_HIP);
+        if (ss == PP_OK)
+            ts.push_back(t);
+        else
+            ++failed;
     }
-    int failed = 0;
     std::thread p2([&] {
         for (uint64_t t : ts) {
             pp_result r{};

@@ -225,7 +225,7 @@ def test_a_failed_batch_poisons_the_server_and_reset_recovers():
     that batch's frames and every frame not yet completed with PP_E_HIP, and
     poisons the server: submits return PP_E_HIP.  pp_server_reset then fails
     what is left, frees the arena, and the server completes new frames."""
-    s = _server(max_batch=2, lanes=1, dry_run_us=5000, dry_run_fail_batch=3)
+    s = _server(max_batch=2, lanes=1, dry_run_us=50000, dry_run_fail_batch=3)  # all 10 queued before it fails
     _open(s)
     ts = [s.submit(0, _frame(k), k) for k in range(10)]
     st = [_poll_status(s, t) for t in ts]
