@@ -62,6 +62,12 @@ struct pp_ctx {
     bool staging_used[kRing] = {false};
     int ring_pos = 0;
     hipStream_t capture_stream = nullptr;
+    // a batch's frames run as up to kMaxChains independent kernel chains: chain 0 on
+    // the launching stream, the others on these, forked and joined by events
+    static constexpr int kMaxChains = 4;
+    hipStream_t chain_stream[kMaxChains] = {};
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kMaxChains] = {};
     std::map<std::string, GraphEntry> graphs;
     uint64_t graph_clock = 0;
     // the stream of the latest enqueue and an event after it: a call on
@@ -375,6 +381,11 @@ pp_status pp_ctx_destroy(pp_ctx* c) {
         if (c->staging_ev[i]) (void)hipEventDestroy(c->staging_ev[i]);
     }
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    for (int k = 0; k < pp_ctx::kMaxChains; ++k) {
+        if (c->chain_stream[k]) (void)hipStreamDestroy(c->chain_stream[k]);
+        if (c->join_ev[k]) (void)hipEventDestroy(c->join_ev[k]);
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     for (int r = 0; r < ppk::kMaxRounds; ++r)
         for (int k = 0; k < 2; ++k)
             if (c->score_ev[r][k]) (void)hipEventDestroy(c->score_ev[r][k]);
@@ -796,8 +807,52 @@ BatchPlan plan_batch(const pp_frame_job* jobs, int n, const ppk::Tuning& tu) {
     return b;
 }
 
+// Frames per kernel chain of a batch: with several chains, one chain's
+// latency-bound kernels (hypotheses, refit, removal of a few frames) overlap
+// with another's scoring, where one chain would leave the GPU mostly idle
+// between its launches.
+constexpr int kChainFrames = 8;
+
+// Frames [f0, f1) of the (sorted) batch table as one chain of launches on st.
+pp_status enqueue_chain(pp_ctx* c, const BatchPlan& b, int f0, int f1, hipStream_t st) {
+    FrameDev* tab = c->batch_tab + f0;
+    const int nf = f1 - f0;
+    for (size_t g = 0; g < b.iter_groups.size(); ++g) {
+        const int g0 = std::max(b.iter_groups[g].first, f0);
+        const int g1 = std::min(b.iter_groups[g].first + b.iter_groups[g].second, f1);
+        if (g0 < g1)
+            HIPCHK(c, ppk::launch_diffuse(c->batch_tab + g0, g1 - g0, b.maxW, b.maxH, b.group_iters[g], b.group_scheme[g],
+                                          c->tuning, st));
+    }
+    HIPCHK(c, ppk::launch_normals(tab, nf, b.maxW, b.maxH, st));
+    HIPCHK(c, ppk::launch_valid_list(tab, nf, b.max_px, b.maxW, b.maxH, st));
+    for (int r = 0; r < b.max_rounds; ++r)
+        HIPCHK(c, ppk::launch_round(tab, nf, r, b.max_scan, b.max_hyps, b.precision, c->tuning, st));
+    return PP_OK;
+}
+
 pp_status enqueue_batch(pp_ctx* c, const BatchPlan& b, hipStream_t st, bool capturing) {
     const bool timed = c->timing && !capturing;
+    const int chains = std::min(pp_ctx::kMaxChains, b.nf / kChainFrames);
+    if (!timed && chains > 1) {
+        for (int k = 1; k < chains; ++k) {
+            if (!c->chain_stream[k]) HIPCHK(c, hipStreamCreateWithFlags(&c->chain_stream[k], hipStreamNonBlocking));
+            if (!c->join_ev[k]) HIPCHK(c, hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming));
+        }
+        if (!c->fork_ev) HIPCHK(c, hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+        HIPCHK(c, hipEventRecord(c->fork_ev, st));
+        for (int k = 1; k < chains; ++k) HIPCHK(c, hipStreamWaitEvent(c->chain_stream[k], c->fork_ev, 0));
+        pp_status s;
+        for (int k = 0; k < chains; ++k) {
+            const int f0 = (int)((int64_t)b.nf * k / chains), f1 = (int)((int64_t)b.nf * (k + 1) / chains);
+            if ((s = enqueue_chain(c, b, f0, f1, k ? c->chain_stream[k] : st)) != PP_OK) return s;
+        }
+        for (int k = 1; k < chains; ++k) {
+            HIPCHK(c, hipEventRecord(c->join_ev[k], c->chain_stream[k]));
+            HIPCHK(c, hipStreamWaitEvent(st, c->join_ev[k], 0));
+        }
+        return PP_OK;
+    }
     if (timed) HIPCHK(c, hipEventRecord(c->stage_ev[0], st));
     for (size_t g = 0; g < b.iter_groups.size(); ++g)
         HIPCHK(c, ppk::launch_diffuse(c->batch_tab + b.iter_groups[g].first, b.iter_groups[g].second, b.maxW, b.maxH,
