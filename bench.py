@@ -59,7 +59,7 @@ def score_kernel_name(precision, tuning):
     form = {"fp32": "vector ALUs", "mfma_f32": "FP32 matrix cores", "bf16": "BF16 matrix cores",
             "fp16": "FP16 matrix cores"}[precision]
     return (f"k_score_tiles<{precision}, {q}> (inlier scoring with 64-point tile culling: most tiles are decided "
-            f"per hypothesis from their bounding box, made at the round's start; undecided ones on the {form})")
+            f"per hypothesis from their bounding box, made with the point list; undecided ones on the {form})")
 
 
 def source_hash():
@@ -292,20 +292,46 @@ def normals_bytes_per_px(valid_frac):
     return 4 + 12 + 12 + 1 + 1 + 4 * valid_frac
 
 
-def hbm_fractions(stage_ms, n_px, iters, T, valid_frac):
+def load_stage_traffic(kernel_hash, size_label):
+    """Counter-measured HBM bytes per pixel of the diffusion and normals stages
+    at one workload size, from the committed rocprofv3 PMC summary, or None
+    when the kernel source changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", "stage_traffic.json")
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_hash:
+        return None
+    return d.get("stages", {}).get(size_label)
+
+
+def hbm_fractions(stage_ms, n_px, iters, T, valid_frac, counted=None):
     """Achieved HBM rates of diffusion (a1) and of back-projection, normals and
-    valid list (a2-a4) from their per-step stage times and algorithmic bytes."""
+    valid list (a2-a4) from their per-step stage times: of their algorithmic
+    bytes, and (counted) of the bytes rocprofv3's counters measured for the
+    same kernels."""
     out = {}
     for name, bpp, ms in (("diffusion", diffusion_bytes_per_px(iters, T), stage_ms["diffusion"]),
                           ("normals_and_valid_list", normals_bytes_per_px(valid_frac), stage_ms["normals"])):
         gbs = bpp * n_px / (ms * 1e-3) / 1e9
         out[name] = {"bytes_per_px": round(bpp, 2), "ms_per_step": round(ms, 4), "gb_per_s": round(gbs, 1),
                      "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 3)}
+        cb = (counted or {}).get(f"{name}_bytes_per_px")
+        if cb:
+            cgbs = cb * n_px / (ms * 1e-3) / 1e9
+            out[name].update({"counter_bytes_per_px": cb, "counter_gb_per_s": round(cgbs, 1),
+                              "counter_frac_of_8tbs": round(cgbs / HBM_PEAK_GBS, 3)})
     out["target_frac"] = 0.6
     out["target_met"] = all(v["frac_of_8tbs"] >= 0.6 for k, v in out.items() if isinstance(v, dict))
-    out["note"] = ("diffusion fuses T iterations per pass in registers and is bound by its arithmetic (two exp per "
-                   "pixel and iteration), not by HBM; the normals stage time also covers the 8x8-ordered scoring list "
-                   "build, whose bytes are not counted here")
+    out["counter_target_met"] = (all(v.get("counter_frac_of_8tbs", 0) >= 0.6 for k, v in out.items()
+                                     if isinstance(v, dict)) if counted else None)
+    out["note"] = ("frac_of_8tbs: algorithmic bytes over the stage time; counter_frac_of_8tbs: the bytes rocprofv3 "
+                   "measured for the same kernels (profiles/stage_traffic.json) over the same time. Diffusion fuses "
+                   "T iterations per pass in registers and is bound by its arithmetic (two exp per pixel and "
+                   "iteration), not by HBM; normals are bound by their arithmetic too (about 194 vector "
+                   "instructions per 64 pixels), and the stage also writes the round-0 scoring list (16.5 B/px), "
+                   "which the algorithmic bytes leave out")
     return out
 
 
@@ -370,7 +396,8 @@ def precision_bench(pp, tuning, n_frames=256, size=(1280, 720), reps=2, forms=No
         if name == "fp32_valu":
             T = tuning["diffuse_t"]
             valid_frac = float(np.mean([(f.depth > 0).mean() for f in base]))
-            rec["hbm"] = hbm_fractions(br, n_frames * W * H, cfg.diffuse_iters, T, valid_frac)
+            rec["hbm"] = hbm_fractions(br, n_frames * W * H, cfg.diffuse_iters, T, valid_frac,
+                                       load_stage_traffic(source_hash(), f"{W}x{H}"))
             rec["stage_ms"] = {k: round(v, 3) for k, v in br.items()}
     ctx.set_stage_timing(False)
     ctx.close()
@@ -618,7 +645,8 @@ def main():
             decided += int(sc[0])
             evaluated += int(sc[1])
     hbm = hbm_fractions({k: v / args.steps for k, v in stage_ms.items()}, args.batch * W * H, cfg.diffuse_iters,
-                        int(tuning["diffuse_t"]), float(np.mean([(f.depth > 0).mean() for f in frames])))
+                        int(tuning["diffuse_t"]), float(np.mean([(f.depth > 0).mean() for f in frames])),
+                        load_stage_traffic(source_hash(), f"{W}x{H}"))
     khash = source_hash()
     traffic = load_traffic(khash)
 
@@ -700,7 +728,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "640x480 straight staircase, 20 diffusion iterations, sequential RANSAC up to "
                                "12 planes x 1024 hypotheses, t = 10 mm",
-                   "batch_frames": args.batch, "form": "batched, one HIP graph replay per step",
+                   "batch_frames": args.batch,
+                   "form": "batched, one HIP graph replay per step; the frames run as up to 4 concurrent kernel "
+                           "chains of 8 or more frames",
                    "scoring": args.precision,
                    "eager_batched_frames_per_s": round(eager_fps, 2),
                    "mpixel_per_s": round(batched_fps * W * H / 1e6, 2),
