@@ -389,9 +389,18 @@ def precision_bench(pp, tuning, n_frames=256, size=(1280, 720), reps=2, forms=No
         wall, br, hb = best
         if fp32_ms is None:
             fp32_ms = br["scoring"]
+        # share of the residuals evaluated point by point that went to the matrix cores (introspection
+        # counters of the per-frame path on two of the frames, same kernels and tuning)
+        ctx.set_tuning(tuning["diffuse_tile"], tuning["diffuse_t"], hb, tuning["score_chunk"])
+        ev = mf = 0
+        for fo in frames[:2]:
+            sc = pp.ransac_planes_debug(fo.points, fo.valid, fo.ransac, ctx=ctx)[3]["scored"].cpu().numpy()
+            ev += int(sc[1])
+            mf += int(sc[2])
         rec["forms"][name] = {"frames_per_s": round(n_frames / wall, 2), "scoring_ms": round(br["scoring"], 3),
                               "scoring_vs_fp32_valu": round(br["scoring"] / fp32_ms, 3), "score_hb": hb,
-                              "recheck_band_m": band, "identical_to_fp32": bool(same)}
+                              "recheck_band_m": band, "identical_to_fp32": bool(same),
+                              "matrix_core_share_of_evaluated": round(mf / ev, 4) if ev else None}
         log(f"precision {W}x{H} {name}: {rec['forms'][name]}")
         if name == "fp32_valu":
             T = tuning["diffuse_t"]

@@ -142,10 +142,10 @@ typedef struct {
  * 0 plane emitted, 1 no valid hypothesis, 2 |F| < min_inliers, -1 not run),
  * masks [max_planes][height*width] (bit0: inlier of j*, bit1: in F),
  * valid_list [height*width] (pixel offsets y*pitch+x) and n_valid [1];
- * scored [2], caller-zeroed, added to by the tile-culled scorers over all
+ * scored [3], caller-zeroed, added to by the tile-culled scorers over all
  * rounds: [0] (64-point tile, hypothesis) pairs decided by the tile's
  * bounding box, [1] residuals evaluated point by point (64 per undecided
- * pair). */
+ * pair), [2] those of [1] evaluated on the matrix cores. */
 typedef struct {
     int32_t* counts;
     float* hyps;

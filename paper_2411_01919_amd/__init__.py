@@ -278,7 +278,7 @@ def ransac_planes_debug(points, valid, cfg: RansacConfig, ctx: Optional[Context]
         masks=torch.zeros((R, H * W), dtype=torch.uint8, device=dev),
         valid_list=torch.zeros((H * W,), dtype=torch.int32, device=dev),
         n_valid=torch.zeros((1,), dtype=torch.int32, device=dev),
-        scored=torch.zeros((2,), dtype=torch.int64, device=dev),
+        scored=torch.zeros((3,), dtype=torch.int64, device=dev),
     )
     dbg = N.RansacDebug(*[_ptr(dbg_t[k]) for k in ("counts", "hyps", "triples", "round_info", "masks",
                                                       "valid_list", "n_valid", "scored")])

@@ -1060,7 +1060,10 @@ __global__ __launch_bounds__(kBlock) void k_round_start(const FrameDev* __restri
 //  - a few of them (or every one, for PP_SCORE_FP32): one at a time with the
 //    canonical formula, the tile's points one per lane (straddle_loop);
 //  - otherwise on the matrix cores, 16 at a time (mfma_groups).
-constexpr int kMfmaMinStraddlers = 40;  // fewer straddlers of a tile go through straddle_loop
+// A tile reaches the matrix cores when at least max(40, 3/8 of the block's)
+// hypotheses straddle it; fewer go through straddle_loop, which costs less per
+// straddler than a 16-hypothesis group on the matrix cores plus its compares.
+constexpr int mfma_min_straddlers(int nh) { return 3 * nh / 8 > 40 ? 3 * nh / 8 : 40; }
 
 // One tile's straddling hypotheses S (bit k: slot k of hyp_lds) against the
 // tile's points (one per lane; lanes past the list's end hold a NaN point,
@@ -1312,7 +1315,7 @@ __global__ __launch_bounds__(kBlock) void k_score_tiles(const FrameDev* __restri
         e_next = ld_global4(box, 2 * tile + 1);
         p_next = ld_global_xyz(pts, min(tile * 64 + lane, M - 1));
     }
-    uint32_t n_tiles = 0, n_straddle = 0;  // this wave's tiles and undecided pairs (introspection)
+    uint32_t n_tiles = 0, n_straddle = 0, n_mfma = 0;  // this wave's tiles, undecided pairs, those on the matrix cores
     for (; tile < ntiles; tile += tstride) {
         const float4 c = c_next, e = e_next;
         float3 p = p_next;
@@ -1337,7 +1340,7 @@ __global__ __launch_bounds__(kBlock) void k_score_tiles(const FrameDev* __restri
         }
         if (ns == 0) continue;
         n_straddle += ns;
-        if (!MF || ns < kMfmaMinStraddlers) {
+        if (!MF || ns < mfma_min_straddlers(NH)) {
             asm volatile("" : "+v"(p.x), "+v"(p.y), "+v"(p.z));  // keeps the select out of the loops below
 #pragma unroll
             for (int q = 0; q < Q; ++q)
@@ -1345,6 +1348,7 @@ __global__ __launch_bounds__(kBlock) void k_score_tiles(const FrameDev* __restri
             continue;
         }
         if constexpr (MF) {
+            n_mfma += ns;
             // the tile's points and the straddlers' slots (in slot order); one
             // wave's LDS accesses complete in order, so no barrier is needed
             s_p[wave][lane] = make_float4(p.x, p.y, p.z, 1.f);
@@ -1375,6 +1379,7 @@ __global__ __launch_bounds__(kBlock) void k_score_tiles(const FrameDev* __restri
         const uint32_t nvalid = (uint32_t)min(NH, hyps - h0);
         atomicAdd(f.dbg.scored, (unsigned long long)n_tiles * nvalid - n_straddle);
         atomicAdd(f.dbg.scored + 1, 64ull * n_straddle);
+        if (n_mfma) atomicAdd(f.dbg.scored + 2, 64ull * n_mfma);
     }
     __syncthreads();
     for (int j = threadIdx.x; j < NH; j += kBlock) {

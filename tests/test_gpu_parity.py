@@ -543,7 +543,13 @@ def test_matrix_core_forms_equal_the_fp32_path_bitwise(pp, cid, k, size, hb):
         assert np.array_equal(g["labels"], ref["labels"]), key
         for a, b in zip(g["planes"], ref["planes"]):
             assert np.array_equal(a["n"], b["n"]) and a["d"] == b["d"], key
-    log(f"  cfg={cid} k={k}: {ref['n_planes']} planes identical under every scoring form")
+    # residuals evaluated on the matrix cores (dbg scored[2]) among those evaluated point by point ([1])
+    share = {key: int(g["dbg"]["scored"][2]) / max(1, int(g["dbg"]["scored"][1])) for key, g in runs.items()}
+    assert share[(pp.PP_SCORE_FP32, 0.0)] == 0.0
+    if hb == 4 or size is not None:  # 64 hypotheses a block, or 4096 hypotheses a round: dense tiles exist
+        assert all(v > 0.0 for key, v in share.items() if key[0] != pp.PP_SCORE_FP32), share
+    log(f"  cfg={cid} k={k}: {ref['n_planes']} planes identical under every scoring form; matrix-core share "
+        + ", ".join(f"{v:.2f}" for key, v in share.items() if key[0] != pp.PP_SCORE_FP32))
 
 
 @pytest.mark.parametrize("prec,band", [(1, 0.0), (2, 0.002), (3, 0.002), (2, 0.0)])
