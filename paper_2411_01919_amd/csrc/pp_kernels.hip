@@ -750,7 +750,6 @@ __device__ __forceinline__ void tile_boxes(const float4* src, int ntiles, float4
 // scorers' recheck bands use.  A block takes 16 tiles (1024 positions) per
 // step, staged in LDS for the boxes.
 __global__ __launch_bounds__(kBlock) void k_list0(const FrameDev* __restrict__ tab) {
-    constexpr int S = kValidChunk / kBlock;
     __shared__ float4 stage[kValidChunk];
     __shared__ float shf[4];
     const FrameDev& f = tab[blockIdx.z];
@@ -761,40 +760,78 @@ __global__ __launch_bounds__(kBlock) void k_list0(const FrameDev* __restrict__ t
     const gf32_cptr pg = (gf32_cptr)f.pts;
     const gi32_cptr lpos = (gi32_cptr)f.delta[0];
     float4* __restrict__ out = f.list[0];
+    // a thread takes 4 consecutive scan positions, 4 pixels of one row of one 8x8 block
+    // (x0 a multiple of 4): one 16-byte load per plane where the rows allow it
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const bool vec_pts = (((uintptr_t)f.pts | (uintptr_t)(f.pitch * 4) | (uintptr_t)(plane * 4)) & 15) == 0;
+    const bool vec_flags = (((uintptr_t)f.valid | (uintptr_t)f.pitch) & 3) == 0;
+    const bool vec_lpos = (f.W & 3) == 0;
     float p1 = 0.f;
     for (int c = blockIdx.x; c < nchq; c += gridDim.x) {
-        int off[S], lp[S];
-        bool v[S];
-        uint8_t vb[S];
-        float px[S], py[S], pz[S];
+        const int q0 = c * kValidChunk + 4 * (int)threadIdx.x;
+        int x0 = 0, y = 0;
+        const bool in_scan = q0 < nq;
+        scan_pixel(f, q0, x0, y);  // (x0, y) of position q0, possibly past the frame's edge
+        const bool row_in = in_scan && y < f.H;
+        const bool full = row_in && x0 + 3 < f.W;  // all 4 pixels inside the frame
+        float px[4] = {0.f, 0.f, 0.f, 0.f}, py[4] = {0.f, 0.f, 0.f, 0.f}, pz[4] = {0.f, 0.f, 0.f, 0.f};
+        int vb[4] = {0, 0, 0, 0}, lp[4] = {0, 0, 0, 0};
+        const uint32_t o = (uint32_t)y * (uint32_t)f.pitch + (uint32_t)x0;
+        if (full && vec_pts) {
+            const v4f a = *(const __attribute__((address_space(1))) v4f*)(pg + o);
+            const v4f b = *(const __attribute__((address_space(1))) v4f*)(pg + plane + o);
+            const v4f d = *(const __attribute__((address_space(1))) v4f*)(pg + 2 * plane + o);
 #pragma unroll
-        for (int k = 0; k < S; ++k) {
-            int x = 0, y = 0;
-            v[k] = scan_pixel(f, c * kValidChunk + k * kBlock + threadIdx.x, x, y);
-            if (!v[k]) x = y = 0;
-            off[k] = y * f.pitch + x;
-            lp[k] = y * f.W + x;
-        }
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            vb[k] = vg[off[k]];
-            px[k] = pg[off[k]];
-            py[k] = pg[plane + off[k]];
-            pz[k] = pg[2 * plane + off[k]];
-            lp[k] = lpos[lp[k]];
-        }
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            const int i = k * kBlock + threadIdx.x;
-            float4 q = pad_point();
-            if (v[k] && (vb[k] & 1)) {
-                q = make_float4(px[k], py[k], pz[k], __int_as_float(lp[k]));
-                p1 = fmaxf(p1, fabsf(px[k]) + fabsf(py[k]) + fabsf(pz[k]));
+            for (int j = 0; j < 4; ++j) {
+                px[j] = a[j];
+                py[j] = b[j];
+                pz[j] = d[j];
             }
-            if (c * kValidChunk + i < nq) out[c * kValidChunk + i] = q;
-            stage[i] = q;
+        } else if (row_in) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (x0 + j < f.W) {
+                    px[j] = pg[o + j];
+                    py[j] = pg[plane + o + j];
+                    pz[j] = pg[2 * plane + o + j];
+                }
+        }
+        if (full && vec_flags) {
+            const uint32_t w = *(const __attribute__((address_space(1))) uint32_t*)(vg + o);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) vb[j] = (w >> (8 * j)) & 1;
+        } else if (row_in) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (x0 + j < f.W) vb[j] = vg[o + j] & 1;
+        }
+        const int lo = y * f.W + x0;
+        if (full && vec_lpos) {
+            const v4i l4 = *(const __attribute__((address_space(1))) v4i*)(lpos + lo);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) lp[j] = l4[j];
+        } else if (row_in) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (x0 + j < f.W && vb[j]) lp[j] = lpos[lo + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float4 q = pad_point();
+            if (vb[j]) {
+                q = make_float4(px[j], py[j], pz[j], __int_as_float(lp[j]));
+                p1 = fmaxf(p1, fabsf(px[j]) + fabsf(py[j]) + fabsf(pz[j]));
+            }
+            stage[4 * threadIdx.x + j] = q;
         }
         __syncthreads();
+        // the chunk's positions in order, one 16-byte store per thread and step
+#pragma unroll
+        for (int k = 0; k < kValidChunk / kBlock; ++k) {
+            const int i = k * kBlock + threadIdx.x;
+            if (c * kValidChunk + i < nq) out[c * kValidChunk + i] = stage[i];
+        }
         const int ntiles = min(kValidChunk, nq - c * kValidChunk) >> 6;
         tile_boxes(stage, ntiles, f.tbox + 2 * (c * kValidChunk >> 6), threadIdx.x >> 6, kBlock / 64);
         __syncthreads();  // the stage is reused by the next chunk
