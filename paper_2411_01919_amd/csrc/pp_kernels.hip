@@ -1582,6 +1582,29 @@ __device__ void solve_refit(const FrameDev& f, int M, double sx, double sy, doub
     *nmom = n;
 }
 
+// The tiles that a wave takes in chunk c of a refit or removal pass (step s:
+// tile (c chunk + s 256) / 64 + wave) which hold no point with |n.p + d| < t
+// for the plane h, decided from the tile boxes as the scorer decides them
+// (hi = t + 16 u (P1 + |d|)): bit s, the same in every lane.  Tiles of padding
+// only and tiles past the chunk's end e are in the set too.  Lane s gets the
+// number of points of step s's tile in *cnt (0 in other lanes).
+__device__ __forceinline__ unsigned long long tiles_outside(const FrameDev& f, int c, int e, float4 h, float hi,
+                                                            int* cnt) {
+    const int lane = threadIdx.x & 63;
+    const int first = c * kRefitChunk + lane * kBlock + (threadIdx.x & ~63);  // the tile's first point (lane < steps)
+    bool out = true;
+    *cnt = 0;
+    if (lane < kChunkSteps && first < e) {
+        const float4 bc = ld_global4(f.tbox, 2 * (first >> 6));
+        const float4 be = ld_global4(f.tbox, 2 * (first >> 6) + 1);
+        *cnt = __float_as_int(bc.w);
+        const float a = fabsf(fmaf(h.x, bc.x, fmaf(h.y, bc.y, fmaf(h.z, bc.z, h.w))));
+        const float ext = fmaf(fabsf(h.x), be.x, fmaf(fabsf(h.y), be.y, fabsf(h.z) * be.z));
+        out = *cnt == 0 || a - ext >= hi;
+    }
+    return __ballot(out);
+}
+
 __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __restrict__ tab, int r) {
     __shared__ int shk[8];
     __shared__ double shd[4][10];
@@ -1609,14 +1632,19 @@ __global__ __launch_bounds__(kBlock) void k_refit_moments(const FrameDev* __rest
     const float4 p0 = ld_global4(f.hyp_p0, js);  // the first point of j*'s triple
     const double sx = p0.x, sy = p0.y, sz = p0.z;
     const float t = f.thresh;
+    const float hi = t + 16.f * 5.9604645e-8f * (__uint_as_float(f.st->p1max_bits) + fabsf(h.w));
     const float4* __restrict__ pts = f.list[r & 1];
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
         double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         const int e = min(M, (c + 1) * kRefitChunk);
-        // every point of this thread in flight at once, then accumulated in index order
+        // tiles without inliers add nothing: their points are not loaded
+        int tcnt;
+        const unsigned long long skip = tiles_outside(f, c, e, h, hi, &tcnt);
+        // every other point of this thread in flight at once, then accumulated in index order
         float4 pp[kChunkSteps];
 #pragma unroll
-        for (int s = 0; s < kChunkSteps; ++s) pp[s] = ld_global4(pts, min(c * kRefitChunk + s * kBlock + (int)threadIdx.x, e - 1));
+        for (int s = 0; s < kChunkSteps; ++s)
+            pp[s] = (skip >> s) & 1ull ? pad_point() : ld_global4(pts, min(c * kRefitChunk + s * kBlock + (int)threadIdx.x, e - 1));
 #pragma unroll
         for (int s = 0; s < kChunkSteps; ++s) {
             const float4 p = pp[s];
@@ -1678,6 +1706,11 @@ __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restri
     solve_refit(f, M, p0.x, p0.y, p0.z, s_plane, s_cent, &s_n, s_red);
     __syncthreads();
     const SplitPlane q = split_plane(s_plane);
+    // the refit plane rounded to FP32 differs from it by at most u/2 (|p|_1 + |d|) in a
+    // residual, which the box test's margin covers along with refit_res's own error
+    const float4 qf = make_float4(q.hx, q.hy, q.hz, q.hd);
+    const float hi = t + 16.f * 5.9604645e-8f * (__uint_as_float(f.st->p1max_bits) + fabsf(q.hd));
+    int keep_skipped = 0;  // points of this lane's skipped tile (lanes below the step count)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         RoundState* st = f.st;
         for (int k = 0; k < 4; ++k) st->plane[k] = s_plane[k];
@@ -1693,6 +1726,7 @@ __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restri
             nF += f_in ? 1 : 0;
             keep += (in && !f_in && pp[s].x == pp[s].x) ? 1 : 0;
         }
+        keep += keep_skipped;
         block_sum2(nF, keep, sh);
         if (threadIdx.x == 0) {
             f.chunk_cnt[c] = nF;
@@ -1701,8 +1735,14 @@ __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restri
         c += gridDim.x;
         if (c >= nch) break;
         e = min(M, (c + 1) * kRefitChunk);
+        // later chunks: a tile that the boxes put wholly outside the refit plane's band
+        // keeps all its points, which are then not loaded
+        int tcnt;
+        const unsigned long long skip = tiles_outside(f, c, e, qf, hi, &tcnt);
+        keep_skipped = ((skip >> (threadIdx.x & 63)) & 1ull) ? tcnt : 0;
 #pragma unroll
-        for (int s = 0; s < kChunkSteps; ++s) pp[s] = ld_global4(pts, min(c * kRefitChunk + s * kBlock + (int)threadIdx.x, e - 1));
+        for (int s = 0; s < kChunkSteps; ++s)
+            pp[s] = (skip >> s) & 1ull ? pad_point() : ld_global4(pts, min(c * kRefitChunk + s * kBlock + (int)threadIdx.x, e - 1));
     }
 }
 
