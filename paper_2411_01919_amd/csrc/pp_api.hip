@@ -532,7 +532,7 @@ pp_status pp_normals(pp_ctx* c, const float* depth_mm_dev, pp_frame_desc desc, p
     f.ifx = 1.0f / K.fx; f.ify = 1.0f / K.fy;
     hipStream_t st = (hipStream_t)stream;
     if ((s = put_plain(c, f, st)) != PP_OK) return s;
-    HIPCHK(c, ppk::launch_normals(c->plain_tab, 1, desc.width, desc.height, st));
+    HIPCHK(c, ppk::launch_normals(c->plain_tab, 1, desc.width * desc.height, false, st));
     return mark_stream(c, st);
 }
 
@@ -559,7 +559,7 @@ static pp_status ransac_common(pp_ctx* c, const float* points_dev, const uint8_t
         if (dbg->round_info) HIPCHK(c, hipMemsetAsync(dbg->round_info, 0xFF, sizeof(int32_t) * 4 * p->max_planes, st));
     }
     if ((s = put_plain(c, f, st)) != PP_OK) return s;
-    HIPCHK(c, ppk::launch_valid_list(c->plain_tab, 1, (int)px, desc.width, desc.height, st));
+    HIPCHK(c, ppk::launch_valid_list(c->plain_tab, 1, (int)px, desc.width, desc.height, false, st));
     for (int r = 0; r < p->max_planes; ++r)
         HIPCHK(c, ppk::launch_round(c->plain_tab, 1, r, (int)ppk::scan_pixels(desc.width, desc.height), p->hyps_per_plane, p->precision, c->tuning, st,
                                     c->timing ? c->score_ev[r][0] : nullptr, c->timing ? c->score_ev[r][1] : nullptr));
@@ -743,7 +743,7 @@ pp_status pp_debug_score_triples(pp_ctx* c, const float* points_dev, const uint8
     f.n_planes = reinterpret_cast<int32_t*>(static_cast<char*>(c->debug_scratch) + align256(px));
     hipStream_t st = (hipStream_t)stream;
     if ((s = put_plain(c, f, st)) != PP_OK) return s;
-    HIPCHK(c, ppk::launch_valid_list(c->plain_tab, 1, (int)px, desc.width, desc.height, st));
+    HIPCHK(c, ppk::launch_valid_list(c->plain_tab, 1, (int)px, desc.width, desc.height, false, st));
     hipLaunchKernelGGL(k_force_active, dim3(1), dim3(1), 0, st, c->plain_tab);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, ppk::launch_hyp_from_triples(c->plain_tab, triples_dev, n, st));
@@ -824,8 +824,8 @@ pp_status enqueue_chain(pp_ctx* c, const BatchPlan& b, int f0, int f1, hipStream
             HIPCHK(c, ppk::launch_diffuse(c->batch_tab + g0, g1 - g0, b.maxW, b.maxH, b.group_iters[g], b.group_scheme[g],
                                           c->tuning, st));
     }
-    HIPCHK(c, ppk::launch_normals(tab, nf, b.maxW, b.maxH, st));
-    HIPCHK(c, ppk::launch_valid_list(tab, nf, b.max_px, b.maxW, b.maxH, st));
+    HIPCHK(c, ppk::launch_normals(tab, nf, b.max_px, true, st));
+    HIPCHK(c, ppk::launch_valid_list(tab, nf, b.max_px, b.maxW, b.maxH, true, st));
     for (int r = 0; r < b.max_rounds; ++r)
         HIPCHK(c, ppk::launch_round(tab, nf, r, b.max_scan, b.max_hyps, b.precision, c->tuning, st));
     return PP_OK;
@@ -858,8 +858,8 @@ pp_status enqueue_batch(pp_ctx* c, const BatchPlan& b, hipStream_t st, bool capt
         HIPCHK(c, ppk::launch_diffuse(c->batch_tab + b.iter_groups[g].first, b.iter_groups[g].second, b.maxW, b.maxH,
                                       b.group_iters[g], b.group_scheme[g], c->tuning, st));
     if (timed) HIPCHK(c, hipEventRecord(c->stage_ev[1], st));
-    HIPCHK(c, ppk::launch_normals(c->batch_tab, b.nf, b.maxW, b.maxH, st));
-    HIPCHK(c, ppk::launch_valid_list(c->batch_tab, b.nf, b.max_px, b.maxW, b.maxH, st));
+    HIPCHK(c, ppk::launch_normals(c->batch_tab, b.nf, b.max_px, true, st));
+    HIPCHK(c, ppk::launch_valid_list(c->batch_tab, b.nf, b.max_px, b.maxW, b.maxH, true, st));
     if (timed) HIPCHK(c, hipEventRecord(c->stage_ev[2], st));
     for (int r = 0; r < b.max_rounds; ++r)
         HIPCHK(c, ppk::launch_round(c->batch_tab, b.nf, r, b.max_scan, b.max_hyps, b.precision, c->tuning, st,
@@ -1103,7 +1103,7 @@ pp_status pp_ransac_planes_noalloc(const float* points_dev, const uint8_t* valid
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_set_frame, dim3(1), dim3(1), 0, st, tab, f);
     e = hipGetLastError();
-    if (e == hipSuccess) e = ppk::launch_valid_list(tab, 1, (int)px, desc.width, desc.height, st);
+    if (e == hipSuccess) e = ppk::launch_valid_list(tab, 1, (int)px, desc.width, desc.height, false, st);
     for (int r = 0; e == hipSuccess && r < p->max_planes; ++r)
         e = ppk::launch_round(tab, 1, r, (int)ppk::scan_pixels(desc.width, desc.height), p->hyps_per_plane, p->precision, kDefaultTuning, st);
     if (e != hipSuccess) return fail(nullptr, PP_E_HIP, std::string("pp_ransac_planes_noalloc: ") + hipGetErrorString(e));

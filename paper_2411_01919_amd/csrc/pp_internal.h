@@ -107,8 +107,10 @@ bool t_supported(int t);
 // the *max* arguments bound the per-frame sizes and size the grids.
 hipError_t launch_diffuse(const FrameDev* tab, int nf, int maxW, int maxH, int iters_max, int scheme,
                           const Tuning& tu, hipStream_t s);
-hipError_t launch_normals(const FrameDev* tab, int nf, int maxW, int maxH, hipStream_t s);
-hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, int maxW, int maxH, hipStream_t s);
+// count: the normals pass also writes the valid-list chunk counts, and the
+// following launch_valid_list is then called with counted = true
+hipError_t launch_normals(const FrameDev* tab, int nf, int max_px, bool count, hipStream_t s);
+hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, int maxW, int maxH, bool counted, hipStream_t s);
 hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_hyps, int precision,
                         const Tuning& tu, hipStream_t s, hipEvent_t score_start = nullptr,
                         hipEvent_t score_end = nullptr);

@@ -430,47 +430,29 @@ __device__ __forceinline__ float plane_ld(const float* base, uint32_t i) {
     return *(const __attribute__((address_space(1))) float*)((const gbyte*)base + i * 4u);
 }
 
-__global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__ tab) {
-    const FrameDev& f = tab[blockIdx.z];
-    const int W = f.W, H = f.H, pitch = f.pitch;
-    // a wave is one image row: y and the row offsets are wave-uniform (scalar)
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (x >= W || y >= H) return;
-    const uint32_t o = (uint32_t)y * (uint32_t)pitch + (uint32_t)x;
-    const size_t plane = (size_t)H * pitch;
-    // the 3x3 neighbourhood in one batch of loads (indices clamped into the frame;
-    // clamped values are used only where the pixel is not interior, i.e. never)
-    float nbv[3][3];
-    {
-        const float* dm = f.dmm;
-        const uint32_t xs[3] = {(uint32_t)max(x - 1, 0), (uint32_t)x, (uint32_t)min(x + 1, W - 1)};
-        const uint32_t ys[3] = {(uint32_t)max(y - 1, 0), (uint32_t)y, (uint32_t)min(y + 1, H - 1)};
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-                nbv[j][i] = plane_ld(dm, ys[j] * (uint32_t)pitch + xs[i]);
-    }
-    const float I = nbv[1][1];
+// Point and normal of pixel (x, y) from its 3x3 depth window nb (mm; values
+// outside the frame are never used): the back-projected point (zero without
+// depth), the unit normal of the product-rule Sobel responses (zero unless
+// the pixel is interior with a full window and a non-degenerate cross
+// product) and the flags (1: depth, 2: normal).
+__device__ __forceinline__ uint8_t normal_pixel(const FrameDev& f, int x, int y, const float (&nb)[3][3], float& px,
+                                                float& py, float& pz, float& n0, float& n1, float& n2) {
+    const float I = nb[1][1];
     const bool dv = I > 0.f;
-    float px = 0.f, py = 0.f, pz = 0.f;
+    px = py = pz = 0.f;
     if (dv) {
         const float z = I / 1000.0f;
         px = z * ((float)x - f.cx) / f.fx;
         py = z * ((float)y - f.cy) / f.fy;
         pz = z;
     }
-    *plane_at(f.pts, o) = px;
-    *plane_at(f.pts + plane, o) = py;
-    *plane_at(f.pts + 2 * plane, o) = pz;
-    bool nv = dv && x >= 1 && x <= W - 2 && y >= 1 && y <= H - 2;
-    float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+    bool nv = dv && x >= 1 && x <= f.W - 2 && y >= 1 && y <= f.H - 2;
+    n0 = n1 = n2 = 0.f;
     if (nv) {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) nv = nv && (nbv[j][i] > 0.f);
+            for (int i = 0; i < 3; ++i) nv = nv && (nb[j][i] > 0.f);
         if (nv) {
             // sums of w * dI * (u - cx), w * dI * (v - cy), w * dI for both kernels;
             // w dI is exact (w is 0, +-1 or +-2), one rounding per term
@@ -483,7 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__
                     const float wx = (float)(i - 1) * wrow[j];  // Sobel x: [-1 0 1] x [1 2 1]^T
                     const float wy = (float)(j - 1) * wrow[i];  // Sobel y: its transpose
                     if (wx == 0.f && wy == 0.f) continue;
-                    const float dI = nbv[j][i] - I;
+                    const float dI = nb[j][i] - I;
                     const float uu = (float)(x + i - 1) - f.cx;
                     const float vv = (float)(y + j - 1) - f.cy;
                     const float ex = wx * dI, ey = wy * dI;
@@ -507,10 +489,115 @@ __global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__
             }
         }
     }
-    *plane_at(f.nrm, o) = n0;
-    *plane_at(f.nrm + plane, o) = n1;
-    *plane_at(f.nrm + 2 * plane, o) = n2;
-    *plane_at(f.valid, o) = (uint8_t)((dv ? 1 : 0) | (nv ? 2 : 0));
+    return (uint8_t)((dv ? 1 : 0) | (nv ? 2 : 0));
+}
+
+// Points, normals and flags of one 1024-pixel row-major chunk per block, 4
+// consecutive pixels per thread.  Four pixels of one row share one 3x6
+// window (a 16-byte load per row where rows are 16-byte aligned) and are
+// stored 16 bytes per plane.  With count set, the block also writes its
+// chunk's number of depth-valid pixels for the valid list (and block 0 resets
+// the frame's |p|_1 bound), which makes the separate count pass unnecessary.
+__global__ __launch_bounds__(kBlock) void k_normals(const FrameDev* __restrict__ tab, int count) {
+    __shared__ int sh[4];
+    const FrameDev& f = tab[blockIdx.z];
+    const int W = f.W, H = f.H, pitch = f.pitch;
+    const int npx = W * H;
+    const int c = blockIdx.x;
+    if (c * kValidChunk >= npx) return;  // the whole block: this frame has fewer chunks
+    if (count && c == 0 && threadIdx.x == 0) f.st->p1max_bits = 0u;
+    const size_t plane = (size_t)H * pitch;
+    const float* dm = f.dmm;
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) v4f gv4f;
+    const bool vec_in = (((uintptr_t)dm | (uintptr_t)(pitch * 4)) & 15) == 0;
+    const bool vec_out = (((uintptr_t)f.pts | (uintptr_t)f.nrm | (uintptr_t)(pitch * 4) | (uintptr_t)(plane * 4)) & 15) == 0 &&
+                         (((uintptr_t)f.valid) & 3) == 0;
+    const int p0 = c * kValidChunk + 4 * (int)threadIdx.x;
+    int cnt = 0;
+    if (p0 < npx) {
+        const int y = p0 / W, x0 = p0 - y * W;
+        if (x0 + 3 < W) {
+            const uint32_t ys[3] = {(uint32_t)max(y - 1, 0), (uint32_t)y, (uint32_t)min(y + 1, H - 1)};
+            const uint32_t xl = (uint32_t)max(x0 - 1, 0), xr = (uint32_t)min(x0 + 4, W - 1);
+            float win[3][6];
+            const bool v4 = vec_in && (x0 & 3) == 0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const uint32_t r = ys[j] * (uint32_t)pitch;
+                win[j][0] = plane_ld(dm, r + xl);
+                if (v4) {
+                    const v4f m = *(const gv4f*)((const gbyte*)dm + (r + (uint32_t)x0) * 4u);
+                    win[j][1] = m[0]; win[j][2] = m[1]; win[j][3] = m[2]; win[j][4] = m[3];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) win[j][1 + i] = plane_ld(dm, r + (uint32_t)(x0 + i));
+                }
+                win[j][5] = plane_ld(dm, r + xr);
+            }
+            float px[4], py[4], pz[4], n0[4], n1[4], n2[4];
+            uint32_t flags = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float nb[3][3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) nb[j][i] = win[j][k + i];
+                const uint8_t fl = normal_pixel(f, x0 + k, y, nb, px[k], py[k], pz[k], n0[k], n1[k], n2[k]);
+                flags |= (uint32_t)fl << (8 * k);
+                cnt += fl & 1;
+            }
+            const uint32_t o = (uint32_t)y * (uint32_t)pitch + (uint32_t)x0;
+            if (vec_out && (x0 & 3) == 0) {
+                *(gv4f*)((gbyte*)f.pts + o * 4u) = v4f{px[0], px[1], px[2], px[3]};
+                *(gv4f*)((gbyte*)(f.pts + plane) + o * 4u) = v4f{py[0], py[1], py[2], py[3]};
+                *(gv4f*)((gbyte*)(f.pts + 2 * plane) + o * 4u) = v4f{pz[0], pz[1], pz[2], pz[3]};
+                *(gv4f*)((gbyte*)f.nrm + o * 4u) = v4f{n0[0], n0[1], n0[2], n0[3]};
+                *(gv4f*)((gbyte*)(f.nrm + plane) + o * 4u) = v4f{n1[0], n1[1], n1[2], n1[3]};
+                *(gv4f*)((gbyte*)(f.nrm + 2 * plane) + o * 4u) = v4f{n2[0], n2[1], n2[2], n2[3]};
+                *(__attribute__((address_space(1))) uint32_t*)((gbyte*)f.valid + o) = flags;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    *plane_at(f.pts, o + k) = px[k];
+                    *plane_at(f.pts + plane, o + k) = py[k];
+                    *plane_at(f.pts + 2 * plane, o + k) = pz[k];
+                    *plane_at(f.nrm, o + k) = n0[k];
+                    *plane_at(f.nrm + plane, o + k) = n1[k];
+                    *plane_at(f.nrm + 2 * plane, o + k) = n2[k];
+                    *plane_at(f.valid, o + k) = (uint8_t)(flags >> (8 * k));
+                }
+            }
+        } else {
+            // the 4 pixels wrap to the next row (or end the frame): one at a time
+            for (int k = 0; k < 4 && p0 + k < npx; ++k) {
+                const int yk = (p0 + k) / W, xk = p0 + k - yk * W;
+                const uint32_t xs[3] = {(uint32_t)max(xk - 1, 0), (uint32_t)xk, (uint32_t)min(xk + 1, W - 1)};
+                const uint32_t ys[3] = {(uint32_t)max(yk - 1, 0), (uint32_t)yk, (uint32_t)min(yk + 1, H - 1)};
+                float nb[3][3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) nb[j][i] = plane_ld(dm, ys[j] * (uint32_t)pitch + xs[i]);
+                float px, py, pz, n0, n1, n2;
+                const uint8_t fl = normal_pixel(f, xk, yk, nb, px, py, pz, n0, n1, n2);
+                const uint32_t o = (uint32_t)yk * (uint32_t)pitch + (uint32_t)xk;
+                *plane_at(f.pts, o) = px;
+                *plane_at(f.pts + plane, o) = py;
+                *plane_at(f.pts + 2 * plane, o) = pz;
+                *plane_at(f.nrm, o) = n0;
+                *plane_at(f.nrm + plane, o) = n1;
+                *plane_at(f.nrm + 2 * plane, o) = n2;
+                *plane_at(f.valid, o) = fl;
+                cnt += fl & 1;
+            }
+        }
+    }
+    if (count) {
+        cnt = block_sum(cnt, sh);
+        if (threadIdx.x == 0) f.chunk_cnt[c] = cnt;
+    }
 }
 
 // ------------------------------------------------------------------ valid list
@@ -567,16 +654,20 @@ __global__ __launch_bounds__(kBlock) void k_valid_count(const FrameDev* __restri
 }
 
 __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __restrict__ tab) {
-    constexpr int S = kValidChunk / kBlock;  // steps of one chunk
-    __shared__ int sh[4 * S];
+    __shared__ int sh[8];
+    __shared__ int s_off[kValidChunk];
     const FrameDev& f = tab[blockIdx.z];
     const int npx = f.W * f.H;
     const int nch = (npx + kValidChunk - 1) / kValidChunk;
-    // valid-list position of every depth-valid pixel, [H][W]; the diffusion
-    // ping-pong buffer is free by now
+    // valid-list position of every pixel, [H][W] (-1 without depth); the
+    // diffusion ping-pong buffer is free by now
     int32_t* __restrict__ lpos = reinterpret_cast<int32_t*>(f.delta[0]);
     const gu8_cptr vg = (gu8_cptr)f.valid;
     const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt;
+    // flags and labels of 4 pixels of one row as one 32-bit word where rows allow it
+    const bool words = (((uintptr_t)f.valid | (uintptr_t)f.labels | (uintptr_t)f.pitch) & 3) == 0;
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // valid pixels before chunk c, carried from this block's previous chunk
     int before = 0;
     for (int c = blockIdx.x; c < nch; c += gridDim.x) {
@@ -585,36 +676,78 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
             for (int i = c - (c == (int)blockIdx.x ? c : (int)gridDim.x) + threadIdx.x; i < c; i += kBlock) add += ccnt[i];
             before += block_sum(add, sh);
         }
-        // all loads of the chunk's steps first (indices clamped into the frame)
-        int off[S];
-        bool in[S], v[S];
-        uint8_t vb[S];
+        // pixels p0 .. p0 + 3 (row-major), 4 per thread
+        const int p0 = c * kValidChunk + 4 * (int)threadIdx.x;
+        const int y0 = p0 / f.W, x0 = p0 - y0 * f.W;
+        const bool row4 = p0 + 3 < npx && x0 + 3 < f.W;
+        int off[4];
+        int bits = 0;
+        if (row4) {
+            const int o = y0 * f.pitch + x0;
 #pragma unroll
-        for (int k = 0; k < S; ++k) {
-            const int p = c * kValidChunk + k * kBlock + threadIdx.x;
-            in[k] = p < npx;
-            const int pc = in[k] ? p : 0;
-            const int y = pc / f.W, x = pc - y * f.W;
-            off[k] = y * f.pitch + x;
-        }
+            for (int j = 0; j < 4; ++j) off[j] = o + j;
+            if (words) {
+                const uint32_t w = *(const __attribute__((address_space(1))) uint32_t*)(vg + o);
+                bits = (int)((w & 1u) | ((w >> 7) & 2u) | ((w >> 14) & 4u) | ((w >> 21) & 8u));
+                *reinterpret_cast<uint32_t*>(f.labels + o) = 0xFFFFFFFFu;
+            } else {
 #pragma unroll
-        for (int k = 0; k < S; ++k) vb[k] = vg[off[k]];
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            v[k] = in[k] && (vb[k] & 1);
-            if (in[k]) f.labels[off[k]] = -1;
-        }
-        int rank[S], tot;
-        block_rank_steps<S>(v, sh, rank, tot);
-#pragma unroll
-        for (int k = 0; k < S; ++k)
-            if (v[k]) {
-                const int kk = before + rank[k];
-                f.L[kk] = off[k];
-                f.taken[kk] = 0;
-                lpos[c * kValidChunk + k * kBlock + threadIdx.x] = kk;
-                if (f.dbg.valid_list) f.dbg.valid_list[kk] = off[k];
+                for (int j = 0; j < 4; ++j) {
+                    bits |= (vg[o + j] & 1) << j;
+                    f.labels[o + j] = -1;
+                }
             }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int p = min(p0 + j, npx - 1);
+                const int y = p / f.W, x = p - y * f.W;
+                off[j] = y * f.pitch + x;
+                if (p0 + j < npx) {
+                    bits |= (vg[off[j]] & 1) << j;
+                    f.labels[off[j]] = -1;
+                }
+            }
+        }
+        // row-major ranks: the valid pixels of lower lanes and waves, then this thread's lower ones
+        unsigned long long m[4];
+        int below = 0, wtot = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            m[j] = __ballot((bits >> j) & 1);
+            below += __popcll(m[j] & lanemask_lt());
+            wtot += __popcll(m[j]);
+        }
+        if (lane == 0) sh[4 + wave] = wtot;  // block_sum uses sh[0..3]
+        __syncthreads();
+        int base = before + below, tot = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            base += w < wave ? sh[4 + w] : 0;
+            tot += sh[4 + w];
+        }
+        int kk[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            kk[j] = (bits >> j) & 1 ? base : -1;
+            base += (bits >> j) & 1;
+        }
+        // the chunk's entries of L through LDS, so that consecutive lanes store consecutive entries
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (kk[j] >= 0) s_off[kk[j] - before] = off[j];
+        __syncthreads();
+        for (int i = threadIdx.x; i < tot; i += kBlock) {
+            f.L[before + i] = s_off[i];
+            f.taken[before + i] = 0;
+            if (f.dbg.valid_list) f.dbg.valid_list[before + i] = s_off[i];
+        }
+        if (p0 + 3 < npx) {
+            *reinterpret_cast<v4i*>(lpos + p0) = v4i{kk[0], kk[1], kk[2], kk[3]};
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (p0 + j < npx) lpos[p0 + j] = kk[j];
+        }
         const int run = before + tot;
         if (c == nch - 1 && threadIdx.x == 0) {
             RoundState* st = f.st;
@@ -1958,17 +2091,18 @@ hipError_t launch_diffuse(const FrameDev* tab, int nf, int maxW, int maxH, int i
     return hipGetLastError();
 }
 
-hipError_t launch_normals(const FrameDev* tab, int nf, int maxW, int maxH, hipStream_t s) {
-    hipLaunchKernelGGL(k_normals, dim3((maxW + 63) / 64, (maxH + 3) / 4, nf), dim3(kBlock), 0, s, tab);
+hipError_t launch_normals(const FrameDev* tab, int nf, int max_px, bool count, hipStream_t s) {
+    const int nch = (max_px + kValidChunk - 1) / kValidChunk;
+    hipLaunchKernelGGL(k_normals, dim3(nch > 0 ? nch : 1, 1, nf), dim3(kBlock), 0, s, tab, count ? 1 : 0);
     return hipGetLastError();
 }
 
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, int maxW, int maxH, hipStream_t s) {
+hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, int maxW, int maxH, bool counted, hipStream_t s) {
     const int nch = (max_px + kValidChunk - 1) / kValidChunk;
     const int gx = clampi(nch, 1, 1024);
-    hipLaunchKernelGGL(k_valid_count, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab);
+    if (!counted) hipLaunchKernelGGL(k_valid_count, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab);
     hipLaunchKernelGGL(k_valid_scatter, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab);
     // block-order chunks: a frame's padded scan covers at most 3.4 W H + 70
     // positions, and at most the padded maxW x maxH grid; one block per chunk
