@@ -65,6 +65,7 @@ struct pp_ctx {
     // a batch's frames run as up to kMaxChains independent kernel chains: chain 0 on
     // the launching stream, the others on these, forked and joined by events
     static constexpr int kMaxChains = 4;
+    bool chains = true;  // false: every batch runs as one chain (the serving runtime's contexts)
     hipStream_t chain_stream[kMaxChains] = {};
     hipEvent_t fork_ev = nullptr;
     hipEvent_t join_ev[kMaxChains] = {};
@@ -833,7 +834,7 @@ pp_status enqueue_chain(pp_ctx* c, const BatchPlan& b, int f0, int f1, hipStream
 
 pp_status enqueue_batch(pp_ctx* c, const BatchPlan& b, hipStream_t st, bool capturing) {
     const bool timed = c->timing && !capturing;
-    const int chains = std::min(pp_ctx::kMaxChains, b.nf / kChainFrames);
+    const int chains = c->chains ? std::min(pp_ctx::kMaxChains, b.nf / kChainFrames) : 1;
     if (!timed && chains > 1) {
         for (int k = 1; k < chains; ++k) {
             if (!c->chain_stream[k]) HIPCHK(c, hipStreamCreateWithFlags(&c->chain_stream[k], hipStreamNonBlocking));
@@ -1016,6 +1017,9 @@ size_t frame_scratch_bytes(int width, int height, int hyps) {
 
 pp_status batch_run_external(pp_ctx* c, int n, const pp_frame_job* jobs, void* const* scratch, hipStream_t s,
                              bool graph) {
+    // the serving runtime's batches run as one kernel chain: concurrent chains
+    // are not validated inside its captured graphs
+    if (c) c->chains = false;
     return batch_run(c, n, jobs, (void*)s, graph, scratch);
 }
 
