@@ -764,6 +764,10 @@ def main():
                    "tuning": {k: tuning[k] for k in ("diffuse_tile", "diffuse_t", "score_hb", "score_chunk")}
                    if tuning else "default",
                    "stage_ms_per_step": {k: round(v / args.steps, 3) for k, v in stage_ms.items()},
+                   # the graph step beyond the eager single-chain time of diffusion, normals and scoring: what
+                   # the per-round hypothesis, refit and removal kernels still add once the chains overlap them
+                   "ransac_other_not_overlapped_ms": round(ms_per_step - sum(
+                       v / args.steps for k, v in stage_ms.items() if k != "ransac_other"), 3) if stage_ms else None,
                    "planes_per_frame": round(planes_tot / len(outs), 2)},
         "plain": plain,
         "ragged_batch": ragged,
