@@ -4,7 +4,8 @@
 //   k_diffuse_wc     Perona-Malik diffusion, Eq. 1 / Alg. 1: T iterations fused
 //                    per pass, FP32 on delta = I - I0, the iterate in registers
 //                    (one wave per column strip); k_diffuse: the same on LDS tiles
-//   k_normals        back-projection (Alg. 2) + Sobel normal image (Eq. 2)
+//   k_normals        back-projection (Alg. 2) + Sobel normal image (Eq. 2);
+//                    in batches also the valid-list chunk counts
 //   k_valid_*        row-major list of depth-valid pixels (Alg. 2 point set)
 //   k_list0          the round-0 scoring list: every position of the image's
 //                    8x8-block scan (NaN for no point) with the bounding boxes
