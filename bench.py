@@ -550,6 +550,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the precision-form leg (256 frames of 1280x720, FP32 / BF16 / FP16 scoring)")
+    ap.add_argument("--no-precision-848", action="store_true", help="skip the precision leg's 848x480 batch")
     ap.add_argument("--precision-forms", type=str, default="",
                     help="comma list of the precision leg's forms to run (fp32_valu first), default all")
     ap.add_argument("--tuning", type=str, default="", help="tile,T,hb,chunk (1-based knobs) instead of autotuning")
@@ -723,7 +724,13 @@ def main():
     precision = None
     if not args.no_precision:
         log("precision-form leg: 256 frames of 1280x720")
-        precision = precision_bench(pp, tuning, forms=[x for x in args.precision_forms.split(",") if x])
+        forms = [x for x in args.precision_forms.split(",") if x]
+        precision = precision_bench(pp, tuning, forms=forms)
+        if not args.no_precision_848:
+            # the same scenes at the form's second size (the straight stair at f = 383)
+            log("precision-form leg: 256 frames of 848x480")
+            precision["848x480"] = precision_bench(
+                pp, tuning, size=(848, 480), forms=forms or ["fp32_valu", "bf16_mfma", "fp16_mfma"])
 
     chain = None
     if not args.no_chain:
