@@ -2165,6 +2165,14 @@ static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int 
 // Blocks of the final pass over all frames (8 per CU): more would repeat the
 // plane solve in more block waves.
 constexpr int kFinalBlocks = 2048;
+// Blocks of the moments and removal passes over all frames (32 per CU).
+constexpr int kPassBlocks = 8192;
+
+static int pass_blocks(int nch, int nf, int cap) {
+    const int per = std::max(cap / std::max(nf, 1), 1);
+    if (nch <= per) return clampi(nch, 1, 1024);
+    return clampi(per | 1, 1, 1023);
+}
 
 // One RANSAC round for every frame of the table: hypotheses, scoring,
 // selection and moments, the refit plane and its inliers per chunk, the
@@ -2178,12 +2186,14 @@ hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_
     const int max_pts = max_px;  // the longest list: the scan positions of the largest frame
     score_dispatch(tab, nf, r, max_pts, max_hyps, precision, tu, s);
     if (ev1) (void)hipEventRecord(ev1, s);
+    // one block per chunk up to a total over all frames, then blocks that take several chunks;
+    // the final count solves the plane in every block, so it gets fewer.  A capped grid is made
+    // odd: workgroups go to the 8 XCDs in turn, and with a multiple of 8 blocks a frame, chunk x
+    // of every frame would land on the same XCD (in late rounds, only the first few chunks work)
     const int nch = (max_pts + kRefitChunk - 1) / kRefitChunk;
-    const int gx = clampi(nch, 1, 1024);
+    const int gx = pass_blocks(nch, nf, kPassBlocks);
     hipLaunchKernelGGL(k_refit_moments, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
-    // a few blocks per CU in all: each solves the plane once, then counts several chunks
-    const int gf = clampi(std::min(nch, kFinalBlocks / std::max(nf, 1)), 1, 1024);
-    hipLaunchKernelGGL(k_refit_final, dim3(gf, 1, nf), dim3(kBlock), 0, s, tab, r);
+    hipLaunchKernelGGL(k_refit_final, dim3(pass_blocks(nch, nf, kFinalBlocks), 1, nf), dim3(kBlock), 0, s, tab, r);
     hipLaunchKernelGGL(k_apply, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
     return hipGetLastError();
 }
