@@ -670,13 +670,18 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
     typedef int v4i __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // valid pixels before chunk c, carried from this block's previous chunk
+    // a block takes a contiguous run of chunks: the valid pixels before its first chunk are
+    // summed once, then carried from chunk to chunk
+    const int per = (nch + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int c0 = (int)blockIdx.x * per, c1 = min(nch, c0 + per);
+    if (c0 >= nch) return;  // the whole block
     int before = 0;
-    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        {
-            int add = 0;
-            for (int i = c - (c == (int)blockIdx.x ? c : (int)gridDim.x) + threadIdx.x; i < c; i += kBlock) add += ccnt[i];
-            before += block_sum(add, sh);
-        }
+    {
+        int add = 0;
+        for (int i = threadIdx.x; i < c0; i += kBlock) add += ccnt[i];
+        before = block_sum(add, sh);
+    }
+    for (int c = c0; c < c1; ++c) {
         // pixels p0 .. p0 + 3 (row-major), 4 per thread
         const int p0 = c * kValidChunk + 4 * (int)threadIdx.x;
         const int y0 = p0 / f.W, x0 = p0 - y0 * f.W;
@@ -742,6 +747,7 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
             f.taken[before + i] = 0;
             if (f.dbg.valid_list) f.dbg.valid_list[before + i] = s_off[i];
         }
+        __syncthreads();  // the next chunk rewrites sh[4..7] and s_off
         if (p0 + 3 < npx) {
             *reinterpret_cast<v4i*>(lpos + p0) = v4i{kk[0], kk[1], kk[2], kk[3]};
         } else {
@@ -750,6 +756,7 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
                 if (p0 + j < npx) lpos[p0 + j] = kk[j];
         }
         const int run = before + tot;
+        before = run;
         if (c == nch - 1 && threadIdx.x == 0) {
             RoundState* st = f.st;
             st->M0 = run;
@@ -2100,11 +2107,24 @@ hipError_t launch_normals(const FrameDev* tab, int nf, int max_px, bool count, h
 
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Blocks per frame for a pass over nch chunks: one per chunk up to cap blocks over all nf
+// frames, then fewer blocks that take several chunks each.  A capped count is made odd:
+// workgroups go to the 8 XCDs in turn, and with a multiple of 8 blocks a frame, block x of
+// every frame would land on the same XCD.
+static int pass_blocks(int nch, int nf, int cap) {
+    const int per = std::max(cap / std::max(nf, 1), 1);
+    if (nch <= per) return clampi(nch, 1, 1024);
+    return clampi(per | 1, 1, 1023);
+}
+
+// Blocks of the moments, removal and valid-list passes over all frames (32 per CU).
+constexpr int kPassBlocks = 8192;
+
 hipError_t launch_valid_list(const FrameDev* tab, int nf, int max_px, int maxW, int maxH, bool counted, hipStream_t s) {
     const int nch = (max_px + kValidChunk - 1) / kValidChunk;
     const int gx = clampi(nch, 1, 1024);
     if (!counted) hipLaunchKernelGGL(k_valid_count, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab);
-    hipLaunchKernelGGL(k_valid_scatter, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab);
+    hipLaunchKernelGGL(k_valid_scatter, dim3(pass_blocks(nch, nf, kPassBlocks), 1, nf), dim3(kBlock), 0, s, tab);
     // block-order chunks: a frame's padded scan covers at most 3.4 W H + 70
     // positions, and at most the padded maxW x maxH grid; one block per chunk
     const int64_t pad = kScanBlock;
@@ -2165,14 +2185,7 @@ static void score_dispatch(const FrameDev* tab, int nf, int r, int max_pts, int 
 // Blocks of the final pass over all frames (8 per CU): more would repeat the
 // plane solve in more block waves.
 constexpr int kFinalBlocks = 2048;
-// Blocks of the moments and removal passes over all frames (32 per CU).
-constexpr int kPassBlocks = 8192;
 
-static int pass_blocks(int nch, int nf, int cap) {
-    const int per = std::max(cap / std::max(nf, 1), 1);
-    if (nch <= per) return clampi(nch, 1, 1024);
-    return clampi(per | 1, 1, 1023);
-}
 
 // One RANSAC round for every frame of the table: hypotheses, scoring,
 // selection and moments, the refit plane and its inliers per chunk, the
@@ -2186,10 +2199,9 @@ hipError_t launch_round(const FrameDev* tab, int nf, int r, int max_px, int max_
     const int max_pts = max_px;  // the longest list: the scan positions of the largest frame
     score_dispatch(tab, nf, r, max_pts, max_hyps, precision, tu, s);
     if (ev1) (void)hipEventRecord(ev1, s);
-    // one block per chunk up to a total over all frames, then blocks that take several chunks;
-    // the final count solves the plane in every block, so it gets fewer.  A capped grid is made
-    // odd: workgroups go to the 8 XCDs in turn, and with a multiple of 8 blocks a frame, chunk x
-    // of every frame would land on the same XCD (in late rounds, only the first few chunks work)
+    // the final count solves the plane in every block, so it gets fewer blocks (in late rounds
+    // only the first few chunks of a frame hold points, which the odd capped grids spread over
+    // the XCDs)
     const int nch = (max_pts + kRefitChunk - 1) / kRefitChunk;
     const int gx = pass_blocks(nch, nf, kPassBlocks);
     hipLaunchKernelGGL(k_refit_moments, dim3(gx, 1, nf), dim3(kBlock), 0, s, tab, r);
