@@ -1902,14 +1902,17 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
     if (!rr.active || rr.stop) return;
     const int M = rr.Mlen;
     const int nch = (M + kRefitChunk - 1) / kRefitChunk;
-    if ((int)blockIdx.x >= nch) return;
+    // a block takes a contiguous run of chunks, whose runs of survivors follow each other
+    const int per = (nch + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int c0 = (int)blockIdx.x * per, c1 = min(nch, c0 + per);
+    if (c0 >= nch) return;
     // |F| and the runs of the chunks before this block's first one, in one pass
     const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt;
     const gi32_cptr crun = (gi32_cptr)f.chunk_run;
     int ftot = 0, pre = 0;
     for (int c = threadIdx.x; c < nch; c += kBlock) {
         ftot += ccnt[c];
-        pre += c < (int)blockIdx.x ? crun[c] : 0;
+        pre += c < c0 ? crun[c] : 0;
     }
     block_sum2(ftot, pre, sh);
     const bool emit = ftot >= f.min_inliers;
@@ -1945,12 +1948,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
     float4* __restrict__ out = f.list[(r + 1) & 1];
     const gi32_cptr Lg = (gi32_cptr)f.L;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        if (c != (int)blockIdx.x) {  // later chunks of this block: add the runs since its previous one
-            int add = 0;
-            for (int i = c - (int)gridDim.x + threadIdx.x; i < c; i += kBlock) add += crun[i];
-            pre += block_sum(add, sh);
-        }
+    for (int c = c0; c < c1; ++c) {
         const int start = pre;
         const int e = min(M, (c + 1) * kRefitChunk);
         // every point of this thread in flight at once: point c*chunk + s*256 + tid of step s
@@ -1997,6 +1995,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
         for (int i = base + (int)threadIdx.x; i < end; i += kBlock) out[i] = pad_point();
         __syncthreads();  // the run is in memory for the whole block
         tile_boxes(out + start, (end - start) >> 6, f.tbox + 2 * (start >> 6), wave, kBlock / 64);
+        pre = end;  // the next chunk's run follows this one's
         __syncthreads();  // s_cnt is reused by the next chunk
     }
 }
