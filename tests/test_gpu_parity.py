@@ -392,6 +392,38 @@ def test_batch_graph_eager_and_plain_are_bitwise_equal(pp):
     log(f"  batch of {len(spec)} ragged frames: plain == eager == graph (x2)")
 
 
+def test_large_batch_with_capped_grids_equals_the_plain_path(pp):
+    """96 frames of 1280x720 in one batch (4 kernel chains of 24 frames): the
+    per-chunk passes (valid-list scatter, moments, final count, removal) run
+    capped, odd grids whose blocks take several chunks each, which no smaller
+    batch reaches; every output of every frame, after a graph and an eager
+    run, is bitwise the plain path's."""
+    import torch
+    base = [scenes.make_frame(4, k) for k in range(8)]
+    frames = []
+    for i in range(96):
+        f = base[i % 8]
+        H, W = f.depth.shape
+        dc, rc = cfg_params(4, W, H, i, hyps=1024)
+        frames.append(pp.make_outputs(to_dev(f.depth), (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc))
+    for fo in frames:
+        pp.run_frame(fo)
+    torch.cuda.synchronize()
+    keys = ("depth_mm", "points", "normals", "valid", "planes", "n_planes", "labels")
+    plain = [[getattr(fo, k).clone() for k in keys] for fo in frames]
+    for graph in (True, False):
+        for fo in frames:
+            for t in (fo.depth_mm, fo.points, fo.normals, fo.planes, fo.labels):
+                t.zero_()
+        pp.batch_run(frames, graph=graph)
+        torch.cuda.synchronize()
+        for i, (fo, ref) in enumerate(zip(frames, plain)):
+            for k, a in zip(keys, ref):
+                assert torch.equal(getattr(fo, k), a), (graph, i, k)
+    log(f"  96 x 1280x720 batch: graph and eager runs bitwise the plain path "
+        f"({sum(int(fo.n_planes.item()) for fo in frames)} planes)")
+
+
 def test_batch_of_nine_frames_equals_the_plain_path(pp):
     """More frames than XCDs and not a multiple of 8: the XCD-ordered grid of
     the hypothesis kernel still covers every (frame, block) once."""
