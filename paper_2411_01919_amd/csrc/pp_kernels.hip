@@ -660,14 +660,14 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
     const FrameDev& f = tab[blockIdx.z];
     const int npx = f.W * f.H;
     const int nch = (npx + kValidChunk - 1) / kValidChunk;
-    // valid-list position of every pixel, [H][W] (-1 without depth); the
-    // diffusion ping-pong buffer is free by now
-    int32_t* __restrict__ lpos = reinterpret_cast<int32_t*>(f.delta[0]);
+    // for every 4 row-major pixels p .. p + 3 (p a multiple of 4), the number of
+    // depth-valid pixels before p: a pixel's valid-list position is that plus the
+    // valid ones before it among the 4 (the diffusion ping-pong buffer is free by now)
+    int32_t* __restrict__ qpre = reinterpret_cast<int32_t*>(f.delta[0]);
     const gu8_cptr vg = (gu8_cptr)f.valid;
     const gi32_cptr ccnt = (gi32_cptr)f.chunk_cnt;
     // flags and labels of 4 pixels of one row as one 32-bit word where rows allow it
     const bool words = (((uintptr_t)f.valid | (uintptr_t)f.labels | (uintptr_t)f.pitch) & 3) == 0;
-    typedef int v4i __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // valid pixels before chunk c, carried from this block's previous chunk
     // a block takes a contiguous run of chunks: the valid pixels before its first chunk are
@@ -731,6 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
             base += w < wave ? sh[4 + w] : 0;
             tot += sh[4 + w];
         }
+        if (p0 < npx) qpre[p0 >> 2] = base;
         int kk[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -748,13 +749,6 @@ __global__ __launch_bounds__(kBlock) void k_valid_scatter(const FrameDev* __rest
             if (f.dbg.valid_list) f.dbg.valid_list[before + i] = s_off[i];
         }
         __syncthreads();  // the next chunk rewrites sh[4..7] and s_off
-        if (p0 + 3 < npx) {
-            *reinterpret_cast<v4i*>(lpos + p0) = v4i{kk[0], kk[1], kk[2], kk[3]};
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (p0 + j < npx) lpos[p0 + j] = kk[j];
-        }
         const int run = before + tot;
         before = run;
         if (c == nch - 1 && threadIdx.x == 0) {
@@ -899,15 +893,14 @@ __global__ __launch_bounds__(kBlock) void k_list0(const FrameDev* __restrict__ t
     const size_t plane = (size_t)f.H * f.pitch;
     const gu8_cptr vg = (gu8_cptr)f.valid;
     const gf32_cptr pg = (gf32_cptr)f.pts;
-    const gi32_cptr lpos = (gi32_cptr)f.delta[0];
+    const gi32_cptr qpre = (gi32_cptr)f.delta[0];  // valid pixels before each row-major group of 4
     float4* __restrict__ out = f.list[0];
     // a thread takes 4 consecutive scan positions, 4 pixels of one row of one 8x8 block
     // (x0 a multiple of 4): one 16-byte load per plane where the rows allow it
     typedef float v4f __attribute__((ext_vector_type(4)));
-    typedef int v4i __attribute__((ext_vector_type(4)));
     const bool vec_pts = (((uintptr_t)f.pts | (uintptr_t)(f.pitch * 4) | (uintptr_t)(plane * 4)) & 15) == 0;
     const bool vec_flags = (((uintptr_t)f.valid | (uintptr_t)f.pitch) & 3) == 0;
-    const bool vec_lpos = (f.W & 3) == 0;
+    const bool quad_rows = (f.W & 3) == 0;  // a thread's 4 pixels are then one row-major group of 4
     float p1 = 0.f;
     for (int c = blockIdx.x; c < nchq; c += gridDim.x) {
         const int q0 = c * kValidChunk + 4 * (int)threadIdx.x;
@@ -948,14 +941,26 @@ __global__ __launch_bounds__(kBlock) void k_list0(const FrameDev* __restrict__ t
                 if (x0 + j < f.W) vb[j] = vg[o + j] & 1;
         }
         const int lo = y * f.W + x0;
-        if (full && vec_lpos) {
-            const v4i l4 = *(const __attribute__((address_space(1))) v4i*)(lpos + lo);
+        if (full && quad_rows) {
+            int run = qpre[lo >> 2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) lp[j] = l4[j];
+            for (int j = 0; j < 4; ++j) {
+                lp[j] = run;
+                run += vb[j];
+            }
         } else if (row_in) {
+            // the group of 4 may start in the previous row: its earlier pixels one by one
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (x0 + j < f.W && vb[j]) lp[j] = lpos[lo + j];
+                if (x0 + j < f.W && vb[j]) {
+                    const int p = lo + j;
+                    int n = qpre[p >> 2];
+                    for (int i = p & ~3; i < p; ++i) {
+                        const int yi = i / f.W, xi = i - yi * f.W;
+                        n += vg[(size_t)yi * f.pitch + xi] & 1;
+                    }
+                    lp[j] = n;
+                }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
