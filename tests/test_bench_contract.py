@@ -52,3 +52,22 @@ def test_stored_traffic_only_for_its_own_kernel_source(tmp_path, monkeypatch):
     (tmp_path / "profiles").mkdir()
     shutil.copy(os.path.join(ROOT, "profiles", "score_traffic.json"), tmp_path / "profiles")
     assert bench.load_traffic(h) == stored["bytes_per_launch"]
+
+
+def test_hbm_fractions_by_algorithmic_and_counted_bytes():
+    """The per-stage HBM rates of the bench line: bytes per pixel times pixels
+    over the stage time, against 8 TB/s, with the 60 % flags per stage."""
+    n_px = 1_000_000
+    stage = {"diffusion": 0.02, "normals": 0.01}  # ms
+    counted = {"diffusion_bytes_per_px": 80.0, "normals_and_valid_list_bytes_per_px": 50.0}
+    out = bench.hbm_fractions(stage, n_px, 20, 4, 0.9, counted)
+    d, n = out["diffusion"], out["normals_and_valid_list"]
+    # 80 B x 1e6 px in 20 us = 4 TB/s (50 %); 50 B x 1e6 px in 10 us = 5 TB/s (62.5 %)
+    assert d["counter_gb_per_s"] == 4000.0 and d["counter_frac_of_8tbs"] == 0.5
+    assert n["counter_gb_per_s"] == 5000.0 and n["counter_frac_of_8tbs"] == 0.625
+    assert out["counter_target_met_by_stage"] == {"diffusion": False, "normals_and_valid_list": True}
+    assert out["counter_target_met"] is False
+    assert abs(d["gb_per_s"] - d["bytes_per_px"] * n_px / 0.02e-3 / 1e9) < 0.1
+    plain = bench.hbm_fractions(stage, n_px, 20, 4, 0.9)
+    assert plain["counter_target_met"] is None and plain["counter_target_met_by_stage"] is None
+    assert "counter_frac_of_8tbs" not in plain["diffusion"]
