@@ -392,6 +392,32 @@ def test_batch_graph_eager_and_plain_are_bitwise_equal(pp):
     log(f"  batch of {len(spec)} ragged frames: plain == eager == graph (x2)")
 
 
+def test_batch_of_odd_widths_equals_the_plain_path(pp):
+    """Widths that are not multiples of 4 (groups of 4 row-major pixels wrap
+    into the next row in the normals, valid-list and round-0 list passes), in
+    a ragged graph batch and one by one: every output bitwise equal."""
+    import torch
+    sizes = [(301, 97), (57, 33), (130, 65), (421, 240), (98, 77)]
+    frames = []
+    for i, (W, H) in enumerate(sizes):
+        f = scenes.make_frame(3, i, size=(W, H))
+        dc, rc = cfg_params(3, W, H, i)
+        frames.append(pp.make_outputs(to_dev(f.depth), (f.K.fx, f.K.fy, f.K.cx, f.K.cy), dc, rc))
+    for fo in frames:
+        pp.run_frame(fo)
+    torch.cuda.synchronize()
+    plain = [_snapshot(fo) for fo in frames]
+    for fo in frames:
+        for t in (fo.depth_mm, fo.points, fo.normals, fo.planes, fo.labels):
+            t.zero_()
+    pp.batch_run(frames, graph=True)
+    torch.cuda.synchronize()
+    for i, (fo, ref) in enumerate(zip(frames, plain)):
+        for a, b in zip(_snapshot(fo), ref):
+            assert np.array_equal(a, b), (i, sizes[i])
+    log(f"  odd widths {sizes}: graph batch == plain, {[int(r[5][0]) for r in plain]} planes")
+
+
 def test_large_batch_with_capped_grids_equals_the_plain_path(pp):
     """96 frames of 1280x720 in one batch (4 kernel chains of 24 frames): the
     per-chunk passes (valid-list scatter, moments, final count, removal) run
