@@ -1896,11 +1896,13 @@ __global__ __launch_bounds__(kBlock) void k_refit_final(const FrameDev* __restri
 // update).  If |F| >= min_inliers: label F with r, mark it assigned, write
 // the plane record, and write each chunk's survivors, in order, as one run
 // padded to a multiple of 64 into the next round's list (at the sum of the
-// earlier chunks' runs), then the bounding boxes of the run's tiles (read
-// back from the cache); otherwise the frame stops without emitting.
+// earlier chunks' runs), assembled in LDS and stored coalesced, then the
+// bounding boxes of the run's tiles from the LDS copy; otherwise the frame
+// stops without emitting.
 __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ tab, int r) {
     __shared__ int sh[8];
     __shared__ int s_cnt[kChunkSteps][kBlock / 64];
+    __shared__ float4 s_run[kRefitChunk];  // the chunk's run of survivors and padding
     const FrameDev& f = tab[blockIdx.z];
     RoundState* st = f.st;
     const RoundRec rr = round_rec(f, r);
@@ -1994,14 +1996,16 @@ __global__ __launch_bounds__(kBlock) void k_apply(const FrameDev* __restrict__ t
                 mine += w < wave ? n : 0;
                 base += n;
             }
-            if ((keepm[s] >> lane) & 1ull) out[mine + __popcll(keepm[s] & lanemask_lt())] = p[s];
+            if ((keepm[s] >> lane) & 1ull) s_run[mine - start + __popcll(keepm[s] & lanemask_lt())] = p[s];
         }
         const int end = align64(base);
-        for (int i = base + (int)threadIdx.x; i < end; i += kBlock) out[i] = pad_point();
-        __syncthreads();  // the run is in memory for the whole block
-        tile_boxes(out + start, (end - start) >> 6, f.tbox + 2 * (start >> 6), wave, kBlock / 64);
+        for (int i = base + (int)threadIdx.x; i < end; i += kBlock) s_run[i - start] = pad_point();
+        __syncthreads();  // the run is in LDS for the whole block
+        // stored in order, one 16-byte store per thread and step; the tile boxes from the LDS copy
+        for (int i = threadIdx.x; i < end - start; i += kBlock) out[start + i] = s_run[i];
+        tile_boxes(s_run, (end - start) >> 6, f.tbox + 2 * (start >> 6), wave, kBlock / 64);
         pre = end;  // the next chunk's run follows this one's
-        __syncthreads();  // s_cnt is reused by the next chunk
+        __syncthreads();  // s_cnt and s_run are reused by the next chunk
     }
 }
 
